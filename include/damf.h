@@ -1,0 +1,161 @@
+/*
+ * damf.h -- C ABI of libdamf, an MI355X (gfx950) implementation of DAMF,
+ * Dynamic Adjacency Matrix Factorization (Deng, Yang, Li, Cai, Pu, Jiang,
+ * "Accelerating Dynamic Network Embedding with Billions of Parameter Updates
+ * to Milliseconds", KDD 2023, arXiv 2306.08967).
+ *
+ * The library keeps a rank-d factorisation A ~ U Sigma V^T of a graph's 0/1
+ * adjacency matrix, its embeddings X = U Sigma^(1/2), Y = V Sigma^(1/2)
+ * (Sec. 4.1) and the PPR-enhanced context embedding Z = PPR(X) (Sec. 4.4),
+ * all resident in GPU memory, and updates them under batches of edge
+ * insertions and deletions by space projection (Sec. 4.3, Theorem 2;
+ * Algorithm 1 and Algorithm 2, edge branch) followed by dynamic PPR push.
+ *
+ * Conventions for every entry point:
+ *   - Every call returns a damf_status; no C++ exception crosses the ABI.
+ *     damf_last_error(ctx) describes the last failure of that context.
+ *   - Pointer arguments are host pointers unless the call's `flags` include
+ *     DAMF_DEVICE_PTRS, in which case they are device pointers (for example
+ *     torch tensors' data_ptr()) readable/writable on the context's device.
+ *     Input arrays are only read during the call; the caller owns them.
+ *     Output arrays are caller-allocated with the sizes stated below.
+ *   - Ids are 0-based int32 node ids in [0, n).
+ *   - Calls on one context are serialised by the caller (one thread at a
+ *     time); separate contexts are independent.
+ *   - After a device error the context is poisoned: later calls return
+ *     DAMF_E_STATE.  An input error (DAMF_E_INVALID_ARG,
+ *     DAMF_E_OUT_OF_RANGE) is detected before any state changes, so the
+ *     context is unchanged.
+ */
+#ifndef DAMF_H
+#define DAMF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct damf_ctx damf_ctx; /* opaque; owns all device state */
+
+typedef enum {
+  DAMF_OK = 0,
+  DAMF_E_INVALID_ARG = 1,  /* bad size, null pointer, bad config value      */
+  DAMF_E_OUT_OF_RANGE = 2, /* node id outside [0, n) or op not +1/-1         */
+  DAMF_E_OOM = 3,          /* device allocation failed                       */
+  DAMF_E_DEVICE = 4,       /* a HIP call failed                              */
+  DAMF_E_NUMERIC = 5,      /* non-finite value or failed factorisation       */
+  DAMF_E_STATE = 6         /* context poisoned by an earlier device error    */
+} damf_status;
+
+typedef enum { DAMF_X = 0, DAMF_Y = 1, DAMF_Z = 2 } damf_which;
+
+enum { DAMF_DEVICE_PTRS = 1 };
+
+/* Configuration.  Fill with damf_config_default() and override fields. */
+typedef struct {
+  int64_t n;             /* number of nodes                                   */
+  int32_t d;             /* t-SVD rank = embedding width (Sec. 4.1); 1..128   */
+  int32_t directed;      /* 0: an op on (u,v) edits A[u,v] and A[v,u]         */
+  int32_t oversample;    /* randomized t-SVD oversampling p (default 10)      */
+  int32_t power_iters;   /* randomized t-SVD power iterations q (default 2)   */
+  uint64_t seed;         /* seed of the Rademacher sketch                     */
+  double alpha;          /* PPR damping factor (Sec. 4.4); 1.0 disables Step 4 */
+  double eps;            /* PPR error tolerance: max |R| <= eps after Step 4  */
+  int32_t max_core_rank; /* r: chunk rank bound, min(|S1|,|S2|) <= r          */
+  int32_t max_side;      /* r_max: max(|S1|,|S2|) <= r_max; d + r_max <= 192  */
+  double tau;            /* residual Gram eigenvalue drop threshold           */
+  int32_t auto_enhance;  /* 1: damf_update runs Step 4 before returning       */
+  int32_t reserved0;
+  double graph_slack;    /* CSR pool capacity = slack * m_init + 2^20 entries */
+  void *hip_stream;      /* hipStream_t to run on; NULL = a context stream    */
+} damf_config;
+
+/* Per-batch statistics written by damf_update when `info` is non-NULL. */
+typedef struct {
+  int64_t ops;            /* ops submitted                                     */
+  int64_t net_entries;    /* nonzero entries of the net change of A            */
+  int64_t chunks;         /* chunks the net change was cut into                */
+  int32_t max_core;       /* largest core dimension (d + rank) used            */
+  int32_t dropped;        /* residual directions dropped by tau                */
+  int64_t push_rounds;    /* Step 4 rounds                                     */
+  int64_t pushes;         /* Step 4 node pushes                                */
+  int64_t push_edges;     /* Step 4 edge traversals                            */
+  double ms_prepare;      /* batch sort / net change / chunking                */
+  double ms_chain;        /* Steps 1-3 over all chunks                         */
+  double ms_enhance;      /* Step 4                                            */
+} damf_batch_info;
+
+/* Defaults: d=128, directed, p=10, q=2, alpha=0.15, eps=1e-5, r=64,
+ * r_max=64, tau=1e-6, auto_enhance=1, slack=1.25. */
+void damf_config_default(damf_config *cfg);
+
+/* Create a context from an initial edge list (Appendix A, Algorithm 3):
+ * builds the graph, takes the randomized rank-d t-SVD of A (sketch
+ * Omega[i,j] = +/-1 from SplitMix64, Q = qr(A Omega), q rounds of
+ * Q = qr(A^T Q), Q = qr(A Q), then B^T = A^T Q = Q2 R2 and svd(R2^T)), sets
+ * the projections to the identity and propagates PPR until max |R| <= eps.
+ * src/dst: m edges (duplicates collapse; self-loops are entries).
+ * Errors: DAMF_E_INVALID_ARG (n < 1, d out of range, m < 0, null arrays with
+ * m > 0), DAMF_E_OUT_OF_RANGE (id outside [0,n)), DAMF_E_OOM. */
+damf_status damf_init(const damf_config *cfg, int64_t m, const int32_t *src,
+                      const int32_t *dst, int32_t flags, damf_ctx **out);
+
+/* As damf_init, but takes the rank-d factorisation from the caller instead
+ * of computing it: U, V are n x d row-major float64, S has d values sorted
+ * descending (host pointers; flags only govern src/dst). */
+damf_status damf_init_factors(const damf_config *cfg, int64_t m,
+                              const int32_t *src, const int32_t *dst,
+                              const double *U, const double *S,
+                              const double *V, int32_t flags, damf_ctx **out);
+
+/* Apply one batch of k edits (Algorithm 2, edge branch, for all events of
+ * the batch).  op[i] = +1 inserts (src[i], dst[i]), -1 deletes it; ops apply
+ * in order with set semantics (inserting a present edge or deleting an
+ * absent one changes nothing).  The net change of A is cut into chunks of
+ * rank <= r; each chunk is one Steps 1-3 update (Theorem 2 with B, C of k
+ * columns).  Then Step 4 runs if auto_enhance.  0 <= k <= 8192; k == 0 is a
+ * no-op.  Errors: DAMF_E_INVALID_ARG, DAMF_E_OUT_OF_RANGE (state unchanged),
+ * DAMF_E_NUMERIC, DAMF_E_DEVICE. */
+damf_status damf_update(damf_ctx *ctx, int64_t k, const int32_t *src,
+                        const int32_t *dst, const int8_t *op, int32_t flags,
+                        damf_batch_info *info);
+
+/* Step 4 (Sec. 4.4): push PPR residuals until max |R| <= eps. */
+damf_status damf_enhance(damf_ctx *ctx);
+
+/* Rows of X, Y or Z for q nodes (nodes == NULL: all n rows, q must be n):
+ * out is q x d row-major float32.  Row of X = U_b[u] P_U Sigma^(1/2)
+ * (Sec. 4.6, O(d^2) per query). */
+damf_status damf_query(damf_ctx *ctx, damf_which which, int64_t q,
+                       const int32_t *nodes, float *out, int32_t flags);
+
+/* The d singular values, descending (host float64 array of d). */
+damf_status damf_singular_values(damf_ctx *ctx, double *out);
+
+/* Canonical CSR of A (transpose = 0) or A^T (transpose = 1): indptr has n+1
+ * int64 entries, indices m int32 entries ascending within each row.  Call
+ * with indices == NULL to get m in *m_out only.  Host pointers. */
+damf_status damf_export_csr(damf_ctx *ctx, int32_t transpose, int64_t *indptr,
+                            int32_t *indices, int64_t *m_out);
+
+/* Internal state for tests, as host float64: Ub, Vb, Zb, R are n x d
+ * row-major (any may be NULL), PU, PV are d x d row-major. */
+damf_status damf_export_state(damf_ctx *ctx, double *Ub, double *Vb,
+                              double *PU, double *PV, double *Zb, double *R);
+
+/* Current max |R| entry (float64); <= eps after Step 4. */
+damf_status damf_residual_max(damf_ctx *ctx, double *out);
+
+/* Wait for all work of the context. */
+damf_status damf_sync(damf_ctx *ctx);
+
+void damf_destroy(damf_ctx *ctx);
+
+const char *damf_last_error(const damf_ctx *ctx);
+const char *damf_status_string(damf_status s);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DAMF_H */

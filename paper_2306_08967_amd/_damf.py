@@ -1,0 +1,262 @@
+"""ctypes binding of libdamf (include/damf.h).
+
+Argument marshalling only: every step of the method runs in the library's HIP
+kernels.  Arrays may be numpy arrays (host) or torch CUDA tensors (device,
+passed by data_ptr with DAMF_DEVICE_PTRS).  The binding fails loudly when the
+library is missing; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_PKG, "libdamf.so")
+
+DAMF_OK = 0
+DAMF_E_INVALID_ARG = 1
+DAMF_E_OUT_OF_RANGE = 2
+DAMF_E_OOM = 3
+DAMF_E_DEVICE = 4
+DAMF_E_NUMERIC = 5
+DAMF_E_STATE = 6
+DAMF_DEVICE_PTRS = 1
+WHICH = {"X": 0, "Y": 1, "Z": 2}
+
+
+class DamfConfig(C.Structure):
+    _fields_ = [
+        ("n", C.c_int64),
+        ("d", C.c_int32),
+        ("directed", C.c_int32),
+        ("oversample", C.c_int32),
+        ("power_iters", C.c_int32),
+        ("seed", C.c_uint64),
+        ("alpha", C.c_double),
+        ("eps", C.c_double),
+        ("max_core_rank", C.c_int32),
+        ("max_side", C.c_int32),
+        ("tau", C.c_double),
+        ("auto_enhance", C.c_int32),
+        ("reserved0", C.c_int32),
+        ("graph_slack", C.c_double),
+        ("hip_stream", C.c_void_p),
+    ]
+
+
+class DamfBatchInfo(C.Structure):
+    _fields_ = [
+        ("ops", C.c_int64),
+        ("net_entries", C.c_int64),
+        ("chunks", C.c_int64),
+        ("max_core", C.c_int32),
+        ("dropped", C.c_int32),
+        ("push_rounds", C.c_int64),
+        ("pushes", C.c_int64),
+        ("push_edges", C.c_int64),
+        ("ms_prepare", C.c_double),
+        ("ms_chain", C.c_double),
+        ("ms_enhance", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DamfError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"damf status {status}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    """Load libdamf.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build it with `python -m paper_2306_08967_amd.build_lib`")
+    L = C.CDLL(LIB_PATH)
+    p = C.c_void_p
+    i32p = C.POINTER(C.c_int32)
+    L.damf_config_default.argtypes = [C.POINTER(DamfConfig)]
+    L.damf_config_default.restype = None
+    L.damf_init.argtypes = [C.POINTER(DamfConfig), C.c_int64, p, p, C.c_int32, C.POINTER(p)]
+    L.damf_init_factors.argtypes = [C.POINTER(DamfConfig), C.c_int64, p, p, p, p, p, C.c_int32,
+                                    C.POINTER(p)]
+    L.damf_update.argtypes = [p, C.c_int64, p, p, p, C.c_int32, C.POINTER(DamfBatchInfo)]
+    L.damf_enhance.argtypes = [p]
+    L.damf_query.argtypes = [p, C.c_int, C.c_int64, p, p, C.c_int32]
+    L.damf_singular_values.argtypes = [p, p]
+    L.damf_export_csr.argtypes = [p, C.c_int32, p, p, C.POINTER(C.c_int64)]
+    L.damf_export_state.argtypes = [p, p, p, p, p, p, p]
+    L.damf_residual_max.argtypes = [p, C.POINTER(C.c_double)]
+    L.damf_sync.argtypes = [p]
+    L.damf_destroy.argtypes = [p]
+    L.damf_destroy.restype = None
+    L.damf_last_error.argtypes = [p]
+    L.damf_last_error.restype = C.c_char_p
+    L.damf_status_string.argtypes = [C.c_int]
+    L.damf_status_string.restype = C.c_char_p
+    for name in ("damf_init", "damf_init_factors", "damf_update", "damf_enhance", "damf_query",
+                 "damf_singular_values", "damf_export_csr", "damf_export_state",
+                 "damf_residual_max", "damf_sync"):
+        getattr(L, name).restype = C.c_int
+    del i32p
+    _lib = L
+    return L
+
+
+def _is_torch(x):
+    return type(x).__module__.startswith("torch")
+
+
+def _ptr(x, dtype):
+    """(pointer, is_device, keepalive) for a numpy array or torch tensor."""
+    if x is None:
+        return None, False, None
+    if _is_torch(x):
+        if not x.is_contiguous():
+            raise ValueError("tensor must be contiguous")
+        return C.c_void_p(x.data_ptr()), x.is_cuda, x
+    a = np.ascontiguousarray(x, dtype=dtype)
+    return a.ctypes.data_as(C.c_void_p), False, a
+
+
+def default_config(n, d=128, directed=True, **kw):
+    cfg = DamfConfig()
+    lib().damf_config_default(C.byref(cfg))
+    cfg.n = int(n)
+    cfg.d = int(d)
+    cfg.directed = 1 if directed else 0
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Context:
+    """A DAMF state on the GPU (owns a damf_ctx)."""
+
+    def __init__(self, handle, cfg):
+        self._h = handle
+        self.cfg = cfg
+        self.n = cfg.n
+        self.d = cfg.d
+
+    def _check(self, st):
+        if st != DAMF_OK:
+            msg = lib().damf_last_error(self._h).decode() if self._h else ""
+            raise DamfError(st, msg or lib().damf_status_string(st).decode())
+
+    @staticmethod
+    def _create(fn, cfg, *args):
+        h = C.c_void_p()
+        st = fn(C.byref(cfg), *args, C.byref(h))
+        if st != DAMF_OK:
+            raise DamfError(st, lib().damf_status_string(st).decode())
+        return Context(h, cfg)
+
+    @classmethod
+    def init(cls, cfg, src, dst):
+        ps, dev, ka1 = _ptr(src, np.int32)
+        pd, _, ka2 = _ptr(dst, np.int32)
+        m = len(src)
+        return cls._create(lib().damf_init, cfg, C.c_int64(m), ps, pd,
+                           C.c_int32(DAMF_DEVICE_PTRS if dev else 0))
+
+    @classmethod
+    def init_factors(cls, cfg, src, dst, U, S, V):
+        ps, dev, ka1 = _ptr(src, np.int32)
+        pd, _, ka2 = _ptr(dst, np.int32)
+        U = np.ascontiguousarray(U, dtype=np.float64)
+        S = np.ascontiguousarray(S, dtype=np.float64)
+        V = np.ascontiguousarray(V, dtype=np.float64)
+        return cls._create(lib().damf_init_factors, cfg, C.c_int64(len(src)), ps, pd,
+                           U.ctypes.data_as(C.c_void_p), S.ctypes.data_as(C.c_void_p),
+                           V.ctypes.data_as(C.c_void_p),
+                           C.c_int32(DAMF_DEVICE_PTRS if dev else 0))
+
+    def update(self, src, dst, op):
+        ps, dev, ka1 = _ptr(src, np.int32)
+        pd, _, ka2 = _ptr(dst, np.int32)
+        po, _, ka3 = _ptr(op, np.int8)
+        info = DamfBatchInfo()
+        self._check(lib().damf_update(self._h, C.c_int64(len(src)), ps, pd, po,
+                                      C.c_int32(DAMF_DEVICE_PTRS if dev else 0), C.byref(info)))
+        return info.as_dict()
+
+    def enhance(self):
+        self._check(lib().damf_enhance(self._h))
+
+    def query(self, which, nodes=None, out=None):
+        if nodes is None:
+            q = self.n
+            pn = None
+            dev = False
+        else:
+            pn, dev, ka = _ptr(nodes, np.int32)
+            q = len(nodes)
+        if out is None:
+            out = np.empty((q, self.d), dtype=np.float32)
+        po, odev, kb = _ptr(out, np.float32)
+        if dev != odev and nodes is not None:
+            raise ValueError("nodes and out must both be host or both be device")
+        self._check(lib().damf_query(self._h, WHICH[which], C.c_int64(q), pn, po,
+                                     C.c_int32(DAMF_DEVICE_PTRS if odev else 0)))
+        return out
+
+    def singular_values(self):
+        s = np.empty(self.d, dtype=np.float64)
+        self._check(lib().damf_singular_values(self._h, s.ctypes.data_as(C.c_void_p)))
+        return s
+
+    def export_csr(self, transpose=False):
+        m = C.c_int64()
+        self._check(lib().damf_export_csr(self._h, int(transpose), None, None, C.byref(m)))
+        indptr = np.empty(self.n + 1, dtype=np.int64)
+        indices = np.empty(max(m.value, 1), dtype=np.int32)
+        self._check(lib().damf_export_csr(self._h, int(transpose),
+                                          indptr.ctypes.data_as(C.c_void_p),
+                                          indices.ctypes.data_as(C.c_void_p), C.byref(m)))
+        return indptr, indices[:m.value]
+
+    def export_state(self):
+        n, d = self.n, self.d
+        Ub = np.empty((n, d)); Vb = np.empty((n, d)); Zb = np.empty((n, d)); R = np.empty((n, d))
+        PU = np.empty((d, d)); PV = np.empty((d, d))
+        args = [a.ctypes.data_as(C.c_void_p) for a in (Ub, Vb, PU, PV, Zb, R)]
+        self._check(lib().damf_export_state(self._h, *args))
+        return dict(Ub=Ub, Vb=Vb, PU=PU, PV=PV, Zb=Zb, R=R)
+
+    def residual_max(self):
+        v = C.c_double()
+        self._check(lib().damf_residual_max(self._h, C.byref(v)))
+        return v.value
+
+    def sync(self):
+        self._check(lib().damf_sync(self._h))
+
+    def close(self):
+        if self._h:
+            lib().damf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()

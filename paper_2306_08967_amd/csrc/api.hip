@@ -1,0 +1,495 @@
+// api.hip -- the C ABI (include/damf.h): context lifetime, argument checks,
+// host <-> device marshalling, and the order of kernels per call.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "damf_internal.h"
+
+namespace damf {
+size_t chain_scratch_doubles();
+}
+
+using namespace damf;
+
+namespace {
+
+damf_status fail(damf_ctx *c, damf_status s, const char *msg) {
+  if (c) c->err = msg;
+  return s;
+}
+
+damf_status dev_fail(damf_ctx *c, hipError_t e, const char *where) {
+  if (c) {
+    c->poisoned = true;
+    c->err = std::string(where) + ": " + hipGetErrorString(e);
+  }
+  return (e == hipErrorOutOfMemory) ? DAMF_E_OOM : DAMF_E_DEVICE;
+}
+
+#define API_HIP(ctx, expr, where)                   \
+  do {                                              \
+    hipError_t _e = (expr);                         \
+    if (_e != hipSuccess) return dev_fail(ctx, _e, where); \
+  } while (0)
+
+template <typename T>
+hipError_t dalloc(T **p, size_t count) {
+  return hipMalloc((void **)p, std::max<size_t>(count, 1) * sizeof(T));
+}
+
+damf_status check_config(const damf_config *cfg) {
+  if (!cfg) return DAMF_E_INVALID_ARG;
+  if (cfg->n < 1 || cfg->n > (int64_t)INT32_MAX) return DAMF_E_INVALID_ARG;
+  if (cfg->d < 1 || cfg->d > kMaxD) return DAMF_E_INVALID_ARG;
+  if (cfg->max_core_rank < 1 || cfg->max_side < 1 || cfg->max_side > kMaxSide)
+    return DAMF_E_INVALID_ARG;
+  if (cfg->max_core_rank > cfg->max_side) return DAMF_E_INVALID_ARG;
+  if (cfg->d + cfg->max_core_rank > kMaxCore) return DAMF_E_INVALID_ARG;
+  if (!(cfg->alpha > 0.0 && cfg->alpha <= 1.0)) return DAMF_E_INVALID_ARG;
+  if (!(cfg->eps > 0.0)) return DAMF_E_INVALID_ARG;
+  if (!(cfg->tau >= 0.0)) return DAMF_E_INVALID_ARG;
+  if (cfg->oversample < 0 || cfg->power_iters < 0) return DAMF_E_INVALID_ARG;
+  if (cfg->d + cfg->oversample > kMaxCore) return DAMF_E_INVALID_ARG;
+  if (!(cfg->graph_slack >= 1.0)) return DAMF_E_INVALID_ARG;
+  return DAMF_OK;
+}
+
+// Allocates everything except the graph.
+damf_status alloc_state(damf_ctx *c) {
+  const int64_t n = c->n;
+  const int d = c->d;
+  API_HIP(c, dalloc(&c->Ub, n * d), "alloc U_b");
+  API_HIP(c, dalloc(&c->Vb, n * d), "alloc V_b");
+  API_HIP(c, dalloc(&c->P, 2 * d * d), "alloc P");
+  API_HIP(c, dalloc(&c->Pnext, 2 * d * d), "alloc P");
+  API_HIP(c, dalloc(&c->sigma, kMaxCore), "alloc sigma");
+  if (c->ppr_on) {
+    API_HIP(c, dalloc(&c->Zb, n * d), "alloc Z_b");
+    API_HIP(c, dalloc(&c->R, n * d), "alloc R");
+  }
+  Workspace &w = c->ws;
+  API_HIP(c, dalloc(&w.ops_src, kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.ops_dst, kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.ops_op, kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.units, kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.chunk_ent, 2 * kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.net, 2 * kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.net_t, 2 * kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.rows_out, 2 * kMaxBatch + 1), "alloc ws");
+  API_HIP(c, dalloc(&w.rowpos_out, 2 * kMaxBatch + 1), "alloc ws");
+  API_HIP(c, dalloc(&w.rows_in, 2 * kMaxBatch + 1), "alloc ws");
+  API_HIP(c, dalloc(&w.rowpos_in, 2 * kMaxBatch + 1), "alloc ws");
+  API_HIP(c, dalloc(&w.chunks, 2 * kMaxBatch + 1), "alloc ws");
+  API_HIP(c, dalloc(&w.chunk_s1, 2 * kMaxBatch + kMaxSide), "alloc ws");
+  API_HIP(c, dalloc(&w.chunk_s2, 2 * kMaxBatch + kMaxSide), "alloc ws");
+  API_HIP(c, dalloc(&w.hdr, 1), "alloc ws");
+  API_HIP(c, hipHostMalloc((void **)&w.hdr_host, sizeof(BatchHeader)), "alloc pinned");
+  API_HIP(c, dalloc(&w.cstats, 1), "alloc ws");
+  API_HIP(c, hipHostMalloc((void **)&w.cstats_host, sizeof(ChainStats)), "alloc pinned");
+  w.scratch_doubles = chain_scratch_doubles();
+  API_HIP(c, dalloc(&w.scratch, w.scratch_doubles), "alloc scratch");
+  API_HIP(c, dalloc(&w.counters, 16), "alloc ws");
+  API_HIP(c, hipHostMalloc((void **)&w.counters_host, 16 * sizeof(int64_t)), "alloc pinned");
+  API_HIP(c, hipHostMalloc((void **)&w.dscratch_host, 16 * sizeof(double)), "alloc pinned");
+  if (c->ppr_on) {
+    API_HIP(c, dalloc(&w.stamp, n), "alloc ppr");
+    API_HIP(c, dalloc(&w.cand, n), "alloc ppr");
+    API_HIP(c, dalloc(&w.cand2, n), "alloc ppr");
+    API_HIP(c, dalloc(&w.frontier, n), "alloc ppr");
+    API_HIP(c, hipMemsetAsync(w.stamp, 0xff, n * sizeof(int32_t), c->stream), "memset");
+  }
+  for (auto &e : c->ev) API_HIP(c, hipEventCreate(&e), "event");
+  return DAMF_OK;
+}
+
+void free_ctx(damf_ctx *c) {
+  if (!c) return;
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  csr_free(c->out);
+  csr_free(c->in);
+  void *ptrs[] = {c->Ub, c->Vb, c->Zb, c->R, c->P, c->Pnext, c->sigma,
+                  c->ws.ops_src, c->ws.ops_dst, c->ws.ops_op, c->ws.units, c->ws.chunk_ent,
+                  c->ws.net, c->ws.net_t, c->ws.rows_out, c->ws.rowpos_out, c->ws.rows_in,
+                  c->ws.rowpos_in, c->ws.chunks, c->ws.chunk_s1, c->ws.chunk_s2, c->ws.hdr,
+                  c->ws.cstats, c->ws.scratch, c->ws.counters, c->ws.stamp, c->ws.cand,
+                  c->ws.cand2, c->ws.frontier};
+  for (void *p : ptrs)
+    if (p) (void)hipFree(p);
+  if (c->ws.hdr_host) (void)hipHostFree(c->ws.hdr_host);
+  if (c->ws.cstats_host) (void)hipHostFree(c->ws.cstats_host);
+  if (c->ws.counters_host) (void)hipHostFree(c->ws.counters_host);
+  if (c->ws.dscratch_host) (void)hipHostFree(c->ws.dscratch_host);
+  for (auto &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+  delete c;
+}
+
+// Builds out- and in-CSR from an edge list (host or device pointers).
+damf_status build_graph(damf_ctx *c, int64_t m, const int32_t *src, const int32_t *dst,
+                        int32_t flags) {
+  if (m < 0 || (m > 0 && (!src || !dst))) return fail(c, DAMF_E_INVALID_ARG, "bad edge list");
+  const int32_t *ds = src, *dd = dst;
+  int32_t *own_s = nullptr, *own_d = nullptr;
+  if (!(flags & DAMF_DEVICE_PTRS) && m > 0) {
+    // host validation before anything is built
+    for (int64_t e = 0; e < m; ++e)
+      if (src[e] < 0 || dst[e] < 0 || src[e] >= c->n || dst[e] >= c->n)
+        return fail(c, DAMF_E_OUT_OF_RANGE, "edge id out of range");
+    API_HIP(c, dalloc(&own_s, m), "alloc edges");
+    API_HIP(c, dalloc(&own_d, m), "alloc edges");
+    API_HIP(c, hipMemcpyAsync(own_s, src, m * sizeof(int32_t), hipMemcpyHostToDevice, c->stream), "copy edges");
+    API_HIP(c, hipMemcpyAsync(own_d, dst, m * sizeof(int32_t), hipMemcpyHostToDevice, c->stream), "copy edges");
+    ds = own_s;
+    dd = own_d;
+  } else if (m > 0) {
+    int32_t *bad = reinterpret_cast<int32_t *>(c->ws.counters);
+    API_HIP(c, launch_validate_edges(ds, dd, m, c->n, bad, c->stream), "validate");
+    int32_t hbad = 0;
+    API_HIP(c, hipMemcpyAsync(&hbad, bad, sizeof(int32_t), hipMemcpyDeviceToHost, c->stream), "validate");
+    API_HIP(c, hipStreamSynchronize(c->stream), "validate");
+    if (hbad) return fail(c, DAMF_E_OUT_OF_RANGE, "edge id out of range");
+  }
+  API_HIP(c, csr_build(c, c->out, ds, dd, m, c->cfg.graph_slack), "build CSR");
+  API_HIP(c, csr_build(c, c->in, dd, ds, m, c->cfg.graph_slack), "build CSR^T");
+  API_HIP(c, hipStreamSynchronize(c->stream), "build CSR");
+  if (own_s) (void)hipFree(own_s);
+  if (own_d) (void)hipFree(own_d);
+  return DAMF_OK;
+}
+
+damf_status new_ctx(const damf_config *cfg, damf_ctx **out, damf_ctx **cptr) {
+  if (!out) return DAMF_E_INVALID_ARG;
+  *out = nullptr;
+  damf_status st = check_config(cfg);
+  if (st != DAMF_OK) return st;
+  damf_ctx *c = new (std::nothrow) damf_ctx();
+  if (!c) return DAMF_E_OOM;
+  c->cfg = *cfg;
+  c->n = cfg->n;
+  c->d = cfg->d;
+  c->ppr_on = cfg->alpha < 1.0;
+  if (hipGetDevice(&c->device) != hipSuccess) {
+    delete c;
+    return DAMF_E_DEVICE;
+  }
+  if (cfg->hip_stream) {
+    c->stream = reinterpret_cast<hipStream_t>(cfg->hip_stream);
+  } else {
+    if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+      delete c;
+      return DAMF_E_DEVICE;
+    }
+    c->own_stream = true;
+  }
+  *cptr = c;
+  return DAMF_OK;
+}
+
+double ms_between(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+  return (double)ms;
+}
+
+}  // namespace
+
+extern "C" {
+
+void damf_config_default(damf_config *cfg) {
+  if (!cfg) return;
+  std::memset(cfg, 0, sizeof(*cfg));
+  cfg->n = 0;
+  cfg->d = 128;
+  cfg->directed = 1;
+  cfg->oversample = 10;
+  cfg->power_iters = 2;
+  cfg->seed = 1;
+  cfg->alpha = 0.15;
+  cfg->eps = 1e-5;
+  cfg->max_core_rank = 64;
+  cfg->max_side = 64;
+  cfg->tau = 1e-6;
+  cfg->auto_enhance = 1;
+  cfg->graph_slack = 1.25;
+  cfg->hip_stream = nullptr;
+}
+
+const char *damf_status_string(damf_status s) {
+  switch (s) {
+    case DAMF_OK: return "ok";
+    case DAMF_E_INVALID_ARG: return "invalid argument";
+    case DAMF_E_OUT_OF_RANGE: return "node id or op out of range";
+    case DAMF_E_OOM: return "out of device memory";
+    case DAMF_E_DEVICE: return "device error";
+    case DAMF_E_NUMERIC: return "numerical failure";
+    case DAMF_E_STATE: return "context poisoned by an earlier device error";
+  }
+  return "unknown status";
+}
+
+const char *damf_last_error(const damf_ctx *ctx) { return ctx ? ctx->err.c_str() : "no context"; }
+
+damf_status damf_init_factors(const damf_config *cfg, int64_t m, const int32_t *src,
+                              const int32_t *dst, const double *U, const double *S,
+                              const double *V, int32_t flags, damf_ctx **out) {
+  damf_ctx *c = nullptr;
+  damf_status st = new_ctx(cfg, out, &c);
+  if (st != DAMF_OK) return st;
+  if (!U || !S || !V) {
+    free_ctx(c);
+    return DAMF_E_INVALID_ARG;
+  }
+  const int64_t n = c->n;
+  const int d = c->d;
+  for (int i = 0; i < d; ++i)
+    if (!std::isfinite(S[i]) || S[i] < 0.0 || (i > 0 && S[i] > S[i - 1] * (1.0 + 1e-12))) {
+      free_ctx(c);
+      return DAMF_E_INVALID_ARG;
+    }
+  if ((st = alloc_state(c)) != DAMF_OK || (st = build_graph(c, m, src, dst, flags)) != DAMF_OK) {
+    free_ctx(c);
+    return st;
+  }
+  std::vector<float> buf((size_t)n * d);
+  for (int side = 0; side < 2; ++side) {
+    const double *M = side ? V : U;
+    for (size_t i = 0; i < buf.size(); ++i) buf[i] = (float)M[i];
+    if (hipMemcpy(side ? c->Vb : c->Ub, buf.data(), buf.size() * sizeof(float),
+                  hipMemcpyHostToDevice) != hipSuccess) {
+      free_ctx(c);
+      return DAMF_E_DEVICE;
+    }
+  }
+  std::vector<double> P(2 * (size_t)d * d, 0.0);
+  for (int s = 0; s < 2; ++s)
+    for (int i = 0; i < d; ++i) P[s * d * d + i * d + i] = 1.0;
+  std::vector<double> sig(kMaxCore, 0.0);
+  std::copy(S, S + d, sig.begin());
+  if (hipMemcpy(c->P, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemcpy(c->sigma, sig.data(), sig.size() * sizeof(double), hipMemcpyHostToDevice) !=
+          hipSuccess) {
+    free_ctx(c);
+    return DAMF_E_DEVICE;
+  }
+  if (c->ppr_on) {
+    if (ppr_init(c) != hipSuccess) {
+      free_ctx(c);
+      return DAMF_E_DEVICE;
+    }
+  }
+  if (hipStreamSynchronize(c->stream) != hipSuccess) {
+    free_ctx(c);
+    return DAMF_E_DEVICE;
+  }
+  *out = c;
+  return DAMF_OK;
+}
+
+damf_status damf_init(const damf_config *cfg, int64_t m, const int32_t *src, const int32_t *dst,
+                      int32_t flags, damf_ctx **out) {
+  damf_ctx *c = nullptr;
+  damf_status st = new_ctx(cfg, out, &c);
+  if (st != DAMF_OK) return st;
+  if ((st = alloc_state(c)) != DAMF_OK || (st = build_graph(c, m, src, dst, flags)) != DAMF_OK) {
+    free_ctx(c);
+    return st;
+  }
+  hipError_t e = rsvd_init(c);
+  if (e == hipSuccess && c->ppr_on) e = ppr_init(c);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  if (e != hipSuccess) {
+    free_ctx(c);
+    return (e == hipErrorOutOfMemory) ? DAMF_E_OOM : DAMF_E_DEVICE;
+  }
+  *out = c;
+  return DAMF_OK;
+}
+
+damf_status damf_update(damf_ctx *c, int64_t k, const int32_t *src, const int32_t *dst,
+                        const int8_t *op, int32_t flags, damf_batch_info *info) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  if (k < 0 || k > kMaxBatch) return fail(c, DAMF_E_INVALID_ARG, "batch size out of range");
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (info) info->ops = k;
+  if (k == 0) return DAMF_OK;
+  if (!src || !dst || !op) return fail(c, DAMF_E_INVALID_ARG, "null op arrays");
+  hipStream_t s = c->stream;
+  Workspace &w = c->ws;
+  auto t0 = std::chrono::steady_clock::now();
+  if (flags & DAMF_DEVICE_PTRS) {
+    API_HIP(c, hipMemcpyAsync(w.ops_src, src, k * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "copy ops");
+    API_HIP(c, hipMemcpyAsync(w.ops_dst, dst, k * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "copy ops");
+    API_HIP(c, hipMemcpyAsync(w.ops_op, op, k * sizeof(int8_t), hipMemcpyDeviceToDevice, s), "copy ops");
+  } else {
+    for (int64_t i = 0; i < k; ++i)
+      if (src[i] < 0 || dst[i] < 0 || src[i] >= c->n || dst[i] >= c->n || (op[i] != 1 && op[i] != -1))
+        return fail(c, DAMF_E_OUT_OF_RANGE, "op id or type out of range");
+    API_HIP(c, hipMemcpyAsync(w.ops_src, src, k * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy ops");
+    API_HIP(c, hipMemcpyAsync(w.ops_dst, dst, k * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy ops");
+    API_HIP(c, hipMemcpyAsync(w.ops_op, op, k * sizeof(int8_t), hipMemcpyHostToDevice, s), "copy ops");
+  }
+  API_HIP(c, hipEventRecord(c->ev[0], s), "event");
+  API_HIP(c, launch_batch_prepare(c, (int)k), "batch prepare");
+  API_HIP(c, hipMemcpyAsync(w.hdr_host, w.hdr, sizeof(BatchHeader), hipMemcpyDeviceToHost, s), "header");
+  API_HIP(c, hipStreamSynchronize(s), "batch prepare");
+  const BatchHeader h = *w.hdr_host;
+  if (h.bad_ops > 0) return fail(c, DAMF_E_OUT_OF_RANGE, "op id or type out of range");
+  API_HIP(c, hipEventRecord(c->ev[1], s), "event");
+  if (h.n_net > 0) {
+    if (c->ppr_on) API_HIP(c, ppr_fixup(c, h.n_rows_out), "PPR structural fix-up");
+    API_HIP(c, launch_csr_edit(c, c->out, w.net, w.rows_out, w.rowpos_out, h.n_rows_out, false), "CSR edit");
+    API_HIP(c, launch_csr_edit(c, c->in, w.net_t, w.rows_in, w.rowpos_in, h.n_rows_in, true), "CSR^T edit");
+    API_HIP(c, launch_chain(c, h.n_chunks), "chain");
+  }
+  API_HIP(c, hipEventRecord(c->ev[2], s), "event");
+  int64_t rounds = 0, pushes = 0, edges = 0;
+  if (c->ppr_on && c->cfg.auto_enhance) {
+    API_HIP(c, ppr_push(c, w.rows_out, h.n_rows_out, &rounds, &pushes, &edges), "PPR push");
+  }
+  API_HIP(c, hipEventRecord(c->ev[3], s), "event");
+  API_HIP(c, hipMemcpyAsync(w.cstats_host, w.cstats, sizeof(ChainStats), hipMemcpyDeviceToHost, s), "stats");
+  API_HIP(c, hipMemcpyAsync(w.hdr_host, w.hdr, sizeof(BatchHeader), hipMemcpyDeviceToHost, s), "header");
+  API_HIP(c, hipStreamSynchronize(s), "update");
+  if (w.hdr_host->pool_overflow) {
+    c->poisoned = true;
+    return fail(c, DAMF_E_OOM, "graph pool exhausted");
+  }
+  if (h.n_net > 0 && w.cstats_host->numeric_error) {
+    c->poisoned = true;
+    return fail(c, DAMF_E_NUMERIC, "singular projection in the lazy update");
+  }
+  if (info) {
+    info->net_entries = h.n_net;
+    info->chunks = h.n_chunks;
+    info->max_core = h.n_net > 0 ? w.cstats_host->max_core : 0;
+    info->dropped = h.n_net > 0 ? w.cstats_host->dropped : 0;
+    info->push_rounds = rounds;
+    info->pushes = pushes;
+    info->push_edges = edges;
+    info->ms_prepare = ms_between(c->ev[0], c->ev[1]);
+    info->ms_chain = ms_between(c->ev[1], c->ev[2]);
+    info->ms_enhance = ms_between(c->ev[2], c->ev[3]);
+  }
+  (void)t0;
+  return DAMF_OK;
+}
+
+damf_status damf_enhance(damf_ctx *c) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  if (!c->ppr_on) return DAMF_OK;
+  int64_t r, p, e;
+  API_HIP(c, ppr_push(c, nullptr, 0, &r, &p, &e), "PPR push");
+  API_HIP(c, hipStreamSynchronize(c->stream), "PPR push");
+  return DAMF_OK;
+}
+
+damf_status damf_query(damf_ctx *c, damf_which which, int64_t q, const int32_t *nodes,
+                       float *out, int32_t flags) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  if (which < DAMF_X || which > DAMF_Z || q < 0 || !out) return fail(c, DAMF_E_INVALID_ARG, "bad query");
+  if (!nodes && q != c->n) return fail(c, DAMF_E_INVALID_ARG, "q must be n without a node list");
+  if (q == 0) return DAMF_OK;
+  const int d = c->d;
+  hipStream_t s = c->stream;
+  if (which == DAMF_Z && !c->ppr_on) which = DAMF_X;  // alpha = 1: Z = X
+  const int32_t *dn = nodes;
+  float *dout = out;
+  int32_t *own_n = nullptr;
+  float *own_o = nullptr;
+  if (!(flags & DAMF_DEVICE_PTRS)) {
+    if (nodes) {
+      for (int64_t i = 0; i < q; ++i)
+        if (nodes[i] < 0 || nodes[i] >= c->n) return fail(c, DAMF_E_OUT_OF_RANGE, "query id out of range");
+      API_HIP(c, dalloc(&own_n, q), "alloc query");
+      API_HIP(c, hipMemcpyAsync(own_n, nodes, q * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy query");
+      dn = own_n;
+    }
+    API_HIP(c, dalloc(&own_o, q * d), "alloc query");
+    dout = own_o;
+  }
+  API_HIP(c, launch_query(c, which, q, dn, dout), "query");
+  if (own_o) {
+    API_HIP(c, hipMemcpyAsync(out, own_o, q * d * sizeof(float), hipMemcpyDeviceToHost, s), "copy query");
+  }
+  API_HIP(c, hipStreamSynchronize(s), "query");
+  if (own_n) (void)hipFree(own_n);
+  if (own_o) (void)hipFree(own_o);
+  return DAMF_OK;
+}
+
+damf_status damf_singular_values(damf_ctx *c, double *out) {
+  if (!c || !out) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  API_HIP(c, hipMemcpyAsync(out, c->sigma, c->d * sizeof(double), hipMemcpyDeviceToHost, c->stream), "sigma");
+  API_HIP(c, hipStreamSynchronize(c->stream), "sigma");
+  return DAMF_OK;
+}
+
+damf_status damf_export_csr(damf_ctx *c, int32_t transpose, int64_t *indptr, int32_t *indices,
+                            int64_t *m_out) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  API_HIP(c, csr_export(c, transpose ? c->in : c->out, indptr, indices, m_out), "export CSR");
+  return DAMF_OK;
+}
+
+damf_status damf_export_state(damf_ctx *c, double *Ub, double *Vb, double *PU, double *PV,
+                              double *Zb, double *R) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  const size_t nd = (size_t)c->n * c->d;
+  const int d = c->d;
+  API_HIP(c, hipStreamSynchronize(c->stream), "export");
+  std::vector<float> buf;
+  auto pull = [&](const float *src, double *dst) -> hipError_t {
+    if (!dst) return hipSuccess;
+    if (!src) {
+      std::fill(dst, dst + nd, 0.0);
+      return hipSuccess;
+    }
+    buf.resize(nd);
+    hipError_t e = hipMemcpy(buf.data(), src, nd * sizeof(float), hipMemcpyDeviceToHost);
+    for (size_t i = 0; i < nd; ++i) dst[i] = buf[i];
+    return e;
+  };
+  API_HIP(c, pull(c->Ub, Ub), "export U_b");
+  API_HIP(c, pull(c->Vb, Vb), "export V_b");
+  API_HIP(c, pull(c->Zb, Zb), "export Z_b");
+  API_HIP(c, pull(c->R, R), "export R");
+  if (PU) API_HIP(c, hipMemcpy(PU, c->P, (size_t)d * d * sizeof(double), hipMemcpyDeviceToHost), "export P");
+  if (PV) API_HIP(c, hipMemcpy(PV, c->P + (size_t)d * d, (size_t)d * d * sizeof(double), hipMemcpyDeviceToHost), "export P");
+  return DAMF_OK;
+}
+
+damf_status damf_residual_max(damf_ctx *c, double *out) {
+  if (!c || !out) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  if (!c->ppr_on) {
+    *out = 0.0;
+    return DAMF_OK;
+  }
+  API_HIP(c, ppr_residual_max(c, out), "residual max");
+  return DAMF_OK;
+}
+
+damf_status damf_sync(damf_ctx *c) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  API_HIP(c, hipStreamSynchronize(c->stream), "sync");
+  return DAMF_OK;
+}
+
+void damf_destroy(damf_ctx *c) { free_ctx(c); }
+
+}  // extern "C"

@@ -1,0 +1,839 @@
+// chain.hip -- Steps 1-3 of the update (Sec. 4.5; Theorem 2; Algorithm 1,
+// UpdateEmbeddingE) for every chunk of a batch, in one workgroup.
+//
+// Chunks depend on each other through Sigma and the projections, so they run
+// one after another inside a single 1024-thread workgroup that keeps the
+// small dense state in LDS / L2 and the core matrix in VGPRs.  For a chunk
+// with rows S1, columns S2 and dA = I[:,S1] D I[:,S2]^T the kernel computes,
+// in the U-form (U = U_b P_U, V = V_b P_V):
+//
+//   Step 1  W_B = U^T B, W_C = V^T C  (gather of the touched rows, Lemma 2)
+//           residual Grams G = B^T B - W^T W (Proposition 1 for k columns),
+//           factored by pivoted Cholesky with drop threshold tau:
+//           (I - U U^T) B ~ Q_B R_B,  Q_B = (I - U U^T) B T_B
+//   Step 2  K = [[Sigma, 0], [0, 0]] + [W_B; R_B][W_C; R_C]^T, FP64 one-sided
+//           Jacobi SVD K = E Theta H^T, keep the top d
+//   Step 3  F_U = E[:d] - W_B T_B E[d:],  dU = B T_B E[d:]   (same for V)
+//           P_U <- P_U F_U and U_b[S1] += dU P_U^-1 (the lazy base-space
+//           update of Sec. 4.1), Sigma <- Theta[:d]
+//
+// The PPR residual R receives the same base-coordinate signal change as U_b
+// (Step 4 input, Algorithm 2).
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "damf_internal.h"
+#include "jacobi.h"
+
+namespace damf {
+
+namespace {
+
+constexpr int NPMAX = 192;   // max padded core size
+constexpr int DMAX = 128;
+constexpr int KMAX = 64;
+constexpr int LDS_DOUBLES = 19200;  // 150 KB
+
+// global scratch layout (doubles)
+constexpr size_t OFF_KG = 0;                              // K, col-major, stride NPMAX
+constexpr size_t OFF_EG = OFF_KG + NPMAX * NPMAX;         // E, col-major, stride NPMAX
+constexpr size_t OFF_HG = OFF_EG + NPMAX * DMAX;          // H, row-major [j][c], stride DMAX
+constexpr size_t OFF_UP = OFF_HG + NPMAX * DMAX;          // U rows of S1, [i][c]
+constexpr size_t OFF_VP = OFF_UP + KMAX * DMAX;
+constexpr size_t OFF_WB = OFF_VP + KMAX * DMAX;           // W_B^T [t][c]
+constexpr size_t OFF_WC = OFF_WB + KMAX * DMAX;
+constexpr size_t OFF_LB = OFF_WC + KMAX * DMAX;           // pivoted Cholesky factor [i][j]
+constexpr size_t OFF_LC = OFF_LB + KMAX * KMAX;
+constexpr size_t OFF_RB = OFF_LC + KMAX * KMAX;           // R_B [i][t]
+constexpr size_t OFF_RC = OFF_RB + KMAX * KMAX;
+constexpr size_t OFF_FU = OFF_RC + KMAX * KMAX;           // F_U [i][c]
+constexpr size_t OFF_FV = OFF_FU + DMAX * DMAX;
+constexpr size_t OFF_DU = OFF_FV + DMAX * DMAX;           // dU rows [i][c]
+constexpr size_t OFF_DV = OFF_DU + KMAX * DMAX;
+constexpr size_t OFF_YB = OFF_DV + KMAX * DMAX;           // Y = T E_bot [t][c]
+constexpr size_t OFF_YC = OFF_YB + KMAX * DMAX;
+constexpr size_t OFF_TH = OFF_YC + KMAX * DMAX;           // theta (NPMAX)
+constexpr size_t SCRATCH_DOUBLES = OFF_TH + NPMAX + 64;
+
+struct ChainParams {
+  int d;
+  int64_t n;
+  const ChunkDesc *chunks;
+  int n_chunks;
+  const int32_t *S1, *S2;
+  const NetEntry *ent;
+  float *Ub, *Vb, *R;
+  double *P, *Pnext;  // [P_U | P_V], 2 d x d row-major
+  double *sigma;
+  double *scr;
+  double tau;
+  ChainStats *stats;
+};
+
+struct ChunkState {
+  int s1, s2, k, mode;  // mode 1: s1 <= s2 (B = I[:,S1]), mode 0: B = I[:,S1] D
+  int rhoB, rhoC;
+  const int32_t *S1, *S2;
+  const NetEntry *ent;
+  int ne;
+};
+
+__device__ __forceinline__ int tid() { return threadIdx.x; }
+constexpr int NT = kChainThreads;
+constexpr int NW = NT / 64;   // waves
+constexpr int NG = NT / 128;  // groups of 128 threads (one column each)
+
+// ---------------------------------------------------------------- Step 1
+
+// MP[i][c] = sum_q Mb[rows[i]][q] * Pm[q][c]  (rows of U or V in the current basis)
+__device__ __noinline__ void gather_project(const float *Mb, const int32_t *rows, int s, const double *Pm,
+                               int d, double *lds, double *MP) {
+  for (int e = tid(); e < s * d; e += NT) {
+    int i = e / d, q = e - i * d;
+    lds[i * d + q] = (double)Mb[(int64_t)rows[i] * d + q];
+  }
+  __syncthreads();
+  const int c = tid() & 127, g = tid() >> 7;
+  if (c < d) {
+    double acc[KMAX / NG];
+#pragma unroll
+    for (int j = 0; j < KMAX / NG; ++j) acc[j] = 0.0;
+    for (int q = 0; q < d; ++q) {
+      const double pv = Pm[q * d + c];
+#pragma unroll
+      for (int j = 0; j < KMAX / NG; ++j) {
+        int i = g + NG * j;
+        if (i < s) acc[j] = fma(lds[i * d + q], pv, acc[j]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < KMAX / NG; ++j) {
+      int i = g + NG * j;
+      if (i < s) MP[i * d + c] = acc[j];
+    }
+  }
+  __syncthreads();
+}
+
+// Dense D (s1 x s2) into LDS from the chunk entries.
+__device__ __noinline__ void build_D(const ChunkState &cs, double *D) {
+  for (int e = tid(); e < cs.s1 * cs.s2; e += NT) D[e] = 0.0;
+  __syncthreads();
+  for (int e = tid(); e < cs.ne; e += NT) {
+    NetEntry en = cs.ent[e];
+    int i = (int)lower_bound(cs.S1, (int64_t)cs.s1, en.row);
+    int j = (int)lower_bound(cs.S2, (int64_t)cs.s2, en.col);
+    D[i * cs.s2 + j] = (double)en.delta;
+  }
+  __syncthreads();
+}
+
+// W^T (k x d) for one side.  side 0 (B): mode 1: W_B^T = UP; mode 0: W_B^T = D^T UP.
+// side 1 (C): mode 1: W_C^T = D VP; mode 0: W_C^T = VP.
+__device__ __noinline__ void build_Wt(const ChunkState &cs, int side, int d, const double *D,
+                         const double *MP, double *Wt_lds) {
+  const int k = cs.k;
+  for (int e = tid(); e < k * d; e += NT) {
+    int t = e / d, c = e - t * d;
+    double v = 0.0;
+    if (side == 0) {
+      if (cs.mode) {
+        v = MP[t * d + c];
+      } else {
+        for (int i = 0; i < cs.s1; ++i) {
+          double dv = D[i * cs.s2 + t];
+          if (dv != 0.0) v = fma(dv, MP[i * d + c], v);
+        }
+      }
+    } else {
+      if (cs.mode) {
+        for (int j = 0; j < cs.s2; ++j) {
+          double dv = D[t * cs.s2 + j];
+          if (dv != 0.0) v = fma(dv, MP[j * d + c], v);
+        }
+      } else {
+        v = MP[t * d + c];
+      }
+    }
+    Wt_lds[t * d + c] = v;
+  }
+  __syncthreads();
+}
+
+// G = B^T B - W^T W (side B) or C^T C - W^T W (side C), k x k in LDS; also
+// returns max diag of B^T B through *bmax.
+__device__ __noinline__ void build_gram(const ChunkState &cs, int side, int d, const double *D,
+                           const double *Wt, double *G, double *bmax_out) {
+  const int k = cs.k;
+  __shared__ double s_bmax;
+  if (tid() == 0) s_bmax = 1.0;
+  __syncthreads();
+  for (int e = tid(); e < k * k; e += NT) {
+    int a = e / k, b = e - a * k;
+    double btb;
+    // side B: B^T B = I (mode 1) or D^T D (mode 0); side C: C^T C = D D^T (mode 1) or I
+    bool ident = (side == 0) ? (cs.mode != 0) : (cs.mode == 0);
+    if (ident) {
+      btb = (a == b) ? 1.0 : 0.0;
+    } else if (side == 0) {
+      btb = 0.0;
+      for (int i = 0; i < cs.s1; ++i) btb = fma(D[i * cs.s2 + a], D[i * cs.s2 + b], btb);
+    } else {
+      btb = 0.0;
+      for (int j = 0; j < cs.s2; ++j) btb = fma(D[a * cs.s2 + j], D[b * cs.s2 + j], btb);
+    }
+    double w = 0.0;
+    for (int c = 0; c < d; ++c) w = fma(Wt[a * d + c], Wt[b * d + c], w);
+    G[a * k + b] = btb - w;
+    if (a == b && btb > 1.0) atomicMax((unsigned long long *)&s_bmax, __double_as_longlong(btb));
+  }
+  __syncthreads();
+  *bmax_out = s_bmax;
+  __syncthreads();
+}
+
+// Pivoted Cholesky of the k x k PSD matrix G (in LDS, overwritten): stops when
+// the largest remaining diagonal <= thr.  On return G[i][j] for j < rho, i >= j
+// holds L in pivoted order, perm[] the pivot order.  Returns rho.
+__device__ __noinline__ int pivoted_cholesky(double *G, int k, double thr, int *perm) {
+  __shared__ int s_piv, s_rho;
+  __shared__ double s_diag;
+  const int lane = tid() & 63;
+  if (tid() < k) perm[tid()] = tid();
+  if (tid() == 0) s_rho = k;
+  __syncthreads();
+  for (int j = 0; j < k; ++j) {
+    if (tid() < 64) {
+      // argmax of diagonal over i >= j (k <= 64: one element per lane)
+      double v = -1.0;
+      int idx = lane;
+      if (lane >= j && lane < k) v = G[lane * k + lane];
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        double ov = __shfl_xor(v, off, 64);
+        int oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+          v = ov;
+          idx = oi;
+        }
+      }
+      if (lane == 0) {
+        s_piv = idx;
+        s_diag = v;
+      }
+    }
+    __syncthreads();
+    if (!(s_diag > thr)) {
+      if (tid() == 0) s_rho = j;
+      __syncthreads();
+      break;
+    }
+    const int p = s_piv;
+    if (p != j) {
+      // symmetric swap of rows/cols j and p
+      for (int c = tid(); c < k; c += NT) {
+        double t = G[j * k + c];
+        G[j * k + c] = G[p * k + c];
+        G[p * k + c] = t;
+      }
+      __syncthreads();
+      for (int r = tid(); r < k; r += NT) {
+        double t = G[r * k + j];
+        G[r * k + j] = G[r * k + p];
+        G[r * k + p] = t;
+      }
+      if (tid() == 0) {
+        int t = perm[j];
+        perm[j] = perm[p];
+        perm[p] = t;
+      }
+      __syncthreads();
+    }
+    const double ljj = sqrt(G[j * k + j]);
+    __syncthreads();
+    for (int i = j + 1 + tid(); i < k; i += NT) G[i * k + j] /= ljj;
+    if (tid() == 0) G[j * k + j] = ljj;
+    __syncthreads();
+    const int m = k - j - 1;
+    for (int e = tid(); e < m * m; e += NT) {
+      int i = j + 1 + e / m, l = j + 1 + e % m;
+      if (l <= i) G[i * k + l] -= G[i * k + j] * G[l * k + j];
+    }
+    __syncthreads();
+    // keep the upper triangle consistent for the next pivot's row swap
+    for (int e = tid(); e < m * m; e += NT) {
+      int i = j + 1 + e / m, l = j + 1 + e % m;
+      if (l > i) G[i * k + l] = G[l * k + i];
+    }
+    __syncthreads();
+  }
+  int rho = s_rho;
+  __syncthreads();
+  return rho;
+}
+
+// R (rho x k): R[i][perm[j]] = L[j][i] (j >= i), i.e. R = L^T Pi^T.
+__device__ __noinline__ void store_factor(const double *G, int k, int rho, const int *perm, double *Lg,
+                             double *Rg) {
+  for (int e = tid(); e < k * k; e += NT) Lg[e] = G[e];
+  for (int e = tid(); e < rho * k; e += NT) {
+    int i = e / k, j = e - i * k;  // R row i, pivoted column j
+    double v = (j >= i) ? G[j * k + i] : 0.0;
+    Rg[i * k + perm[j]] = v;
+  }
+}
+
+// ---------------------------------------------------------------- Step 2
+
+template <int RPL>
+__device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double *sigma, double *scr,
+                         double *lds, int *ilds, int *sweeps_out) {
+  using SH = JacobiShape<RPL, NW>;
+  constexpr int NP = SH::NP;
+  constexpr int CPW = SH::CPW;
+  const int lane = tid() & 63, w = tid() >> 6;
+  const int k = cs.k;
+  const int NB = d + cs.rhoB, NC = d + cs.rhoC;
+  const double *WBt = scr + OFF_WB, *WCt = scr + OFF_WC;
+  const double *RB = scr + OFF_RB, *RC = scr + OFF_RC;
+  double *KG = scr + OFF_KG, *EG = scr + OFF_EG, *HG = scr + OFF_HG, *TH = scr + OFF_TH;
+  // L_m = [W_B; R_B] into LDS as [t][i] (k x NP)
+  double *Lm = lds;
+  for (int e = tid(); e < k * NP; e += NT) {
+    int t = e / NP, i = e - t * NP;
+    double v = 0.0;
+    if (i < d)
+      v = WBt[t * d + i];
+    else if (i < NB)
+      v = RB[(i - d) * k + t];
+    Lm[e] = v;
+  }
+  __syncthreads();
+  JacobiRegs<RPL, NW> J;
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = jacobi_slot_col<RPL, NW>(w, c);
+    // R_m[j][t] held by lane t
+    double rm = 0.0;
+    if (j < NC && lane < k) rm = (j < d) ? WCt[lane * d + j] : RC[(j - d) * k + lane];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) J.a[c][r] = 0.0;
+    for (int t = 0; t < k; ++t) {
+      const double rt = __shfl(rm, t, 64);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) J.a[c][r] = fma(Lm[t * NP + r * 64 + lane], rt, J.a[c][r]);
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = r * 64 + lane;
+      if (i >= NB || j >= NC) J.a[c][r] = 0.0;
+      if (i == j && i < d) J.a[c][r] += sigma[i];
+      KG[j * NPMAX + i] = J.a[c][r];
+    }
+  }
+  __syncthreads();
+  int *flag = ilds;
+  const int sweeps = jacobi_sweeps<RPL, NW>(J, lds, flag, 60, 1e-14);
+  *sweeps_out = sweeps;
+  // ---- singular values, descending order
+  double *sv = lds;                        // NP values
+  int *sid = ilds + 8;                     // NP column ids -> sorted order
+  int *rank_of = ilds + 8 + 256;           // column id -> rank
+  const double *nrm = lds + 4 * NW * SH::SLOT;
+  __syncthreads();
+  for (int j = tid(); j < NP; j += NT) {
+    sv[j] = sqrt(nrm[j]);
+    sid[j] = j;
+  }
+  __syncthreads();
+  // bitonic sort descending by value (ties by id), NP entries padded to 256
+  for (int i = NP + tid(); i < 256; i += NT) {
+    sv[i] = -1.0;
+    sid[i] = 1 << 20;
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= 256; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      if (tid() < 256) {
+        int i = tid(), q = i ^ jj;
+        if (q > i) {
+          double a = sv[i], b = sv[q];
+          int ia = sid[i], ib = sid[q];
+          bool before = (a > b) || (a == b && ia < ib);  // a should precede b
+          bool up = (i & kk) == 0;
+          if (before != up) {
+            sv[i] = b;
+            sv[q] = a;
+            sid[i] = ib;
+            sid[q] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (tid() < NP) rank_of[sid[tid()]] = tid();
+  if (tid() < NPMAX) TH[tid()] = (tid() < NP) ? sv[tid()] : 0.0;
+  __syncthreads();
+  const double smax = sv[0];
+  const double cut = 1e-10 * smax;
+  // E columns (top d), zero rows beyond NB
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = jacobi_slot_col<RPL, NW>(w, c);
+    const int rk = rank_of[j];
+    if (rk < d) {
+      const double s = sv[rk];
+      const double inv = (s > cut) ? 1.0 / s : 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = r * 64 + lane;
+        EG[rk * NPMAX + i] = (i < NB) ? J.a[c][r] * inv : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+  // ---- H = K^T E Theta^-1 for the top d (tiles of 32 rows of K and E)
+  {
+    const int c = tid() & 127, g = tid() >> 7;
+    constexpr int JPT = NP / NG;  // j values per thread
+    double acc[JPT];
+#pragma unroll
+    for (int q = 0; q < JPT; ++q) acc[q] = 0.0;
+    double *Et = lds;             // [32][128]
+    double *Kt = lds + 32 * 128;  // [32][NP]
+    for (int i0 = 0; i0 < NB; i0 += 32) {
+      for (int e = tid(); e < 32 * 128; e += NT) {
+        int ii = e >> 7, cc = e & 127;
+        Et[e] = (cc < d && i0 + ii < NB) ? EG[cc * NPMAX + i0 + ii] : 0.0;
+      }
+      for (int e = tid(); e < 32 * NP; e += NT) {
+        int jj = e / 32, ii = e - jj * 32;
+        Kt[ii * NP + jj] = (i0 + ii < NB) ? KG[jj * NPMAX + i0 + ii] : 0.0;
+      }
+      __syncthreads();
+      for (int ii = 0; ii < 32; ++ii) {
+        const double ev = Et[ii * 128 + c];
+#pragma unroll
+        for (int q = 0; q < JPT; ++q) acc[q] = fma(Kt[ii * NP + g + NG * q], ev, acc[q]);
+      }
+      __syncthreads();
+    }
+    if (c < d) {
+      const double s = TH[c];
+      const double inv = (s > cut) ? 1.0 / s : 0.0;
+#pragma unroll
+      for (int q = 0; q < JPT; ++q) {
+        const int j = g + NG * q;
+        if (j < NPMAX) HG[j * DMAX + c] = (j < NC) ? acc[q] * inv : 0.0;
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// Orthonormal completion of columns c < d whose singular value is <= cut:
+// E (NB rows, col-major stride NPMAX) and H (NC rows, row-major stride DMAX).
+__device__ __noinline__ void complete_basis(int d, int NB, int NC, double *scr) {
+  const double *TH = scr + OFF_TH;
+  double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
+  const double cut = 1e-10 * TH[0];
+  if (tid() >= 64) return;
+  const int lane = tid() & 63;
+  for (int c = 0; c < d; ++c) {
+    if (TH[c] > cut) continue;
+    for (int side = 0; side < 2; ++side) {
+      const int N = side ? NC : NB;
+      auto at = [&](int i, int cc) -> double & {
+        return side ? HG[i * DMAX + cc] : EG[cc * NPMAX + i];
+      };
+      for (int cand = 0; cand < N; ++cand) {
+        double v[3];
+        for (int r = 0; r < 3; ++r) {
+          int i = r * 64 + lane;
+          v[r] = (i == cand) ? 1.0 : 0.0;
+        }
+        for (int pass = 0; pass < 2; ++pass) {
+          for (int o = 0; o < d; ++o) {
+            if (o == c || (TH[o] <= cut && o > c)) continue;
+            double dot = 0.0;
+            for (int r = 0; r < 3; ++r) {
+              int i = r * 64 + lane;
+              if (i < N) dot += at(i, o) * v[r];
+            }
+            dot = wave_sum(dot);
+            for (int r = 0; r < 3; ++r) {
+              int i = r * 64 + lane;
+              if (i < N) v[r] -= dot * at(i, o);
+            }
+          }
+        }
+        double nn = 0.0;
+        for (int r = 0; r < 3; ++r) {
+          int i = r * 64 + lane;
+          if (i < N) nn += v[r] * v[r];
+        }
+        nn = wave_sum(nn);
+        if (nn > 0.25) {
+          double inv = 1.0 / sqrt(nn);
+          for (int r = 0; r < 3; ++r) {
+            int i = r * 64 + lane;
+            if (i < N) at(i, c) = v[r] * inv;
+          }
+          break;
+        }
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- Step 3
+
+// Y = T E_bot (k x d): solve L1^T X = E_bot (rho x d) and scatter rows by perm.
+// side 0 uses E (rows d.. of EG), side 1 uses H (rows d.. of HG).
+__device__ __noinline__ void solve_Y(int side, int d, int k, int rho, const int *perm, const double *Lg,
+                        double *scr, double *lds) {
+  double *Y = scr + (side ? OFF_YC : OFF_YB);
+  const double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
+  double *L = lds;              // k x k
+  double *X = lds + KMAX * KMAX;  // rho x d
+  for (int e = tid(); e < k * k; e += NT) L[e] = Lg[e];
+  for (int e = tid(); e < rho * d; e += NT) {
+    int i = e / d, c = e - i * d;
+    X[e] = side ? HG[(d + i) * DMAX + c] : EG[c * NPMAX + d + i];
+  }
+  __syncthreads();
+  const int c = tid();
+  if (c < d) {
+    for (int i = rho - 1; i >= 0; --i) {
+      double v = X[i * d + c];
+      for (int j = i + 1; j < rho; ++j) v -= L[j * k + i] * X[j * d + c];
+      X[i * d + c] = v / L[i * k + i];
+    }
+  }
+  __syncthreads();
+  for (int e = tid(); e < k * d; e += NT) Y[e] = 0.0;
+  __syncthreads();
+  for (int e = tid(); e < rho * d; e += NT) {
+    int i = e / d, c2 = e - i * d;
+    Y[perm[i] * d + c2] = X[e];
+  }
+  __syncthreads();
+}
+
+// F = E_top - W Y (d x d) and the row corrections.
+__device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, int d, double *scr,
+                                  double *lds) {
+  const int k = cs.k;
+  const double *Y = scr + (side ? OFF_YC : OFF_YB);
+  const double *Wt = scr + (side ? OFF_WC : OFF_WB);
+  const double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
+  double *F = scr + (side ? OFF_FV : OFF_FU);
+  double *Dl = scr + (side ? OFF_DV : OFF_DU);
+  double *Ys = lds;               // k x d
+  double *Ws = lds + KMAX * DMAX;  // k x d
+  for (int e = tid(); e < k * d; e += NT) {
+    Ys[e] = Y[e];
+    Ws[e] = Wt[e];
+  }
+  __syncthreads();
+  for (int e = tid(); e < d * d; e += NT) {
+    int i = e / d, c = e - i * d;
+    double v = side ? HG[i * DMAX + c] : EG[c * NPMAX + i];
+    for (int t = 0; t < k; ++t) v -= Ws[t * d + i] * Ys[t * d + c];
+    F[i * d + c] = v;
+  }
+  __syncthreads();
+  // row corrections: side B: mode 1 -> Y (s1 rows); mode 0 -> D Y (s1 x d)
+  //                  side C: mode 1 -> D^T Y (s2 rows); mode 0 -> Y
+  double *D = lds + KMAX * DMAX;  // s1 x s2, over the W copy
+  for (int e = tid(); e < cs.s1 * cs.s2; e += NT) D[e] = 0.0;
+  __syncthreads();
+  for (int e = tid(); e < cs.ne; e += NT) {
+    NetEntry en = cs.ent[e];
+    int i = (int)lower_bound(cs.S1, (int64_t)cs.s1, en.row);
+    int j = (int)lower_bound(cs.S2, (int64_t)cs.s2, en.col);
+    D[i * cs.s2 + j] = (double)en.delta;
+  }
+  __syncthreads();
+  const int rows = side ? cs.s2 : cs.s1;
+  const bool direct = side ? (cs.mode == 0) : (cs.mode != 0);
+  for (int e = tid(); e < rows * d; e += NT) {
+    int i = e / d, c = e - i * d;
+    double v = 0.0;
+    if (direct) {
+      v = Ys[i * d + c];
+    } else if (side == 0) {
+      for (int t = 0; t < k; ++t) v = fma(D[i * cs.s2 + t], Ys[t * d + c], v);
+    } else {
+      for (int t = 0; t < k; ++t) v = fma(D[t * cs.s2 + i], Ys[t * d + c], v);
+    }
+    Dl[i * d + c] = v;
+  }
+  __syncthreads();
+}
+
+// Pn = Po F (d x d); F staged in LDS.
+__device__ __noinline__ void mul_PF(int d, const double *Po, const double *F, double *Pn, double *lds) {
+  for (int e = tid(); e < d * d; e += NT) lds[e] = F[e];
+  __syncthreads();
+  const int c = tid() & 127, g = tid() >> 7;
+  if (c < d) {
+    const int rows_per = (d + NG - 1) / NG;
+    for (int i0 = 0; i0 < rows_per; i0 += 16) {
+      double acc[16];
+#pragma unroll
+      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
+      for (int kk = 0; kk < d; ++kk) {
+        const double f = lds[kk * d + c];
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+          int i = g * rows_per + i0 + q;
+          if (i0 + q < rows_per && i < d) acc[q] = fma(Po[i * d + kk], f, acc[q]);
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 16; ++q) {
+        int i = g * rows_per + i0 + q;
+        if (i0 + q < rows_per && i < d) Pn[i * d + c] = acc[q];
+      }
+    }
+  }
+  __syncthreads();
+}
+
+// LU with partial pivoting of Pn (d x d) in LDS, then X Pn = Dl for `rows`
+// row vectors; adds X to M_b[rows] (and to R when given).  Returns 0, or 1 if
+// a zero pivot was met.
+__device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const double *Dl, const int32_t *rows,
+                                int nrows, float *Mb, float *Rr, double *lds, int *ilds) {
+  double *A = lds;  // d x d
+  int *piv = ilds;  // d
+  int *src = ilds + DMAX;
+  __shared__ int s_p, s_bad;
+  for (int e = tid(); e < d * d; e += NT) A[e] = Pn[e];
+  if (tid() == 0) s_bad = 0;
+  __syncthreads();
+  const int lane = tid() & 63;
+  for (int j = 0; j < d; ++j) {
+    if (tid() < 64) {
+      double v = -1.0;
+      int idx = j;
+      for (int i = j + lane; i < d; i += 64) {
+        double a = fabs(A[i * d + j]);
+        if (a > v) {
+          v = a;
+          idx = i;
+        }
+      }
+#pragma unroll
+      for (int off = 32; off >= 1; off >>= 1) {
+        double ov = __shfl_xor(v, off, 64);
+        int oi = __shfl_xor(idx, off, 64);
+        if (ov > v || (ov == v && oi < idx)) {
+          v = ov;
+          idx = oi;
+        }
+      }
+      if (lane == 0) {
+        s_p = idx;
+        piv[j] = idx;
+        if (!(v > 0.0)) s_bad = 1;
+      }
+    }
+    __syncthreads();
+    const int p = s_p;
+    if (p != j) {
+      for (int c = tid(); c < d; c += NT) {
+        double t = A[j * d + c];
+        A[j * d + c] = A[p * d + c];
+        A[p * d + c] = t;
+      }
+      __syncthreads();
+    }
+    const double pv = A[j * d + j];
+    const int m = d - j - 1;
+    if (pv != 0.0) {
+      for (int i = j + 1 + tid(); i < d; i += NT) A[i * d + j] /= pv;
+    }
+    __syncthreads();
+    for (int e = tid(); e < m * m; e += NT) {
+      int i = j + 1 + e / m, c = j + 1 + e % m;
+      A[i * d + c] -= A[i * d + j] * A[j * d + c];
+    }
+    __syncthreads();
+  }
+  if (tid() == 0) {
+    for (int c = 0; c < d; ++c) src[c] = c;
+    for (int j = d - 1; j >= 0; --j) {
+      int t = src[j];
+      src[j] = src[piv[j]];
+      src[piv[j]] = t;
+    }
+  }
+  __syncthreads();
+  if (s_bad) return 1;
+  // one wave per row vector: lanes own columns c = lane, lane + 64
+  const int w = tid() >> 6;
+  double *rowbuf = lds + d * d + w * DMAX;
+  for (int i = w; i < nrows; i += NT / 64) {
+    double y0 = (lane < d) ? Dl[i * d + lane] : 0.0;
+    double y1 = (lane + 64 < d) ? Dl[i * d + lane + 64] : 0.0;
+    // Y U = Dl (forward over columns)
+    for (int c = 0; c < d; ++c) {
+      double own = (c < 64) ? y0 : y1;
+      double yc = __shfl(own, c & 63, 64) / A[c * d + c];
+      if (lane == (c & 63)) {
+        if (c < 64)
+          y0 = yc;
+        else
+          y1 = yc;
+      }
+      if (lane > c && lane < d) y0 -= yc * A[c * d + lane];
+      if (lane + 64 > c && lane + 64 < d) y1 -= yc * A[c * d + lane + 64];
+    }
+    // W L = Y (L unit lower, backward over columns)
+    for (int c = d - 1; c >= 0; --c) {
+      double own = (c < 64) ? y0 : y1;
+      double zc = __shfl(own, c & 63, 64);
+      if (lane < c && lane < d) y0 -= zc * A[c * d + lane];
+      if (lane + 64 < c) y1 -= zc * A[c * d + lane + 64];
+    }
+    if (lane < d) rowbuf[lane] = y0;
+    if (lane + 64 < d) rowbuf[lane + 64] = y1;
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    const int64_t row = rows[i];
+    for (int c = lane; c < d; c += 64) {
+      const double x = rowbuf[src[c]];
+      float *mp = Mb + row * d + c;
+      *mp = (float)((double)(*mp) + x);
+      if (Rr) {
+        float *rp = Rr + row * d + c;
+        *rp = (float)((double)(*rp) + x);
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+  return 0;
+}
+
+__global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ int ilds[1024];
+  __shared__ int permB[KMAX], permC[KMAX];
+  __shared__ double s_bmax;
+  const int d = p.d;
+  double *scr = p.scr;
+  double *Pc = p.P, *Pn = p.Pnext;
+  int max_core = 0, dropped = 0, sweeps_tot = 0, numeric = 0;
+  for (int ch = 0; ch < p.n_chunks; ++ch) {
+    const ChunkDesc desc = p.chunks[ch];
+    ChunkState cs;
+    cs.s1 = desc.s1;
+    cs.s2 = desc.s2;
+    cs.mode = (cs.s1 <= cs.s2) ? 1 : 0;
+    cs.k = cs.mode ? cs.s1 : cs.s2;
+    cs.S1 = p.S1 + desc.s1_off;
+    cs.S2 = p.S2 + desc.s2_off;
+    cs.ent = p.ent + desc.e_off;
+    cs.ne = desc.ne;
+    const int k = cs.k;
+    // ---- Step 1: gather + project
+    gather_project(p.Ub, cs.S1, cs.s1, Pc, d, lds, scr + OFF_UP);
+    gather_project(p.Vb, cs.S2, cs.s2, Pc + d * d, d, lds, scr + OFF_VP);
+    double bmax = 1.0;
+    for (int side = 0; side < 2; ++side) {
+      double *D = lds;                          // s1 x s2 (<= 4096)
+      double *Wt = lds + KMAX * KMAX;           // k x d (<= 8192)
+      double *G = lds + KMAX * KMAX + KMAX * DMAX;  // k x k
+      build_D(cs, D);
+      build_Wt(cs, side, d, D, scr + (side ? OFF_VP : OFF_UP), Wt);
+      for (int e = tid(); e < k * d; e += NT) scr[(side ? OFF_WC : OFF_WB) + e] = Wt[e];
+      build_gram(cs, side, d, D, Wt, G, &bmax);
+      const double thr = p.tau * bmax;
+      int *perm = side ? permC : permB;
+      int rho = pivoted_cholesky(G, k, thr, perm);
+      store_factor(G, k, rho, perm, scr + (side ? OFF_LC : OFF_LB), scr + (side ? OFF_RC : OFF_RB));
+      if (side == 0)
+        cs.rhoB = rho;
+      else
+        cs.rhoC = rho;
+      dropped += k - rho;
+      __syncthreads();
+    }
+    (void)s_bmax;
+    // ---- Step 2: core SVD
+    const int N = d + max(cs.rhoB, cs.rhoC);
+    max_core = max(max_core, N);
+    int sw = 0;
+    if (N <= 64)
+      core_svd<1>(cs, d, p.sigma, scr, lds, ilds, &sw);
+    else if (N <= 128)
+      core_svd<2>(cs, d, p.sigma, scr, lds, ilds, &sw);
+    else
+      core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw);
+    sweeps_tot += sw;
+    if (scr[OFF_TH + d - 1] <= 1e-10 * scr[OFF_TH]) {
+      complete_basis(d, d + cs.rhoB, d + cs.rhoC, scr);
+      __syncthreads();
+    }
+    // ---- Step 3: rotations and row corrections
+    solve_Y(0, d, k, cs.rhoB, permB, scr + OFF_LB, scr, lds);
+    solve_Y(1, d, k, cs.rhoC, permC, scr + OFF_LC, scr, lds);
+    build_F_and_delta(cs, 0, d, scr, lds);
+    build_F_and_delta(cs, 1, d, scr, lds);
+    mul_PF(d, Pc, scr + OFF_FU, Pn, lds);
+    mul_PF(d, Pc + d * d, scr + OFF_FV, Pn + d * d, lds);
+    numeric |= lu_solve_scatter(d, Pn, scr + OFF_DU, cs.S1, cs.s1, p.Ub, p.R, lds, ilds);
+    numeric |= lu_solve_scatter(d, Pn + d * d, scr + OFF_DV, cs.S2, cs.s2, p.Vb, nullptr, lds,
+                                ilds);
+    for (int c = tid(); c < d; c += NT) p.sigma[c] = scr[OFF_TH + c];
+    double *t = Pc;
+    Pc = Pn;
+    Pn = t;
+    __syncthreads();
+  }
+  // current projections back into p.P
+  if (Pc != p.P) {
+    for (int e = tid(); e < 2 * d * d; e += NT) p.P[e] = Pc[e];
+  }
+  if (tid() == 0) {
+    ChainStats st;
+    st.max_core = max_core;
+    st.dropped = dropped;
+    st.sweeps = sweeps_tot;
+    st.numeric_error = numeric;
+    *p.stats = st;
+  }
+}
+
+}  // namespace
+
+size_t chain_scratch_doubles() { return SCRATCH_DOUBLES; }
+
+hipError_t launch_chain(damf_ctx *c, int n_chunks) {
+  if (n_chunks <= 0) return hipSuccess;
+  ChainParams p;
+  p.d = c->d;
+  p.n = c->n;
+  p.chunks = c->ws.chunks;
+  p.n_chunks = n_chunks;
+  p.S1 = c->ws.chunk_s1;
+  p.S2 = c->ws.chunk_s2;
+  p.ent = c->ws.chunk_ent;
+  p.Ub = c->Ub;
+  p.Vb = c->Vb;
+  p.R = c->ppr_on ? c->R : nullptr;
+  p.P = c->P;
+  p.Pnext = c->Pnext;
+  p.sigma = c->sigma;
+  p.scr = c->ws.scratch;
+  p.tau = c->cfg.tau;
+  p.stats = c->ws.cstats;
+  chain_kernel<<<1, NT, 0, c->stream>>>(p);
+  return hipGetLastError();
+}
+
+}  // namespace damf

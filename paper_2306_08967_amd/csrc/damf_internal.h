@@ -1,0 +1,167 @@
+// damf_internal.h -- device state and kernel entry points shared by the
+// library's translation units.  Not part of the public ABI (include/damf.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/damf.h"
+
+namespace damf {
+
+constexpr int kMaxBatch = 8192;     // ops per damf_update call (sorted in LDS)
+constexpr int kMaxCore = 192;       // d + chunk rank <= kMaxCore (Jacobi in VGPRs)
+constexpr int kMaxD = 128;          // embedding width
+constexpr int kMaxSide = 64;        // |S1|, |S2| per chunk
+constexpr int kChainThreads = 1024; // one workgroup (16 waves) runs Steps 1-3
+
+// Dynamic CSR with per-row slack.  Row u occupies col[start[u] .. start[u] +
+// len[u]) in ascending order; cap[u] >= len[u] entries are reserved there.
+// Rows that outgrow their reservation move to fresh space taken from the pool
+// by a device-side bump pointer (*top).
+struct Csr {
+  int64_t *start = nullptr;
+  int32_t *len = nullptr;
+  int32_t *cap = nullptr;
+  int32_t *col = nullptr;
+  int64_t pool_cap = 0;
+  int64_t *top = nullptr;  // device counter: first free pool entry
+};
+
+// One net edit of A (after set semantics), sorted by (row, col).
+struct NetEntry {
+  int32_t row, col;
+  int32_t delta;  // +1 / -1
+  int32_t pad;
+};
+
+// Chunk descriptor (Sec. 4.3 with B, C of several columns): rows S1 and
+// columns S2 as index ranges into the chunk lists, entries as a range of
+// NetEntry.
+struct ChunkDesc {
+  int32_t s1_off, s1, s2_off, s2;
+  int32_t e_off, ne;
+  int32_t pad0, pad1;
+};
+
+// Written by the batch-preparation kernel, read back by the host.
+struct BatchHeader {
+  int32_t bad_ops;        // ops with an id out of range or op not +1/-1
+  int32_t n_net;          // net entries (both orientations for undirected)
+  int32_t n_chunks;
+  int32_t n_rows_out;     // distinct rows touched in A
+  int32_t n_rows_in;      // distinct rows touched in A^T
+  int32_t max_s;          // largest |S1| or |S2|
+  int32_t pool_overflow;  // CSR rows that found no pool space (set by edits)
+  int32_t pad;
+};
+
+// Per-chunk results written by the chain kernel (for batch info).
+struct ChainStats {
+  int32_t max_core;
+  int32_t dropped;
+  int32_t sweeps;
+  int32_t numeric_error;
+};
+
+struct Workspace {
+  // batch preparation
+  int32_t *ops_src = nullptr, *ops_dst = nullptr;
+  int8_t *ops_op = nullptr;
+  uint64_t *units = nullptr;     // canonical edit units of the batch
+  NetEntry *chunk_ent = nullptr; // entries of each chunk, chunk after chunk
+  NetEntry *net = nullptr;       // sorted by (row, col)
+  NetEntry *net_t = nullptr;     // same entries sorted by (col, row)
+  int32_t *rows_out = nullptr;   // distinct rows of net (CSR edit list)
+  int32_t *rowpos_out = nullptr; // start of each row's run in net (+1 sentinel)
+  int32_t *rows_in = nullptr;
+  int32_t *rowpos_in = nullptr;
+  ChunkDesc *chunks = nullptr;
+  int32_t *chunk_s1 = nullptr;   // concatenated sorted S1 lists
+  int32_t *chunk_s2 = nullptr;
+  BatchHeader *hdr = nullptr;    // device
+  BatchHeader *hdr_host = nullptr;  // pinned
+  ChainStats *cstats = nullptr;
+  ChainStats *cstats_host = nullptr;
+  // chain kernel scratch (float64, L2 resident)
+  double *scratch = nullptr;
+  size_t scratch_doubles = 0;
+  // PPR push
+  int32_t *stamp = nullptr;      // per node: last round it was queued
+  int32_t *cand = nullptr;       // candidate list (n)
+  int32_t *cand2 = nullptr;      // next round's candidates (n)
+  int32_t *frontier = nullptr;   // frontier list (n)
+  int64_t *counters = nullptr;   // device counters (cand, frontier, edges, ...)
+  int64_t *counters_host = nullptr;
+  double *dscratch_host = nullptr;
+};
+
+}  // namespace damf
+
+struct damf_ctx {
+  damf_config cfg{};
+  int64_t n = 0;
+  int d = 0;
+  hipStream_t stream = nullptr;
+  bool own_stream = false;
+  int device = 0;
+  bool poisoned = false;
+  std::string err;
+  damf::Csr out, in;
+  float *Ub = nullptr, *Vb = nullptr, *Zb = nullptr, *R = nullptr;
+  double *P = nullptr;     // [P_U | P_V] (2 d x d, row-major)
+  double *Pnext = nullptr; // double buffer for the chain kernel
+  double *sigma = nullptr; // d
+  damf::Workspace ws;
+  int64_t round_counter = 0;
+  bool ppr_on = true;
+  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+};
+
+namespace damf {
+
+// ---- graph.hip
+hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows,
+                     const int32_t *d_cols, int64_t m, double slack);
+hipError_t csr_free(Csr &g);
+hipError_t csr_export(damf_ctx *c, const Csr &g, int64_t *h_indptr,
+                      int32_t *h_indices, int64_t *m_out);
+hipError_t launch_validate_edges(const int32_t *src, const int32_t *dst,
+                                 int64_t m, int64_t n, int32_t *bad,
+                                 hipStream_t s);
+hipError_t launch_batch_prepare(damf_ctx *c, int k);
+hipError_t launch_csr_edit(damf_ctx *c, Csr &g, const NetEntry *net,
+                           const int32_t *rows, const int32_t *rowpos,
+                           int nrows, bool transposed);
+
+// ---- chain.hip
+hipError_t launch_chain(damf_ctx *c, int n_chunks);
+
+// ---- ppr.hip
+hipError_t ppr_init(damf_ctx *c);
+hipError_t ppr_fixup(damf_ctx *c, int n_rows);
+hipError_t ppr_push(damf_ctx *c, const int32_t *first_rows, int64_t nfirst,
+                    int64_t *rounds, int64_t *pushes, int64_t *edges);
+hipError_t ppr_residual_max(damf_ctx *c, double *out);
+
+// ---- rsvd.hip
+hipError_t rsvd_init(damf_ctx *c);
+hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B,
+                     int d, float *C, int ldc, hipStream_t s);
+hipError_t tsqr_public(float *A, int64_t m, int l, int ld, float *Rtop,
+                       hipStream_t s);
+
+// ---- query.hip
+hipError_t launch_query(damf_ctx *c, int which, int64_t q,
+                        const int32_t *d_nodes, float *d_out);
+
+}  // namespace damf
+
+#define DAMF_HIP(expr)                              \
+  do {                                              \
+    hipError_t _e = (expr);                         \
+    if (_e != hipSuccess) return _e;                \
+  } while (0)

@@ -1,0 +1,526 @@
+// rsvd.hip -- initial factorisation (Appendix A, Algorithm 3): randomized
+// rank-d t-SVD of A with oversampling p and q power iterations, as cited by
+// the paper (Halko, Martinsson, Tropp) for its O(n d^2 + m d) cost:
+//
+//   Omega[i, j] = +/-1 from SplitMix64,  Y = A Omega,  Q = qr(Y)
+//   q times:  Q = qr(A^T Q),  Q = qr(A Q)
+//   B^T = A^T Q = Q2 R2,   svd(R2^T) = Ut S Vt^T,
+//   U = Q Ut[:, :d],  V = Q2 Vt[:, :d],  Sigma = S[:d]
+//
+// Kernels: sketch generation, CSR SpMM of width l = d + p, tall-skinny
+// Householder QR (recursive TSQR over blocks of 256 rows), an FP64 one-sided
+// Jacobi SVD of the l x l factor in one workgroup, and the n x l by l x d
+// rotation GEMM on MFMA (FP32 in, FP32 accumulate).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "common.h"
+#include "damf_internal.h"
+#include "jacobi.h"
+
+namespace damf {
+
+namespace {
+
+// ---------------------------------------------------------------- sketch
+
+__device__ __forceinline__ uint64_t splitmix64_out(uint64_t state) {
+  // output of SplitMix64 whose state before the call is `state`
+  uint64_t z = state + 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  return z ^ (z >> 31);
+}
+
+__global__ void sketch_kernel(float *Om, int64_t n, int l, int ld, uint64_t seed) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * l) return;
+  const int64_t i = e / l;
+  const int j = (int)(e - i * l);
+  const uint64_t ctr = (seed << 40) ^ ((uint64_t)i * (uint64_t)l + (uint64_t)j);
+  Om[i * ld + j] = (splitmix64_out(ctr) >> 63) ? -1.f : 1.f;
+}
+
+// ---------------------------------------------------------------- SpMM
+// Y[u][0..l) = sum over the CSR row u of X[v][0..l); one wave per row, lanes
+// own columns lane, lane + 64, lane + 128.
+__global__ __launch_bounds__(256) void spmm_kernel(Csr g, const float *__restrict__ X,
+                                                   float *__restrict__ Y, int64_t n, int l,
+                                                   int ld) {
+  const int lane = threadIdx.x & 63;
+  const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+  if (u >= n) return;
+  const int32_t L = g.len[u];
+  const int32_t *row = g.col + g.start[u];
+  const bool c0 = lane < l, c1 = lane + 64 < l, c2 = lane + 128 < l;
+  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
+  int32_t e = 0;
+  for (; e + 2 <= L; e += 2) {
+    const int64_t v0 = row[e], v1 = row[e + 1];
+    if (c0) a0 += X[v0 * ld + lane] + X[v1 * ld + lane];
+    if (c1) a1 += X[v0 * ld + lane + 64] + X[v1 * ld + lane + 64];
+    if (c2) a2 += X[v0 * ld + lane + 128] + X[v1 * ld + lane + 128];
+  }
+  for (; e < L; ++e) {
+    const int64_t v = row[e];
+    if (c0) a0 += X[v * ld + lane];
+    if (c1) a1 += X[v * ld + lane + 64];
+    if (c2) a2 += X[v * ld + lane + 128];
+  }
+  if (c0) Y[u * ld + lane] = a0;
+  if (c1) Y[u * ld + lane + 64] = a1;
+  if (c2) Y[u * ld + lane + 128] = a2;
+}
+
+// ---------------------------------------------------------------- TSQR
+// Block of TB = 256 rows; the l <= 192 columns are spread over the 16 waves
+// (column c lives in wave c % 16, slot c / 16); lane holds rows lane + 64 r.
+
+constexpr int TB = 256;
+constexpr int TNT = 1024;
+constexpr int TW = 16;
+constexpr int TCOLS = 12;  // ceil(192 / 16)
+constexpr int TRPL = TB / 64;
+
+// Householder reflector of x (rows >= j of one column held by a wave):
+// beta = -sign(x_j) ||x||, v = (x - beta e_j) / (x_j - beta), tau = (beta - x_j) / beta.
+// Writes v (v_j = 1, zeros above) to vbuf and tau to *tau_out; returns beta.
+__device__ float house(float (&x)[TRPL], int j, int rows, float *vbuf, float *tau_out) {
+  const int lane = threadIdx.x & 63;
+  float s2 = 0.f, xj = 0.f;
+#pragma unroll
+  for (int r = 0; r < TRPL; ++r) {
+    const int i = r * 64 + lane;
+    if (i > j && i < rows) s2 = fmaf(x[r], x[r], s2);
+    if (i == j) xj = x[r];
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) {
+    s2 += __shfl_xor(s2, off, 64);
+    xj += __shfl_xor(xj, off, 64);
+  }
+  float beta, tau, scale;
+  if (s2 == 0.f) {
+    beta = xj;
+    tau = 0.f;
+    scale = 0.f;
+  } else {
+    const float nrm = sqrtf(xj * xj + s2);
+    beta = (xj >= 0.f) ? -nrm : nrm;
+    tau = (beta - xj) / beta;
+    scale = 1.f / (xj - beta);
+  }
+#pragma unroll
+  for (int r = 0; r < TRPL; ++r) {
+    const int i = r * 64 + lane;
+    float v = 0.f;
+    if (i == j) v = 1.f;
+    else if (i > j && i < rows) v = x[r] * scale;
+    vbuf[i] = v;
+  }
+  if (lane == 0) *tau_out = tau;
+  return beta;
+}
+
+// Factor one block: V (reflectors) overwrites the block in place, tau[l] per
+// block, R (l x l, upper) written to S rows [blk * l, (blk + 1) * l).
+__global__ __launch_bounds__(TNT) void tsqr_factor_kernel(float *A, int64_t m, int l, int ld,
+                                                          float *tau_all, float *S) {
+  __shared__ float vbuf[2][TB];
+  __shared__ float taus[2];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = (int64_t)blockIdx.x * TB;
+  const int rows = (int)min<int64_t>(TB, m - r0);
+  float x[TCOLS][TRPL];
+#pragma unroll
+  for (int s = 0; s < TCOLS; ++s) {
+    const int c = s * TW + w;
+#pragma unroll
+    for (int r = 0; r < TRPL; ++r) {
+      const int i = r * 64 + lane;
+      x[s][r] = (c < l && i < rows) ? A[(r0 + i) * ld + c] : 0.f;
+    }
+  }
+  for (int j = 0; j < l; ++j) {
+    const int par = j & 1;
+    const int owner = j % TW, slot = j / TW;
+    if (w == owner) {
+#pragma unroll
+      for (int s = 0; s < TCOLS; ++s) {
+        if (s == slot) {
+          const float beta = house(x[s], j, TB, vbuf[par], &taus[par]);
+          // the column becomes (beta at row j, v below): keep v below j, R above
+#pragma unroll
+          for (int r = 0; r < TRPL; ++r) {
+            const int i = r * 64 + lane;
+            if (i == j) x[s][r] = beta;
+            else if (i > j) x[s][r] = vbuf[par][i];
+          }
+        }
+      }
+    }
+    __syncthreads();
+    const float tau = taus[par];
+    if (tau != 0.f) {
+#pragma unroll
+      for (int s = 0; s < TCOLS; ++s) {
+        const int c = s * TW + w;
+        if (c > j && c < l) {
+          float p = 0.f;
+#pragma unroll
+          for (int r = 0; r < TRPL; ++r) p = fmaf(vbuf[par][r * 64 + lane], x[s][r], p);
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off, 64);
+          const float tw = tau * p;
+#pragma unroll
+          for (int r = 0; r < TRPL; ++r) x[s][r] = fmaf(-tw, vbuf[par][r * 64 + lane], x[s][r]);
+        }
+      }
+    }
+    if (threadIdx.x == 0) tau_all[(int64_t)blockIdx.x * l + j] = tau;
+  }
+  // write back: reflectors below the diagonal, R to S
+#pragma unroll
+  for (int s = 0; s < TCOLS; ++s) {
+    const int c = s * TW + w;
+    if (c < l) {
+#pragma unroll
+      for (int r = 0; r < TRPL; ++r) {
+        const int i = r * 64 + lane;
+        if (i < rows) A[(r0 + i) * ld + c] = x[s][r];
+        if (i < l) S[((int64_t)blockIdx.x * l + i) * l + c] = (i <= c) ? x[s][r] : 0.f;
+      }
+    }
+  }
+}
+
+// Form the explicit Q of one block: X = [C; 0] with C the block's l x l slab
+// of the next level's Q (or I at the top), then X <- H_0 ... H_{l-1} X.
+// Overwrites the block (which held the reflectors) with Q.
+__global__ __launch_bounds__(TNT) void tsqr_formq_kernel(float *A, int64_t m, int l, int ld,
+                                                         const float *tau_all, const float *QS) {
+  __shared__ float vb[2][TB];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  const int64_t r0 = (int64_t)blockIdx.x * TB;
+  const int rows = (int)min<int64_t>(TB, m - r0);
+  float x[TCOLS][TRPL];
+#pragma unroll
+  for (int s = 0; s < TCOLS; ++s) {
+    const int c = s * TW + w;
+#pragma unroll
+    for (int r = 0; r < TRPL; ++r) {
+      const int i = r * 64 + lane;
+      float v = 0.f;
+      if (c < l && i < l) v = QS ? QS[((int64_t)blockIdx.x * l + i) * l + c] : (i == c ? 1.f : 0.f);
+      x[s][r] = v;
+    }
+  }
+  for (int j = l - 1; j >= 0; --j) {
+    const int par = j & 1;
+    for (int i = threadIdx.x; i < TB; i += TNT) {
+      float v = 0.f;
+      if (i == j) v = 1.f;
+      else if (i > j && i < rows) v = A[(r0 + i) * ld + j];
+      vb[par][i] = v;
+    }
+    __syncthreads();
+    const float tau = tau_all[(int64_t)blockIdx.x * l + j];
+    if (tau != 0.f) {
+#pragma unroll
+      for (int s = 0; s < TCOLS; ++s) {
+        const int c = s * TW + w;
+        if (c < l) {
+          float p = 0.f;
+#pragma unroll
+          for (int r = 0; r < TRPL; ++r) p = fmaf(vb[par][r * 64 + lane], x[s][r], p);
+#pragma unroll
+          for (int off = 32; off >= 1; off >>= 1) p += __shfl_xor(p, off, 64);
+          const float tw = tau * p;
+#pragma unroll
+          for (int r = 0; r < TRPL; ++r) x[s][r] = fmaf(-tw, vb[par][r * 64 + lane], x[s][r]);
+        }
+      }
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int s = 0; s < TCOLS; ++s) {
+    const int c = s * TW + w;
+    if (c < l) {
+#pragma unroll
+      for (int r = 0; r < TRPL; ++r) {
+        const int i = r * 64 + lane;
+        if (i < rows) A[(r0 + i) * ld + c] = x[s][r];
+      }
+    }
+  }
+}
+
+// ---------------------------------------------------------------- small SVD
+// FP64 one-sided Jacobi SVD of M (l x l, row-major FP32 upper-triangular R
+// given; the kernel factors M = R^T).  Outputs the top d left vectors E
+// (l x d), singular values and right vectors H = M^T E Theta^-1 (l x d),
+// all float64, row-major.
+__global__ __launch_bounds__(1024) void small_svd_kernel(const float *Rtop, int l, int d,
+                                                         double *E, double *theta, double *H) {
+  constexpr int RPL = 3, NW = 16;
+  using SH = JacobiShape<RPL, NW>;
+  constexpr int NP = SH::NP, CPW = SH::CPW;
+  __shared__ double lds[SH::LDS];
+  __shared__ double sv[256];
+  __shared__ int sid[256], rank_of[256];
+  __shared__ int flag;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  JacobiRegs<RPL, NW> J;
+  // M = R^T: M[i][j] = R[j][i]
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = jacobi_slot_col<RPL, NW>(w, c);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const int i = r * 64 + lane;
+      J.a[c][r] = (i < l && j < l) ? (double)Rtop[j * l + i] : 0.0;
+    }
+  }
+  jacobi_sweeps<RPL, NW>(J, lds, &flag, 60, 1e-14);
+  const double *nrm = lds + 4 * NW * SH::SLOT;
+  for (int j = threadIdx.x; j < 256; j += 1024) {
+    sv[j] = (j < NP) ? sqrt(nrm[j]) : -1.0;
+    sid[j] = j;
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= 256; kk <<= 1) {
+    for (int jj = kk >> 1; jj > 0; jj >>= 1) {
+      if (threadIdx.x < 256) {
+        int i = threadIdx.x, q = i ^ jj;
+        if (q > i) {
+          double a = sv[i], b = sv[q];
+          int ia = sid[i], ib = sid[q];
+          bool before = (a > b) || (a == b && ia < ib);
+          bool up = (i & kk) == 0;
+          if (before != up) {
+            sv[i] = b;
+            sv[q] = a;
+            sid[i] = ib;
+            sid[q] = ia;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (threadIdx.x < NP) rank_of[sid[threadIdx.x]] = threadIdx.x;
+  if (threadIdx.x < d) theta[threadIdx.x] = sv[threadIdx.x];
+  __syncthreads();
+  const double cut = 1e-12 * sv[0];
+#pragma unroll
+  for (int c = 0; c < CPW; ++c) {
+    const int j = jacobi_slot_col<RPL, NW>(w, c);
+    const int rk = rank_of[j];
+    if (rk < d) {
+      const double inv = (sv[rk] > cut) ? 1.0 / sv[rk] : 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) {
+        const int i = r * 64 + lane;
+        if (i < l) E[i * d + rk] = J.a[c][r] * inv;
+      }
+    }
+  }
+  __syncthreads();
+  // H[j][c] = sum_i M[i][j] E[i][c] / theta_c = sum_i R[j][i] E[i][c] / theta_c
+  for (int e = threadIdx.x; e < l * d; e += 1024) {
+    const int j = e / d, c = e - j * d;
+    double acc = 0.0;
+    for (int i = 0; i < l; ++i) acc = fma((double)Rtop[j * l + i], E[i * d + c], acc);
+    H[j * d + c] = (sv[c] > cut) ? acc / sv[c] : 0.0;
+  }
+}
+
+// ---------------------------------------------------------------- GEMM
+// C (n x d, ldc) = A (n x l, lda) * B (l x d, row-major, FP32) on MFMA
+// (v_mfma_f32_16x16x4f32).  Workgroup: 64 rows x 128 cols; 4 waves, each 16
+// rows x 128 cols = 8 MFMA tiles.  A and B tiles staged in LDS.
+constexpr int GM = 64;
+constexpr int GK = 16;
+
+typedef float v4f __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gemm_tall_kernel(const float *__restrict__ A, int64_t n,
+                                                        int l, int lda,
+                                                        const float *__restrict__ B, int d,
+                                                        float *__restrict__ C, int ldc) {
+  __shared__ float As[GM][GK + 1];
+  __shared__ float Bs[GK][128 + 4];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * GM;
+  v4f acc[8];
+#pragma unroll
+  for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < l; k0 += GK) {
+    for (int e = threadIdx.x; e < GM * GK; e += 256) {
+      const int i = e / GK, k = e - i * GK;
+      const int64_t r = row0 + i;
+      As[i][k] = (r < n && k0 + k < l) ? A[r * lda + k0 + k] : 0.f;
+    }
+    for (int e = threadIdx.x; e < GK * 128; e += 256) {
+      const int k = e >> 7, j = e & 127;
+      Bs[k][j] = (k0 + k < l && j < d) ? B[(k0 + k) * d + j] : 0.f;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < GK; kk += 4) {
+      const float a = As[w * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+      for (int t = 0; t < 8; ++t) {
+        const float b = Bs[kk + (lane >> 4)][t * 16 + (lane & 15)];
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int t = 0; t < 8; ++t) {
+    const int j = t * 16 + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = row0 + w * 16 + (lane >> 4) * 4 + q;
+      if (r < n && j < d) C[r * ldc + j] = acc[t][q];
+    }
+  }
+}
+
+__global__ void to_float_kernel(const double *x, float *y, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) y[i] = (float)x[i];
+}
+
+// ---------------------------------------------------------------- driver
+
+struct Tsqr {
+  std::vector<float *> S;    // stacked R per level
+  std::vector<float *> tau;  // per level
+  std::vector<int64_t> m;    // rows per level
+};
+
+// In-place QR of A (m x l): A <- Q.  Rtop receives the final R (l x l).
+hipError_t tsqr(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) {
+  // levels: level 0 is A itself
+  std::vector<float *> mats{A};
+  std::vector<int64_t> rows{m};
+  std::vector<int> lds{ld};
+  std::vector<float *> taus;
+  hipError_t err = hipSuccess;
+  while (true) {
+    const int64_t mm = rows.back();
+    const int64_t nb = (mm + TB - 1) / TB;
+    float *tau = nullptr, *S = nullptr;
+    if ((err = hipMalloc(&tau, nb * l * sizeof(float))) != hipSuccess) break;
+    if ((err = hipMalloc(&S, nb * l * (int64_t)l * sizeof(float))) != hipSuccess) break;
+    taus.push_back(tau);
+    tsqr_factor_kernel<<<(unsigned)nb, TNT, 0, s>>>(mats.back(), mm, l, lds.back(), tau, S);
+    if ((err = hipGetLastError()) != hipSuccess) break;
+    if (nb == 1) {
+      // S holds the final R
+      err = hipMemcpyAsync(Rtop, S, (size_t)l * l * sizeof(float), hipMemcpyDeviceToDevice, s);
+      (void)hipStreamSynchronize(s);
+      (void)hipFree(S);
+      break;
+    }
+    mats.push_back(S);
+    rows.push_back(nb * l);
+    lds.push_back(l);
+  }
+  if (err == hipSuccess) {
+    // form Q top-down: level L-1 from I, then each lower level from the next
+    const int levels = (int)mats.size();
+    for (int lev = levels - 1; lev >= 0; --lev) {
+      const int64_t mm = rows[lev];
+      const int64_t nb = (mm + TB - 1) / TB;
+      const float *QS = (lev == levels - 1) ? nullptr : mats[lev + 1];
+      tsqr_formq_kernel<<<(unsigned)nb, TNT, 0, s>>>(mats[lev], mm, l, lds[lev], taus[lev], QS);
+      if ((err = hipGetLastError()) != hipSuccess) break;
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  for (size_t i = 1; i < mats.size(); ++i) (void)hipFree(mats[i]);
+  for (float *t : taus) (void)hipFree(t);
+  return err;
+}
+
+hipError_t spmm(const Csr &g, const float *X, float *Y, int64_t n, int l, int ld, hipStream_t s) {
+  spmm_kernel<<<ceil_div(n, 4), 256, 0, s>>>(g, X, Y, n, l, ld);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B, int d, float *C,
+                     int ldc, hipStream_t s) {
+  gemm_tall_kernel<<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+  return hipGetLastError();
+}
+
+hipError_t tsqr_public(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) {
+  return tsqr(A, m, l, ld, Rtop, s);
+}
+
+hipError_t rsvd_init(damf_ctx *c) {
+  hipStream_t s = c->stream;
+  const int64_t n = c->n;
+  const int d = c->d;
+  const int l = d + c->cfg.oversample;
+  const int ld = l;
+  float *Y = nullptr, *T = nullptr, *Rt = nullptr, *Ef = nullptr, *Hf = nullptr;
+  double *E = nullptr, *H = nullptr, *th = nullptr;
+  DAMF_HIP(hipMalloc(&Y, (size_t)n * ld * sizeof(float)));
+  DAMF_HIP(hipMalloc(&T, (size_t)n * ld * sizeof(float)));
+  DAMF_HIP(hipMalloc(&Rt, (size_t)l * l * sizeof(float)));
+  DAMF_HIP(hipMalloc(&E, (size_t)l * d * sizeof(double)));
+  DAMF_HIP(hipMalloc(&H, (size_t)l * d * sizeof(double)));
+  DAMF_HIP(hipMalloc(&th, (size_t)kMaxCore * sizeof(double)));
+  DAMF_HIP(hipMalloc(&Ef, (size_t)l * d * sizeof(float)));
+  DAMF_HIP(hipMalloc(&Hf, (size_t)l * d * sizeof(float)));
+  sketch_kernel<<<ceil_div(n * l, 256), 256, 0, s>>>(T, n, l, ld, c->cfg.seed);
+  DAMF_HIP(hipGetLastError());
+  DAMF_HIP(spmm(c->out, T, Y, n, l, ld, s));  // Y = A Omega
+  DAMF_HIP(tsqr(Y, n, l, ld, Rt, s));
+  for (int it = 0; it < c->cfg.power_iters; ++it) {
+    DAMF_HIP(spmm(c->in, Y, T, n, l, ld, s));  // A^T Q
+    DAMF_HIP(tsqr(T, n, l, ld, Rt, s));
+    DAMF_HIP(spmm(c->out, T, Y, n, l, ld, s));  // A Q
+    DAMF_HIP(tsqr(Y, n, l, ld, Rt, s));
+  }
+  DAMF_HIP(spmm(c->in, Y, T, n, l, ld, s));  // B^T = A^T Q
+  DAMF_HIP(tsqr(T, n, l, ld, Rt, s));        // T = Q2, Rt = R2
+  small_svd_kernel<<<1, 1024, 0, s>>>(Rt, l, d, E, th, H);
+  DAMF_HIP(hipGetLastError());
+  to_float_kernel<<<ceil_div((int64_t)l * d, 256), 256, 0, s>>>(E, Ef, (int64_t)l * d);
+  to_float_kernel<<<ceil_div((int64_t)l * d, 256), 256, 0, s>>>(H, Hf, (int64_t)l * d);
+  DAMF_HIP(gemm_tall(Y, n, l, ld, Ef, d, c->Ub, d, s));  // U = Q Ut_d
+  DAMF_HIP(gemm_tall(T, n, l, ld, Hf, d, c->Vb, d, s));  // V = Q2 Vt_d
+  // projections = I, Sigma
+  std::vector<double> P(2 * (size_t)d * d, 0.0);
+  for (int sd = 0; sd < 2; ++sd)
+    for (int i = 0; i < d; ++i) P[sd * d * d + i * d + i] = 1.0;
+  DAMF_HIP(hipMemcpyAsync(c->P, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  DAMF_HIP(hipMemsetAsync(c->sigma, 0, kMaxCore * sizeof(double), s));
+  DAMF_HIP(hipMemcpyAsync(c->sigma, th, d * sizeof(double), hipMemcpyDeviceToDevice, s));
+  DAMF_HIP(hipStreamSynchronize(s));
+  (void)hipFree(Y);
+  (void)hipFree(T);
+  (void)hipFree(Rt);
+  (void)hipFree(E);
+  (void)hipFree(H);
+  (void)hipFree(th);
+  (void)hipFree(Ef);
+  (void)hipFree(Hf);
+  return hipSuccess;
+}
+
+}  // namespace damf

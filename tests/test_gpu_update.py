@@ -1,0 +1,158 @@
+"""GPU parity of the update path (Steps 1-3) and the graph store against the FP64 oracle.
+
+Tolerances (stated here, derived in the design notes): singular values within
+1e-5 * sigma_1; embedding product X Y^T within 1e-5 relative Frobenius error;
+canonical CSR of A and A^T bit-exact; U = X Sigma^(-1/2) orthonormal to 1e-5.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+from oracle.graph import EdgeSet
+from oracle.model import DAMFOracle
+from tests._checks import orth_err, product_rel_err, unit_factor
+from workloads import c1_workload, er_undirected
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def damf():
+    import torch
+    assert torch.cuda.is_available()
+    import paper_2306_08967_amd as P
+    P.lib()
+    return P
+
+
+def _ctx_from_oracle(P, orc, init, **kw):
+    cfg = P.default_config(orc.n, orc.d, directed=orc.directed, alpha=1.0,
+                           max_core_rank=orc.r, max_side=orc.r_max, tau=orc.tau, **kw)
+    return P.Context.init_factors(cfg, init[0], init[1], orc.U, orc.s, orc.V)
+
+
+def _assert_csr(ctx, orc):
+    for t in (False, True):
+        ip, ix = ctx.export_csr(transpose=t)
+        rp, rx = orc.graph.csr(transpose=t)
+        assert np.array_equal(ip, rp), f"indptr transpose={t}"
+        assert np.array_equal(ix, rx), f"indices transpose={t}"
+
+
+@pytest.mark.parametrize("directed", [True, False])
+def test_csr_edits_bit_exact(damf, directed):
+    _say(f"case csr_edits directed={directed}")
+    rng = np.random.default_rng(3)
+    n, d = 50, 6
+    s0, t0 = rng.integers(0, n, 200), rng.integers(0, n, 200)
+    orc = DAMFOracle(n, d, directed, alpha=1.0, r=4, r_max=8, tau=1e-6).init_exact(s0, t0)
+    ctx = _ctx_from_oracle(damf, orc, (s0, t0))
+    _assert_csr(ctx, orc)
+    for b in range(12):
+        k = int(rng.integers(1, 40))
+        s, t = rng.integers(0, n, k), rng.integers(0, n, k)
+        op = rng.choice(np.array([-1, 1], dtype=np.int8), k)
+        info_o = orc.update(s, t, op)
+        info = ctx.update(s, t, op)
+        assert info["net_entries"] == len(info_o["net"])
+        assert info["chunks"] == len(info_o["chunks"])
+        _assert_csr(ctx, orc)
+    sg = ctx.singular_values()
+    assert np.max(np.abs(sg - orc.s)) <= 1e-5 * orc.s[0]
+    ctx.close()
+
+
+def test_small_update_parity(damf):
+    _say("case small_update_parity")
+    rng = np.random.default_rng(5)
+    n, d = 80, 8
+    s0, t0 = rng.integers(0, n, 400), rng.integers(0, n, 400)
+    orc = DAMFOracle(n, d, True, alpha=1.0, r=4, r_max=8, tau=1e-6).init_exact(s0, t0)
+    ctx = _ctx_from_oracle(damf, orc, (s0, t0))
+    for b in range(10):
+        k = 12
+        s, t = rng.integers(0, n, k), rng.integers(0, n, k)
+        op = rng.choice(np.array([-1, 1], dtype=np.int8), k)
+        orc.update(s, t, op)
+        ctx.update(s, t, op)
+        sg = ctx.singular_values()
+        X, Y = ctx.query("X"), ctx.query("Y")
+        err_s = np.max(np.abs(sg - orc.s)) / orc.s[0]
+        err_p = product_rel_err(X, Y, orc.X(), orc.Y())
+        _say(f"  batch {b}: sigma err {err_s:.2e} product err {err_p:.2e}")
+        assert err_s <= 1e-5 and err_p <= 1e-5
+    ctx.close()
+
+
+def test_c1_parity(damf):
+    """C1: undirected G(2000, 20000), d = 32, exact init on 90%, 200 batches of 10 inserts."""
+    _say("case c1_parity")
+    w = c1_workload()
+    orc = DAMFOracle(w["n"], w["d"], False, alpha=1.0, r=32, r_max=64, tau=1e-6).init_exact(*w["init"])
+    ctx = _ctx_from_oracle(damf, orc, w["init"])
+    for b, (s, t, op) in enumerate(w["stream"]):
+        orc.update(s, t, op)
+        ctx.update(s, t, op)
+        if b % 50 == 49:
+            sg = ctx.singular_values()
+            X, Y = ctx.query("X"), ctx.query("Y")
+            err_s = np.max(np.abs(sg - orc.s)) / orc.s[0]
+            err_p = product_rel_err(X, Y, orc.X(), orc.Y())
+            eo = max(orth_err(unit_factor(X, sg)), orth_err(unit_factor(Y, sg)))
+            _say(f"  batch {b}: sigma err {err_s:.2e} product err {err_p:.2e} orth {eo:.2e}")
+            assert err_s <= 1e-5 and err_p <= 1e-5 and eo <= 1e-5
+    _assert_csr(ctx, orc)
+    ctx.close()
+
+
+def test_exact_when_d_at_least_n(damf):
+    _say("case exact_d_ge_n")
+    rng = np.random.default_rng(11)
+    n = 24
+    s0, t0 = rng.integers(0, n, 80), rng.integers(0, n, 80)
+    orc = DAMFOracle(n, n, True, alpha=1.0, r=4, r_max=8, tau=1e-6).init_exact(s0, t0)
+    ctx = _ctx_from_oracle(damf, orc, (s0, t0))
+    for _ in range(8):
+        k = 6
+        s, t = rng.integers(0, n, k), rng.integers(0, n, k)
+        op = rng.choice(np.array([-1, 1], dtype=np.int8), k)
+        orc.update(s, t, op)
+        ctx.update(s, t, op)
+        X, Y = ctx.query("X"), ctx.query("Y")
+        A = orc.graph.dense()
+        assert np.abs(X.astype(np.float64) @ Y.astype(np.float64).T - A).max() <= 1e-4
+    ctx.close()
+
+
+def test_invalid_ops_leave_state_unchanged(damf):
+    _say("case invalid_ops")
+    rng = np.random.default_rng(2)
+    n, d = 40, 4
+    s0, t0 = rng.integers(0, n, 120), rng.integers(0, n, 120)
+    orc = DAMFOracle(n, d, True, alpha=1.0, r=4, r_max=8).init_exact(s0, t0)
+    ctx = _ctx_from_oracle(damf, orc, (s0, t0))
+    before = ctx.export_state()
+    csr_before = ctx.export_csr()
+    for bad in ([0, n], [-1, 3]):
+        with pytest.raises(damf.DamfError) as ei:
+            ctx.update(np.array(bad, dtype=np.int32), np.array([1, 2], dtype=np.int32),
+                       np.array([1, 1], dtype=np.int8))
+        assert ei.value.status == 2
+    with pytest.raises(damf.DamfError):
+        ctx.update(np.array([1], dtype=np.int32), np.array([2], dtype=np.int32),
+                   np.array([3], dtype=np.int8))
+    after = ctx.export_state()
+    for key in ("Ub", "Vb", "PU", "PV"):
+        assert np.array_equal(before[key], after[key])
+    csr_after = ctx.export_csr()
+    assert all(np.array_equal(a, b) for a, b in zip(csr_before, csr_after))
+    # empty batch is a no-op
+    info = ctx.update(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int8))
+    assert info["chunks"] == 0
+    ctx.close()
