@@ -82,9 +82,29 @@ typedef struct {
   int64_t pushes;         /* Step 4 node pushes                                */
   int64_t push_edges;     /* Step 4 edge traversals                            */
   double ms_prepare;      /* batch sort / net change / chunking                */
-  double ms_chain;        /* Steps 1-3 over all chunks                         */
+  double ms_chain;        /* Steps 1-3 over all chunks (with CSR edits)        */
   double ms_enhance;      /* Step 4                                            */
+  double ms_chain_kernel; /* the Steps 1-3 kernel alone (HIP events)           */
+  double chain_flops;     /* FP64 flops that kernel executed (counted model)   */
+  double ms_push_kernel;  /* Step 4 push kernels, summed over rounds          */
+  double push_bytes;      /* compulsory HBM bytes of those push kernels        */
+  int64_t sweeps;         /* Jacobi sweeps over all chunks                     */
+  double chain_phase_ms[8]; /* inside the Steps 1-3 kernel: 0 gather/project,
+                               1 Jacobi sweeps, 2 core SVD (incl. 1), 3 basis
+                               completion, 4 rotations/row corrections,
+                               5 P <- P F, 6 LU solve + scatter, 7 Grams   */
 } damf_batch_info;
+
+/* Statistics of the initialisation (damf_init / damf_init_factors). */
+typedef struct {
+  double ms_graph;        /* CSR build of A and A^T                            */
+  double ms_rsvd;         /* randomized t-SVD                                  */
+  double ms_ppr;          /* initial PPR propagation                           */
+  int64_t ppr_rounds;     /* propagation rounds (CSR SpMM passes)              */
+  double ms_spmm_kernel;  /* propagation SpMM kernels, summed                  */
+  double spmm_bytes;      /* compulsory HBM bytes of those SpMM kernels        */
+  int64_t nnz;            /* edges of A                                        */
+} damf_init_info;
 
 /* Defaults: d=128, directed, p=10, q=2, alpha=0.15, eps=1e-5, r=64,
  * r_max=64, tau=1e-6, auto_enhance=1, slack=1.25. */
@@ -143,6 +163,9 @@ damf_status damf_export_csr(damf_ctx *ctx, int32_t transpose, int64_t *indptr,
  * row-major (any may be NULL), PU, PV are d x d row-major. */
 damf_status damf_export_state(damf_ctx *ctx, double *Ub, double *Vb,
                               double *PU, double *PV, double *Zb, double *R);
+
+/* Statistics of the context's initialisation. */
+damf_status damf_get_init_info(damf_ctx *ctx, damf_init_info *info);
 
 /* Current max |R| entry (float64); <= eps after Step 4. */
 damf_status damf_residual_max(damf_ctx *ctx, double *out);

@@ -59,6 +59,29 @@ class DamfBatchInfo(C.Structure):
         ("ms_prepare", C.c_double),
         ("ms_chain", C.c_double),
         ("ms_enhance", C.c_double),
+        ("ms_chain_kernel", C.c_double),
+        ("chain_flops", C.c_double),
+        ("ms_push_kernel", C.c_double),
+        ("push_bytes", C.c_double),
+        ("sweeps", C.c_int64),
+        ("chain_phase_ms", C.c_double * 8),
+    ]
+
+    def as_dict(self):
+        out = {k: getattr(self, k) for k, _ in self._fields_}
+        out["chain_phase_ms"] = list(self.chain_phase_ms)
+        return out
+
+
+class DamfInitInfo(C.Structure):
+    _fields_ = [
+        ("ms_graph", C.c_double),
+        ("ms_rsvd", C.c_double),
+        ("ms_ppr", C.c_double),
+        ("ppr_rounds", C.c_int64),
+        ("ms_spmm_kernel", C.c_double),
+        ("spmm_bytes", C.c_double),
+        ("nnz", C.c_int64),
     ]
 
     def as_dict(self):
@@ -97,6 +120,7 @@ def lib():
     L.damf_export_csr.argtypes = [p, C.c_int32, p, p, C.POINTER(C.c_int64)]
     L.damf_export_state.argtypes = [p, p, p, p, p, p, p]
     L.damf_residual_max.argtypes = [p, C.POINTER(C.c_double)]
+    L.damf_get_init_info.argtypes = [p, C.POINTER(DamfInitInfo)]
     L.damf_sync.argtypes = [p]
     L.damf_destroy.argtypes = [p]
     L.damf_destroy.restype = None
@@ -106,7 +130,7 @@ def lib():
     L.damf_status_string.restype = C.c_char_p
     for name in ("damf_init", "damf_init_factors", "damf_update", "damf_enhance", "damf_query",
                  "damf_singular_values", "damf_export_csr", "damf_export_state",
-                 "damf_residual_max", "damf_sync"):
+                 "damf_residual_max", "damf_sync", "damf_get_init_info"):
         getattr(L, name).restype = C.c_int
     del i32p
     _lib = L
@@ -235,6 +259,11 @@ class Context:
         args = [a.ctypes.data_as(C.c_void_p) for a in (Ub, Vb, PU, PV, Zb, R)]
         self._check(lib().damf_export_state(self._h, *args))
         return dict(Ub=Ub, Vb=Vb, PU=PU, PV=PV, Zb=Zb, R=R)
+
+    def init_info(self):
+        info = DamfInitInfo()
+        self._check(lib().damf_get_init_info(self._h, C.byref(info)))
+        return info.as_dict()
 
     def residual_max(self):
         v = C.c_double()

@@ -107,6 +107,8 @@ damf_status alloc_state(damf_ctx *c) {
     API_HIP(c, hipMemsetAsync(w.stamp, 0xff, n * sizeof(int32_t), c->stream), "memset");
   }
   for (auto &e : c->ev) API_HIP(c, hipEventCreate(&e), "event");
+  API_HIP(c, hipEventCreate(&c->ev_k[0]), "event");
+  API_HIP(c, hipEventCreate(&c->ev_k[1]), "event");
   return DAMF_OK;
 }
 
@@ -128,6 +130,8 @@ void free_ctx(damf_ctx *c) {
   if (c->ws.counters_host) (void)hipHostFree(c->ws.counters_host);
   if (c->ws.dscratch_host) (void)hipHostFree(c->ws.dscratch_host);
   for (auto &e : c->ev)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &e : c->ev_k)
     if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -181,6 +185,9 @@ damf_status new_ctx(const damf_config *cfg, damf_ctx **out, damf_ctx **cptr) {
     delete c;
     return DAMF_E_DEVICE;
   }
+  int khz = 0;
+  if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
+    c->wall_khz = (double)khz;
   if (cfg->hip_stream) {
     c->stream = reinterpret_cast<hipStream_t>(cfg->hip_stream);
   } else {
@@ -299,12 +306,21 @@ damf_status damf_init(const damf_config *cfg, int64_t m, const int32_t *src, con
   damf_ctx *c = nullptr;
   damf_status st = new_ctx(cfg, out, &c);
   if (st != DAMF_OK) return st;
+  auto t0 = std::chrono::steady_clock::now();
   if ((st = alloc_state(c)) != DAMF_OK || (st = build_graph(c, m, src, dst, flags)) != DAMF_OK) {
     free_ctx(c);
     return st;
   }
+  auto t1 = std::chrono::steady_clock::now();
   hipError_t e = rsvd_init(c);
+  if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+  auto t2 = std::chrono::steady_clock::now();
   if (e == hipSuccess && c->ppr_on) e = ppr_init(c);
+  auto t3 = std::chrono::steady_clock::now();
+  c->init_info.ms_graph = std::chrono::duration<double, std::milli>(t1 - t0).count();
+  c->init_info.ms_rsvd = std::chrono::duration<double, std::milli>(t2 - t1).count();
+  c->init_info.ms_ppr = std::chrono::duration<double, std::milli>(t3 - t2).count();
+  c->init_info.nnz = m;
   if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
   if (e != hipSuccess) {
     free_ctx(c);
@@ -349,10 +365,14 @@ damf_status damf_update(damf_ctx *c, int64_t k, const int32_t *src, const int32_
     if (c->ppr_on) API_HIP(c, ppr_fixup(c, h.n_rows_out), "PPR structural fix-up");
     API_HIP(c, launch_csr_edit(c, c->out, w.net, w.rows_out, w.rowpos_out, h.n_rows_out, false), "CSR edit");
     API_HIP(c, launch_csr_edit(c, c->in, w.net_t, w.rows_in, w.rowpos_in, h.n_rows_in, true), "CSR^T edit");
+    API_HIP(c, hipEventRecord(c->ev[4], s), "event");
     API_HIP(c, launch_chain(c, h.n_chunks), "chain");
+    API_HIP(c, hipEventRecord(c->ev[5], s), "event");
   }
   API_HIP(c, hipEventRecord(c->ev[2], s), "event");
   int64_t rounds = 0, pushes = 0, edges = 0;
+  c->push_ms = 0.0;
+  c->push_bytes = 0.0;
   if (c->ppr_on && c->cfg.auto_enhance) {
     API_HIP(c, ppr_push(c, w.rows_out, h.n_rows_out, &rounds, &pushes, &edges), "PPR push");
   }
@@ -379,6 +399,13 @@ damf_status damf_update(damf_ctx *c, int64_t k, const int32_t *src, const int32_
     info->ms_prepare = ms_between(c->ev[0], c->ev[1]);
     info->ms_chain = ms_between(c->ev[1], c->ev[2]);
     info->ms_enhance = ms_between(c->ev[2], c->ev[3]);
+    info->ms_chain_kernel = h.n_net > 0 ? ms_between(c->ev[4], c->ev[5]) : 0.0;
+    info->chain_flops = h.n_net > 0 ? w.cstats_host->flops : 0.0;
+    info->ms_push_kernel = c->push_ms;
+    info->push_bytes = c->push_bytes;
+    info->sweeps = h.n_net > 0 ? w.cstats_host->sweeps : 0;
+    for (int i = 0; i < 8; ++i)
+      info->chain_phase_ms[i] = h.n_net > 0 ? (double)w.cstats_host->phase_ticks[i] / c->wall_khz : 0.0;
   }
   (void)t0;
   return DAMF_OK;
@@ -470,6 +497,12 @@ damf_status damf_export_state(damf_ctx *c, double *Ub, double *Vb, double *PU, d
   API_HIP(c, pull(c->R, R), "export R");
   if (PU) API_HIP(c, hipMemcpy(PU, c->P, (size_t)d * d * sizeof(double), hipMemcpyDeviceToHost), "export P");
   if (PV) API_HIP(c, hipMemcpy(PV, c->P + (size_t)d * d, (size_t)d * d * sizeof(double), hipMemcpyDeviceToHost), "export P");
+  return DAMF_OK;
+}
+
+damf_status damf_get_init_info(damf_ctx *c, damf_init_info *info) {
+  if (!c || !info) return DAMF_E_INVALID_ARG;
+  *info = c->init_info;
   return DAMF_OK;
 }
 

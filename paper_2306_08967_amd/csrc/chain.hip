@@ -287,7 +287,7 @@ __device__ __noinline__ void store_factor(const double *G, int k, int rho, const
 
 template <int RPL>
 __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double *sigma, double *scr,
-                         double *lds, int *ilds, int *sweeps_out) {
+                         double *lds, int *ilds, int *sweeps_out, uint64_t *ticks) {
   using SH = JacobiShape<RPL, NW>;
   constexpr int NP = SH::NP;
   constexpr int CPW = SH::CPW;
@@ -333,7 +333,9 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
   }
   __syncthreads();
   int *flag = ilds;
-  const int sweeps = jacobi_sweeps<RPL, NW>(J, lds, flag, 60, 1e-14);
+  uint64_t tj0 = wall_clock64();
+  const int sweeps = jacobi_sweeps<RPL, NW>(J, lds, flag, 40, 1e-12);
+  if (tid() == 0) ticks[1] += wall_clock64() - tj0;
   *sweeps_out = sweeps;
   // ---- singular values, descending order
   double *sv = lds;                        // NP values
@@ -728,6 +730,20 @@ __global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
   double *scr = p.scr;
   double *Pc = p.P, *Pn = p.Pnext;
   int max_core = 0, dropped = 0, sweeps_tot = 0, numeric = 0;
+  double flops = 0.0;
+  // phase clocks (thread 0): 0 gather/project, 7 Grams + pivoted Cholesky,
+  // 2 core SVD total, 1 Jacobi sweeps (inside 2), 3 basis completion,
+  // 4 Y/F/row corrections, 5 P <- P F, 6 LU + solve + scatter
+  __shared__ uint64_t jt[8];
+  if (tid() < 8) jt[tid()] = 0;
+  uint64_t tlast = wall_clock64();
+  auto tick = [&](int ph) {
+    if (tid() == 0) {
+      const uint64_t now = wall_clock64();
+      if (ph >= 0) jt[ph] += now - tlast;
+      tlast = now;
+    }
+  };
   for (int ch = 0; ch < p.n_chunks; ++ch) {
     const ChunkDesc desc = p.chunks[ch];
     ChunkState cs;
@@ -741,8 +757,10 @@ __global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
     cs.ne = desc.ne;
     const int k = cs.k;
     // ---- Step 1: gather + project
+    tick(-1);
     gather_project(p.Ub, cs.S1, cs.s1, Pc, d, lds, scr + OFF_UP);
     gather_project(p.Vb, cs.S2, cs.s2, Pc + d * d, d, lds, scr + OFF_VP);
+    tick(0);
     double bmax = 1.0;
     for (int side = 0; side < 2; ++side) {
       double *D = lds;                          // s1 x s2 (<= 4096)
@@ -764,31 +782,48 @@ __global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
       __syncthreads();
     }
     (void)s_bmax;
+    tick(7);
     // ---- Step 2: core SVD
     const int N = d + max(cs.rhoB, cs.rhoC);
     max_core = max(max_core, N);
     int sw = 0;
+    tick(-1);
     if (N <= 64)
-      core_svd<1>(cs, d, p.sigma, scr, lds, ilds, &sw);
+      core_svd<1>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
     else if (N <= 128)
-      core_svd<2>(cs, d, p.sigma, scr, lds, ilds, &sw);
+      core_svd<2>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
     else
-      core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw);
+      core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
+    tick(2);
     sweeps_tot += sw;
+    {
+      // counted FP64 work of this chunk: Jacobi (dot + rotation = 8N flops per
+      // pair, N(N-1)/2 pairs per sweep), H = K^T E, F, P F, LU and solves
+      const double Nn = (double)N, dd = (double)d, kk = (double)k;
+      flops += sw * 4.0 * Nn * Nn * (Nn - 1.0) + 2.0 * Nn * Nn * dd;
+      flops += 2.0 * (2.0 * dd * dd * kk + 2.0 * dd * dd * dd + (2.0 / 3.0) * dd * dd * dd +
+                      2.0 * 2.0 * (double)max(cs.s1, cs.s2) * dd * dd);
+      flops += 2.0 * (double)(cs.s1 + cs.s2) * dd * dd + 4.0 * kk * kk * dd;
+    }
     if (scr[OFF_TH + d - 1] <= 1e-10 * scr[OFF_TH]) {
       complete_basis(d, d + cs.rhoB, d + cs.rhoC, scr);
       __syncthreads();
     }
+    tick(3);
     // ---- Step 3: rotations and row corrections
+    tick(-1);
     solve_Y(0, d, k, cs.rhoB, permB, scr + OFF_LB, scr, lds);
     solve_Y(1, d, k, cs.rhoC, permC, scr + OFF_LC, scr, lds);
     build_F_and_delta(cs, 0, d, scr, lds);
     build_F_and_delta(cs, 1, d, scr, lds);
+    tick(4);
     mul_PF(d, Pc, scr + OFF_FU, Pn, lds);
     mul_PF(d, Pc + d * d, scr + OFF_FV, Pn + d * d, lds);
+    tick(5);
     numeric |= lu_solve_scatter(d, Pn, scr + OFF_DU, cs.S1, cs.s1, p.Ub, p.R, lds, ilds);
     numeric |= lu_solve_scatter(d, Pn + d * d, scr + OFF_DV, cs.S2, cs.s2, p.Vb, nullptr, lds,
                                 ilds);
+    tick(6);
     for (int c = tid(); c < d; c += NT) p.sigma[c] = scr[OFF_TH + c];
     double *t = Pc;
     Pc = Pn;
@@ -805,6 +840,8 @@ __global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
     st.dropped = dropped;
     st.sweeps = sweeps_tot;
     st.numeric_error = numeric;
+    st.flops = flops;
+    for (int i = 0; i < 8; ++i) st.phase_ticks[i] = jt[i];
     *p.stats = st;
   }
 }

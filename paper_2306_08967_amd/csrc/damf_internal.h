@@ -29,6 +29,7 @@ struct Csr {
   int32_t *col = nullptr;
   int64_t pool_cap = 0;
   int64_t *top = nullptr;  // device counter: first free pool entry
+  int64_t nnz_built = 0;    // entries when the CSR was built
 };
 
 // One net edit of A (after set semantics), sorted by (row, col).
@@ -65,6 +66,8 @@ struct ChainStats {
   int32_t dropped;
   int32_t sweeps;
   int32_t numeric_error;
+  double flops;  // FP64 flops executed (counted per phase)
+  uint64_t phase_ticks[8];  // wall-clock ticks per phase (see chain.hip)
 };
 
 struct Workspace {
@@ -118,7 +121,11 @@ struct damf_ctx {
   damf::Workspace ws;
   int64_t round_counter = 0;
   bool ppr_on = true;
-  hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+  hipEvent_t ev[8] = {};
+  hipEvent_t ev_k[2] = {};  // per-kernel timing inside multi-launch stages
+  damf_init_info init_info{};
+  double push_ms = 0.0, push_bytes = 0.0;  // accumulated by ppr_push
+  double wall_khz = 100000.0;               // device wall-clock rate (kHz)
 };
 
 namespace damf {

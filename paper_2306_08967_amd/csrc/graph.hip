@@ -280,6 +280,13 @@ __global__ void copy_rows_kernel(int64_t n, const int64_t *src_off, const int32_
   for (int32_t j = lane; j < L; j += 64) d[j] = s[j];
 }
 
+__global__ void sum_len_kernel(int64_t n, const int32_t *len, int64_t *total) {
+  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int v = (r < n) ? len[r] : 0;
+  v = wave_sum_i(v);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long *)total, (unsigned long long)v);
+}
+
 __global__ void set_caps_kernel(int64_t n, const int32_t *len, int32_t *cap) {
   int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (r >= n) return;
@@ -328,6 +335,9 @@ hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows, const int32_t *
     DAMF_HIP(hipGetLastError());
   }
   set_caps_kernel<<<ceil_div(n, 256), 256, 0, s>>>(n, g.len, g.cap);
+  DAMF_HIP(hipMemsetAsync(total + 1, 0, sizeof(int64_t), s));
+  sum_len_kernel<<<ceil_div(n, 256), 256, 0, s>>>(n, g.len, total + 1);
+  DAMF_HIP(hipMemcpyAsync(&g.nnz_built, total + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   DAMF_HIP(exclusive_scan(CapOf{g.len}, n, g.start, tmp_sums, total, s));
   int64_t pool_used = 0;
   DAMF_HIP(hipMemcpyAsync(&pool_used, total, sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -79,7 +79,9 @@ __device__ __forceinline__ double col_norm2(const double (&col)[RPL]) {
   return wave_sum(s);
 }
 
-// Runs sweeps until a sweep applies no rotation (or max_sweeps).  Returns
+// Runs sweeps until a sweep applies no rotation (or max_sweeps).  A pair is
+// rotated when |a_i . a_j| > tol ||a_i|| ||a_j|| and neither column is
+// numerically zero.  Returns
 // the number of sweeps; on return the squared column norms are in
 // lds[4 * NW * NP + id].  All NW * 64 threads must call it.
 template <int RPL, int NW>
@@ -99,6 +101,15 @@ __device__ int jacobi_sweeps(JacobiRegs<RPL, NW> &J, double *lds, int *lds_flag,
   __syncthreads();
   for (; sweeps < max_sweeps; ++sweeps) {
     int rot = 0;
+    // columns below 1e-15 of the largest column norm are numerically zero:
+    // rotating them only moves rounding noise (a core with more columns than
+    // rows, or a rank-deficient one, has such columns)
+    double mx = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) mx = fmax(mx, nrm[r * 64 + lane]);
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    const double floor2 = 1e-30 * mx;
     for (int step = 0; step < NP - 1; ++step) {
       // ---- rotate the H local pairs
       double g[H];
@@ -124,7 +135,7 @@ __device__ int jacobi_sweeps(JacobiRegs<RPL, NW> &J, double *lds, int *lds_flag,
         const int it = top_id<NP>(w * H + lane, step);
         const int ib = bot_id<NP>(w * H + lane, step);
         const double al = nrm[it], be = nrm[ib];
-        doit = al > 0.0 && be > 0.0 && fabs(myg) > tol * sqrt(al * be);
+        doit = al > floor2 && be > floor2 && fabs(myg) > tol * sqrt(al * be);
         if (doit) {
           const double zeta = (be - al) / (2.0 * myg);
           const double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));

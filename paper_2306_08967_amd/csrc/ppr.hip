@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <algorithm>
 #include <cstring>
 
 #include "common.h"
@@ -30,17 +31,19 @@ namespace {
 constexpr int kRowsPerBlock = 4;  // one wave per row
 
 // One synchronous propagation round over all rows (pull form, out-CSR).
+// Waves stride over rows; the block's max |R'| goes out with one atomic.
 __global__ __launch_bounds__(256) void pull_round_kernel(Csr g, const float *__restrict__ Rold,
                                                          float *__restrict__ Rnew,
                                                          float *__restrict__ Z, int64_t n, int d,
                                                          float alpha, unsigned *maxbits) {
+  __shared__ float bmax[4];
   const int lane = threadIdx.x & 63;
-  const int64_t u = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
+  const bool c0 = lane < d, c1 = lane + 64 < d;
   float m = 0.f;
-  if (u < n) {
+  const int64_t stride = (int64_t)gridDim.x * kRowsPerBlock;
+  for (int64_t u = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6); u < n; u += stride) {
     const int32_t L = g.len[u];
     const int32_t *row = g.col + g.start[u];
-    const bool c0 = lane < d, c1 = lane + 64 < d;
     float a0 = 0.f, a1 = 0.f;
     int32_t e = 0;
     for (; e + 4 <= L; e += 4) {
@@ -76,7 +79,12 @@ __global__ __launch_bounds__(256) void pull_round_kernel(Csr g, const float *__r
     }
   }
   m = wave_max(m);
-  if (lane == 0 && m > 0.f) atomicMax(maxbits, __float_as_uint(m));
+  if (lane == 0) bmax[threadIdx.x >> 6] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    const float b = fmaxf(fmaxf(bmax[0], bmax[1]), fmaxf(bmax[2], bmax[3]));
+    if (b > 0.f) atomicMax(maxbits, __float_as_uint(b));
+  }
 }
 
 // Structural fix-up for each changed out-row u (before the CSR edit and
@@ -112,58 +120,105 @@ __global__ __launch_bounds__(256) void fixup_kernel(Csr g, const NetEntry *net,
 }
 
 // Frontier selection: candidates with max |R| > eps (compared in FP64).
+// Appends are compacted per block (one global atomic per block).
 __global__ __launch_bounds__(256) void select_kernel(const int32_t *cand, int64_t ncand,
                                                      const float *R, int d, double eps,
                                                      int32_t *frontier, int64_t *counters) {
-  const int lane = threadIdx.x & 63;
-  const int64_t j = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
-  if (j >= ncand) return;
-  const int32_t v = cand ? cand[j] : (int32_t)j;
-  float m = 0.f;
-  for (int c = lane; c < d; c += 64) m = fmaxf(m, fabsf(R[(int64_t)v * d + c]));
-  m = wave_max(m);
-  if (lane == 0 && (double)m > eps) {
-    const int64_t at = atomicAdd((unsigned long long *)&counters[1], 1ull);
-    frontier[at] = v;
+  __shared__ int s_cnt;
+  __shared__ int32_t s_list[kRowsPerBlock];
+  __shared__ unsigned long long s_base;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  if (threadIdx.x == 0) s_cnt = 0;
+  __syncthreads();
+  const int64_t j = (int64_t)blockIdx.x * kRowsPerBlock + w;
+  if (j < ncand) {
+    const int32_t v = cand ? cand[j] : (int32_t)j;
+    float m = 0.f;
+    for (int c = lane; c < d; c += 64) m = fmaxf(m, fabsf(R[(int64_t)v * d + c]));
+    m = wave_max(m);
+    if (lane == 0 && (double)m > eps) s_list[atomicAdd(&s_cnt, 1)] = v;
   }
+  __syncthreads();
+  if (threadIdx.x == 0 && s_cnt > 0)
+    s_base = atomicAdd((unsigned long long *)&counters[1], (unsigned long long)s_cnt);
+  __syncthreads();
+  if (threadIdx.x < s_cnt) frontier[s_base + threadIdx.x] = s_list[threadIdx.x];
 }
 
 // Push every frontier node: take R[v] atomically, Z_b[v] += alpha R[v], and
 // spread (1 - alpha) R[v] / deg(u) to each in-neighbour u (in-CSR row v).
+// New candidates (first touch of u in this round, by stamp) are gathered in
+// LDS and appended with one global atomic per block.
+constexpr int kCandBuf = 1024;
 __global__ __launch_bounds__(256) void push_kernel(Csr gin, const int32_t *outdeg,
                                                    const int32_t *frontier, int64_t nf, float *R,
                                                    float *Z, int d, float alpha, int32_t round,
                                                    int32_t *stamp, int32_t *next_cand,
                                                    int64_t *counters) {
+  __shared__ int32_t s_list[kCandBuf];
+  __shared__ int s_cnt;
+  __shared__ unsigned long long s_edges, s_base;
   const int lane = threadIdx.x & 63;
+  if (threadIdx.x == 0) {
+    s_cnt = 0;
+    s_edges = 0;
+  }
+  __syncthreads();
   const int64_t j = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
-  if (j >= nf) return;
-  const int32_t v = frontier[j];
-  const bool c0 = lane < d, c1 = lane + 64 < d;
-  float r0 = 0.f, r1 = 0.f;
-  if (c0) {
-    const int64_t i = (int64_t)v * d + lane;
-    r0 = atomicExch(&R[i], 0.f);
-    Z[i] += alpha * r0;
-  }
-  if (c1) {
-    const int64_t i = (int64_t)v * d + lane + 64;
-    r1 = atomicExch(&R[i], 0.f);
-    Z[i] += alpha * r1;
-  }
-  const int32_t L = gin.len[v];
-  const int32_t *row = gin.col + gin.start[v];
-  for (int32_t e = 0; e < L; ++e) {
-    const int32_t u = row[e];
-    const float s = (1.f - alpha) / (float)outdeg[u];
-    if (c0) atomicAdd(&R[(int64_t)u * d + lane], s * r0);
-    if (c1) atomicAdd(&R[(int64_t)u * d + lane + 64], s * r1);
-    if (lane == 0 && atomicExch(&stamp[u], round) != round) {
-      const int64_t at = atomicAdd((unsigned long long *)&counters[2], 1ull);
-      next_cand[at] = u;
+  if (j < nf) {
+    const int32_t v = frontier[j];
+    const bool c0 = lane < d, c1 = lane + 64 < d;
+    float r0 = 0.f, r1 = 0.f;
+    if (c0) {
+      const int64_t i = (int64_t)v * d + lane;
+      r0 = atomicExch(&R[i], 0.f);
+      Z[i] += alpha * r0;
     }
+    if (c1) {
+      const int64_t i = (int64_t)v * d + lane + 64;
+      r1 = atomicExch(&R[i], 0.f);
+      Z[i] += alpha * r1;
+    }
+    const int32_t L = gin.len[v];
+    const int32_t *row = gin.col + gin.start[v];
+    for (int32_t e0 = 0; e0 < L; e0 += 64) {
+      // one neighbour per lane for the stamp check, then the wave updates rows
+      const int32_t myu = (e0 + lane < L) ? row[e0 + lane] : -1;
+      bool fresh = false;
+      if (myu >= 0) fresh = atomicExch(&stamp[myu], round) != round;
+      const unsigned long long fm = __ballot(fresh);
+      if (fm) {
+        int base = 0;
+        if (lane == 0) base = atomicAdd(&s_cnt, __popcll(fm));
+        base = __shfl(base, 0, 64);
+        if (fresh) {
+          const int at = base + __popcll(fm & ((1ull << lane) - 1ull));
+          if (at < kCandBuf) {
+            s_list[at] = myu;
+          } else {
+            const unsigned long long g = atomicAdd((unsigned long long *)&counters[2], 1ull);
+            next_cand[g] = myu;
+          }
+        }
+      }
+      const int cnt = min(64, L - e0);
+      for (int q = 0; q < cnt; ++q) {
+        const int32_t u = __shfl(myu, q, 64);
+        const float s = (1.f - alpha) / (float)outdeg[u];
+        if (c0) atomicAdd(&R[(int64_t)u * d + lane], s * r0);
+        if (c1) atomicAdd(&R[(int64_t)u * d + lane + 64], s * r1);
+      }
+    }
+    if (lane == 0) atomicAdd(&s_edges, (unsigned long long)L);
   }
-  if (lane == 0) atomicAdd((unsigned long long *)&counters[3], (unsigned long long)L);
+  __syncthreads();
+  const int cnt = min(s_cnt, kCandBuf);
+  if (threadIdx.x == 0) {
+    s_base = cnt ? atomicAdd((unsigned long long *)&counters[2], (unsigned long long)cnt) : 0;
+    if (s_edges) atomicAdd((unsigned long long *)&counters[3], s_edges);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += 256) next_cand[s_base + i] = s_list[i];
 }
 
 __global__ void abs_max_kernel(const float *R, int64_t count, unsigned *maxbits) {
@@ -200,11 +255,20 @@ hipError_t ppr_init(damf_ctx *c) {
     std::memcpy(&mx, &h, sizeof(float));
     if (!((double)mx > c->cfg.eps)) break;
     DAMF_HIP(hipMemsetAsync(maxbits, 0, sizeof(unsigned), s));
-    pull_round_kernel<<<ceil_div(n, kRowsPerBlock), 256, 0, s>>>(c->out, Rcur, Rnxt, c->Zb, n, d,
-                                                                  alpha, maxbits);
+    DAMF_HIP(hipEventRecord(c->ev_k[0], s));
+    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n, kRowsPerBlock), 8192);
+    pull_round_kernel<<<grid, 256, 0, s>>>(c->out, Rcur, Rnxt, c->Zb, n, d, alpha, maxbits);
     DAMF_HIP(hipGetLastError());
+    DAMF_HIP(hipEventRecord(c->ev_k[1], s));
     DAMF_HIP(hipMemcpyAsync(&h, maxbits, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     DAMF_HIP(hipStreamSynchronize(s));
+    float kms = 0.f;
+    DAMF_HIP(hipEventElapsedTime(&kms, c->ev_k[0], c->ev_k[1]));
+    c->init_info.ms_spmm_kernel += kms;
+    c->init_info.ppr_rounds += 1;
+    // compulsory bytes: CSR (start, len, indices), R read once, R' written, Z read + written
+    c->init_info.spmm_bytes += 12.0 * n + 4.0 * (double)c->out.nnz_built +
+                               4.0 * 4.0 * (double)n * d;
     float *t = Rcur;
     Rcur = Rnxt;
     Rnxt = t;
@@ -247,12 +311,22 @@ hipError_t ppr_push(damf_ctx *c, const int32_t *first_rows, int64_t nfirst, int6
     const int64_t nf = w.counters_host[1];
     if (nf == 0) break;
     const int32_t round = (int32_t)(++c->round_counter & 0x7fffffff);
+    DAMF_HIP(hipEventRecord(c->ev_k[0], s));
     push_kernel<<<ceil_div(nf, kRowsPerBlock), 256, 0, s>>>(c->in, c->out.len, front, nf, c->R,
                                                             c->Zb, d, (float)c->cfg.alpha, round,
                                                             w.stamp, next, w.counters);
     DAMF_HIP(hipGetLastError());
+    DAMF_HIP(hipEventRecord(c->ev_k[1], s));
     DAMF_HIP(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DAMF_HIP(hipStreamSynchronize(s));
+    float kms = 0.f;
+    DAMF_HIP(hipEventElapsedTime(&kms, c->ev_k[0], c->ev_k[1]));
+    c->push_ms += kms;
+    // compulsory bytes: per pushed node R[v] and Z_b[v] read + written and
+    // its in-row metadata; per traversed edge the index, deg(u), R[u] read +
+    // written and the stamp word
+    c->push_bytes += (double)nf * (4.0 * 4.0 * d + 12.0) +
+                     (double)w.counters_host[3] * (4.0 + 4.0 + 2.0 * 4.0 * d + 8.0);
     ++*rounds;
     *pushes += nf;
     *edges += w.counters_host[3];

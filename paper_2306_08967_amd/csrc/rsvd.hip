@@ -8,7 +8,7 @@
 //   U = Q Ut[:, :d],  V = Q2 Vt[:, :d],  Sigma = S[:d]
 //
 // Kernels: sketch generation, CSR SpMM of width l = d + p, tall-skinny
-// Householder QR (recursive TSQR over blocks of 256 rows), an FP64 one-sided
+// Householder QR (recursive TSQR over blocks of 512 rows), an FP64 one-sided
 // Jacobi SVD of the l x l factor in one workgroup, and the n x l by l x d
 // rotation GEMM on MFMA (FP32 in, FP32 accumulate).
 #include <hip/hip_runtime.h>
@@ -76,10 +76,10 @@ __global__ __launch_bounds__(256) void spmm_kernel(Csr g, const float *__restric
 }
 
 // ---------------------------------------------------------------- TSQR
-// Block of TB = 256 rows; the l <= 192 columns are spread over the 16 waves
+// Block of TB = 512 rows; the l <= 192 columns are spread over the 16 waves
 // (column c lives in wave c % 16, slot c / 16); lane holds rows lane + 64 r.
 
-constexpr int TB = 256;
+constexpr int TB = 512;
 constexpr int TNT = 1024;
 constexpr int TW = 16;
 constexpr int TCOLS = 12;  // ceil(192 / 16)
@@ -287,7 +287,7 @@ __global__ __launch_bounds__(1024) void small_svd_kernel(const float *Rtop, int 
       J.a[c][r] = (i < l && j < l) ? (double)Rtop[j * l + i] : 0.0;
     }
   }
-  jacobi_sweeps<RPL, NW>(J, lds, &flag, 60, 1e-14);
+  jacobi_sweeps<RPL, NW>(J, lds, &flag, 40, 1e-12);
   const double *nrm = lds + 4 * NW * SH::SLOT;
   for (int j = threadIdx.x; j < 256; j += 1024) {
     sv[j] = (j < NP) ? sqrt(nrm[j]) : -1.0;
@@ -416,7 +416,13 @@ hipError_t tsqr(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) 
   std::vector<int> lds{ld};
   std::vector<float *> taus;
   hipError_t err = hipSuccess;
+  // each level has at most ceil(m / TB) * l <= 0.375 m + l rows, so the stack
+  // of R factors shrinks until it fits one block
   while (true) {
+    if (mats.size() > 64) {
+      err = hipErrorInvalidValue;
+      break;
+    }
     const int64_t mm = rows.back();
     const int64_t nb = (mm + TB - 1) / TB;
     float *tau = nullptr, *S = nullptr;

@@ -56,7 +56,9 @@ def test_struct_layouts_match_header(tmp_path):
     if cc is None:
         pytest.skip("no C compiler")
     lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
-    for cname, py in (("damf_config", _damf.DamfConfig), ("damf_batch_info", _damf.DamfBatchInfo)):
+    pairs = (("damf_config", _damf.DamfConfig), ("damf_batch_info", _damf.DamfBatchInfo),
+             ("damf_init_info", _damf.DamfInitInfo))
+    for cname, py in pairs:
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
             lines.append(f'printf("%zu\\n", offsetof({cname}, {f}));')
@@ -67,7 +69,7 @@ def test_struct_layouts_match_header(tmp_path):
     subprocess.run([cc, str(src), "-o", str(exe)], check=True)
     got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True).stdout.split()]
     want = []
-    for py in (_damf.DamfConfig, _damf.DamfBatchInfo):
+    for _, py in pairs:
         want.append(ctypes.sizeof(py))
         want += [getattr(py, f).offset for f, _ in py._fields_]
     assert got == want

@@ -156,3 +156,31 @@ def test_invalid_ops_leave_state_unchanged(damf):
     info = ctx.update(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int8))
     assert info["chunks"] == 0
     ctx.close()
+
+
+@pytest.mark.parametrize("d,r", [(64, 32), (128, 32), (128, 64)])
+def test_wide_core_parity(damf, d, r):
+    """d + r up to 192: the core SVD runs at padded sizes 128 and 192."""
+    _say(f"case wide_core d={d} r={r}")
+    from workloads import chung_lu_directed
+    n, m = 1200, 16000
+    s0, t0 = chung_lu_directed(n, m, 2.1, 41)
+    orc = DAMFOracle(n, d, True, alpha=1.0, r=r, r_max=64, tau=1e-6).init_exact(s0, t0)
+    ctx = _ctx_from_oracle(damf, orc, (s0, t0))
+    rng = np.random.default_rng(d + r)
+    for b in range(4):
+        k = 150
+        s, t = rng.integers(0, n, k), rng.integers(0, n, k)
+        op = rng.choice(np.array([-1, 1, 1, 1], dtype=np.int8), k)
+        io = orc.update(s, t, op)
+        info = ctx.update(s, t, op)
+        assert info["chunks"] == len(io["chunks"])
+        sg = ctx.singular_values()
+        X, Y = ctx.query("X"), ctx.query("Y")
+        err_s = np.max(np.abs(sg - orc.s)) / orc.s[0]
+        err_p = product_rel_err(X, Y, orc.X(), orc.Y())
+        _say(f"  batch {b}: chunks {info['chunks']} max core {info['max_core']} sweeps "
+             f"{info['sweeps']} sigma err {err_s:.2e} product err {err_p:.2e}")
+        assert err_s <= 1e-5 and err_p <= 1e-5
+    _assert_csr(ctx, orc)
+    ctx.close()
