@@ -23,7 +23,7 @@
 
 #include "common.h"
 #include "damf_internal.h"
-#include "jacobi.h"
+#include "jacobi16.h"
 
 namespace damf {
 
@@ -98,6 +98,7 @@ __device__ __noinline__ void gather_project(const float *Mb, const int32_t *rows
     double acc[KMAX / NG];
 #pragma unroll
     for (int j = 0; j < KMAX / NG; ++j) acc[j] = 0.0;
+#pragma unroll 8
     for (int q = 0; q < d; ++q) {
       const double pv = Pm[q * d + c];
 #pragma unroll
@@ -160,114 +161,121 @@ __device__ __noinline__ void build_Wt(const ChunkState &cs, int side, int d, con
   __syncthreads();
 }
 
-// G = B^T B - W^T W (side B) or C^T C - W^T W (side C), k x k in LDS; also
-// returns max diag of B^T B through *bmax.
+// G = B^T B - W^T W (side B) or C^T C - W^T W (side C), k x k in LDS (row
+// stride KMAX); also returns max(1, max diag of B^T B) through *bmax.
+// Thread t owns row a = t / 8 and columns b = 8 (t % 8) .. + 7.
 __device__ __noinline__ void build_gram(const ChunkState &cs, int side, int d, const double *D,
                            const double *Wt, double *G, double *bmax_out) {
   const int k = cs.k;
   __shared__ double s_bmax;
   if (tid() == 0) s_bmax = 1.0;
   __syncthreads();
-  for (int e = tid(); e < k * k; e += NT) {
-    int a = e / k, b = e - a * k;
-    double btb;
-    // side B: B^T B = I (mode 1) or D^T D (mode 0); side C: C^T C = D D^T (mode 1) or I
-    bool ident = (side == 0) ? (cs.mode != 0) : (cs.mode == 0);
-    if (ident) {
-      btb = (a == b) ? 1.0 : 0.0;
-    } else if (side == 0) {
-      btb = 0.0;
-      for (int i = 0; i < cs.s1; ++i) btb = fma(D[i * cs.s2 + a], D[i * cs.s2 + b], btb);
-    } else {
-      btb = 0.0;
-      for (int j = 0; j < cs.s2; ++j) btb = fma(D[a * cs.s2 + j], D[b * cs.s2 + j], btb);
+  // side B: B^T B = I (mode 1) or D^T D (mode 0); side C: C^T C = D D^T (mode 1) or I
+  const bool ident = (side == 0) ? (cs.mode != 0) : (cs.mode == 0);
+  for (int t = tid(); t < KMAX * 8; t += NT) {
+    const int a = t >> 3, b0 = (t & 7) * 8;
+    if (a >= k || b0 >= k) continue;
+    double w[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) w[q] = 0.0;
+    for (int c = 0; c < d; ++c) {
+      const double wa = Wt[a * d + c];
+#pragma unroll
+      for (int q = 0; q < 8; ++q)
+        if (b0 + q < k) w[q] = fma(wa, Wt[(b0 + q) * d + c], w[q]);
     }
-    double w = 0.0;
-    for (int c = 0; c < d; ++c) w = fma(Wt[a * d + c], Wt[b * d + c], w);
-    G[a * k + b] = btb - w;
-    if (a == b && btb > 1.0) atomicMax((unsigned long long *)&s_bmax, __double_as_longlong(btb));
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int b = b0 + q;
+      if (b >= k) break;
+      double btb;
+      if (ident) {
+        btb = (a == b) ? 1.0 : 0.0;
+      } else if (side == 0) {
+        btb = 0.0;
+        for (int i = 0; i < cs.s1; ++i) btb = fma(D[i * cs.s2 + a], D[i * cs.s2 + b], btb);
+      } else {
+        btb = 0.0;
+        for (int j = 0; j < cs.s2; ++j) btb = fma(D[a * cs.s2 + j], D[b * cs.s2 + j], btb);
+      }
+      G[a * KMAX + b] = btb - w[q];
+      if (a == b && btb > 1.0)
+        atomicMax((unsigned long long *)&s_bmax, __double_as_longlong(btb));
+    }
   }
   __syncthreads();
   *bmax_out = s_bmax;
   __syncthreads();
 }
 
-// Pivoted Cholesky of the k x k PSD matrix G (in LDS, overwritten): stops when
-// the largest remaining diagonal <= thr.  On return G[i][j] for j < rho, i >= j
-// holds L in pivoted order, perm[] the pivot order.  Returns rho.
+// Pivoted Cholesky of the k x k PSD matrix G (LDS, row stride KMAX,
+// overwritten): stops when the largest remaining diagonal <= thr.  On return
+// G[i][j] for j < rho, i >= j holds L in pivoted order and perm[] the pivot
+// order.  Wave 0 picks the pivot, swaps and scales; all threads then update
+// the trailing block (two barriers per step).  Returns rho.
 __device__ __noinline__ int pivoted_cholesky(double *G, int k, double thr, int *perm) {
-  __shared__ int s_piv, s_rho;
-  __shared__ double s_diag;
+  __shared__ int s_rho;
   const int lane = tid() & 63;
-  if (tid() < k) perm[tid()] = tid();
+  if (tid() < KMAX) perm[tid()] = tid();
   if (tid() == 0) s_rho = k;
   __syncthreads();
   for (int j = 0; j < k; ++j) {
     if (tid() < 64) {
-      // argmax of diagonal over i >= j (k <= 64: one element per lane)
-      double v = -1.0;
+      double v = (lane >= j && lane < k) ? G[lane * KMAX + lane] : -1.0;
       int idx = lane;
-      if (lane >= j && lane < k) v = G[lane * k + lane];
 #pragma unroll
       for (int off = 32; off >= 1; off >>= 1) {
-        double ov = __shfl_xor(v, off, 64);
-        int oi = __shfl_xor(idx, off, 64);
+        const double ov = __shfl_xor(v, off, 64);
+        const int oi = __shfl_xor(idx, off, 64);
         if (ov > v || (ov == v && oi < idx)) {
           v = ov;
           idx = oi;
         }
       }
-      if (lane == 0) {
-        s_piv = idx;
-        s_diag = v;
+      if (!(v > thr)) {
+        if (lane == 0) s_rho = j;
+      } else {
+        const int p = idx;
+        if (p != j) {
+          // symmetric swap of rows and columns j, p (lane c handles column c)
+          if (lane < k) {
+            const double a = G[j * KMAX + lane], b = G[p * KMAX + lane];
+            G[j * KMAX + lane] = b;
+            G[p * KMAX + lane] = a;
+          }
+          __builtin_amdgcn_wave_barrier();
+          if (lane < k) {
+            const double a = G[lane * KMAX + j], b = G[lane * KMAX + p];
+            G[lane * KMAX + j] = b;
+            G[lane * KMAX + p] = a;
+          }
+          if (lane == 0) {
+            const int t = perm[j];
+            perm[j] = perm[p];
+            perm[p] = t;
+          }
+          __builtin_amdgcn_wave_barrier();
+        }
+        const double ljj = sqrt(G[j * KMAX + j]);
+        __builtin_amdgcn_wave_barrier();
+        if (lane > j && lane < k) G[lane * KMAX + j] /= ljj;
+        if (lane == j) G[j * KMAX + j] = ljj;
       }
     }
     __syncthreads();
-    if (!(s_diag > thr)) {
-      if (tid() == 0) s_rho = j;
-      __syncthreads();
-      break;
-    }
-    const int p = s_piv;
-    if (p != j) {
-      // symmetric swap of rows/cols j and p
-      for (int c = tid(); c < k; c += NT) {
-        double t = G[j * k + c];
-        G[j * k + c] = G[p * k + c];
-        G[p * k + c] = t;
+    if (s_rho == j) break;  // uniform: s_rho was set before the barrier
+    // trailing update of the lower triangle, mirrored to the upper one
+    for (int e = tid(); e < KMAX * KMAX; e += NT) {
+      const int i = e >> 6, l = e & 63;
+      if (i > j && l > j && l <= i && i < k) {
+        const double v = G[i * KMAX + l] - G[i * KMAX + j] * G[l * KMAX + j];
+        G[i * KMAX + l] = v;
+        G[l * KMAX + i] = v;
       }
-      __syncthreads();
-      for (int r = tid(); r < k; r += NT) {
-        double t = G[r * k + j];
-        G[r * k + j] = G[r * k + p];
-        G[r * k + p] = t;
-      }
-      if (tid() == 0) {
-        int t = perm[j];
-        perm[j] = perm[p];
-        perm[p] = t;
-      }
-      __syncthreads();
-    }
-    const double ljj = sqrt(G[j * k + j]);
-    __syncthreads();
-    for (int i = j + 1 + tid(); i < k; i += NT) G[i * k + j] /= ljj;
-    if (tid() == 0) G[j * k + j] = ljj;
-    __syncthreads();
-    const int m = k - j - 1;
-    for (int e = tid(); e < m * m; e += NT) {
-      int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (l <= i) G[i * k + l] -= G[i * k + j] * G[l * k + j];
-    }
-    __syncthreads();
-    // keep the upper triangle consistent for the next pivot's row swap
-    for (int e = tid(); e < m * m; e += NT) {
-      int i = j + 1 + e / m, l = j + 1 + e % m;
-      if (l > i) G[i * k + l] = G[l * k + i];
     }
     __syncthreads();
   }
-  int rho = s_rho;
+  const int rho = s_rho;
   __syncthreads();
   return rho;
 }
@@ -275,11 +283,10 @@ __device__ __noinline__ int pivoted_cholesky(double *G, int k, double thr, int *
 // R (rho x k): R[i][perm[j]] = L[j][i] (j >= i), i.e. R = L^T Pi^T.
 __device__ __noinline__ void store_factor(const double *G, int k, int rho, const int *perm, double *Lg,
                              double *Rg) {
-  for (int e = tid(); e < k * k; e += NT) Lg[e] = G[e];
-  for (int e = tid(); e < rho * k; e += NT) {
-    int i = e / k, j = e - i * k;  // R row i, pivoted column j
-    double v = (j >= i) ? G[j * k + i] : 0.0;
-    Rg[i * k + perm[j]] = v;
+  for (int e = tid(); e < KMAX * KMAX; e += NT) {
+    const int i = e >> 6, j = e & 63;
+    if (i < k && j < k) Lg[i * k + j] = G[i * KMAX + j];
+    if (i < rho && j < k) Rg[i * k + perm[j]] = (j >= i) ? G[j * KMAX + i] : 0.0;
   }
 }
 
@@ -288,10 +295,12 @@ __device__ __noinline__ void store_factor(const double *G, int k, int rho, const
 template <int RPL>
 __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double *sigma, double *scr,
                          double *lds, int *ilds, int *sweeps_out, uint64_t *ticks) {
-  using SH = JacobiShape<RPL, NW>;
-  constexpr int NP = SH::NP;
-  constexpr int CPW = SH::CPW;
-  const int lane = tid() & 63, w = tid() >> 6;
+  constexpr int NP = 64 * RPL;
+  using S = J16<NP, (NP == 64) ? 16 : 32>;
+  constexpr int CPG = S::CPG, RL = S::RL;
+  const int lane = tid() & 63, sl = lane & 15;
+  const int grp = __builtin_amdgcn_readfirstlane(tid() >> 6) * 4 + (lane >> 4);
+  const bool active = grp < S::G;
   const int k = cs.k;
   const int NB = d + cs.rhoB, NC = d + cs.rhoC;
   const double *WBt = scr + OFF_WB, *WCt = scr + OFF_WC;
@@ -309,39 +318,51 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
     Lm[e] = v;
   }
   __syncthreads();
-  JacobiRegs<RPL, NW> J;
+  // K = diag(Sigma, 0) + L_m R_m^T, R_m = [W_C; R_C], column j held by group grp
+  J16Regs<S> J;
+  if (active) {
+    int jc[CPG];
 #pragma unroll
-  for (int c = 0; c < CPW; ++c) {
-    const int j = jacobi_slot_col<RPL, NW>(w, c);
-    // R_m[j][t] held by lane t
-    double rm = 0.0;
-    if (j < NC && lane < k) rm = (j < d) ? WCt[lane * d + j] : RC[(j - d) * k + lane];
+    for (int c = 0; c < CPG; ++c) {
+      jc[c] = j16_col<S>(grp, c);
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) J.a[c][r] = 0.0;
+      for (int r = 0; r < RL; ++r) J.a[c][r] = 0.0;
+    }
     for (int t = 0; t < k; ++t) {
-      const double rt = __shfl(rm, t, 64);
+      double lm[RL];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) J.a[c][r] = fma(Lm[t * NP + r * 64 + lane], rt, J.a[c][r]);
+      for (int r = 0; r < RL; ++r) lm[r] = Lm[t * NP + r * 16 + sl];
+#pragma unroll
+      for (int c = 0; c < CPG; ++c) {
+        const int j = jc[c];
+        const double rm = (j < d) ? WCt[t * d + j] : ((j < NC) ? RC[(j - d) * k + t] : 0.0);
+#pragma unroll
+        for (int r = 0; r < RL; ++r) J.a[c][r] = fma(lm[r], rm, J.a[c][r]);
+      }
     }
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) {
-      const int i = r * 64 + lane;
-      if (i >= NB || j >= NC) J.a[c][r] = 0.0;
-      if (i == j && i < d) J.a[c][r] += sigma[i];
-      KG[j * NPMAX + i] = J.a[c][r];
+    for (int c = 0; c < CPG; ++c) {
+      const int j = jc[c];
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int i = r * 16 + sl;
+        if (i >= NB || j >= NC) J.a[c][r] = 0.0;
+        if (i == j && i < d) J.a[c][r] += sigma[i];
+        KG[j * NPMAX + i] = J.a[c][r];
+      }
     }
   }
   __syncthreads();
   int *flag = ilds;
   uint64_t tj0 = wall_clock64();
-  const int sweeps = jacobi_sweeps<RPL, NW>(J, lds, flag, 40, 1e-12);
+  const int sweeps = jacobi16_sweeps<S>(J, lds, flag, 40, 1e-12);
   if (tid() == 0) ticks[1] += wall_clock64() - tj0;
   *sweeps_out = sweeps;
   // ---- singular values, descending order
   double *sv = lds;                        // NP values
   int *sid = ilds + 8;                     // NP column ids -> sorted order
   int *rank_of = ilds + 8 + 256;           // column id -> rank
-  const double *nrm = lds + 4 * NW * SH::SLOT;
+  const double *nrm = lds + 2 * S::G * S::SLOT;
   __syncthreads();
   for (int j = tid(); j < NP; j += NT) {
     sv[j] = sqrt(nrm[j]);
@@ -380,17 +401,19 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
   const double smax = sv[0];
   const double cut = 1e-10 * smax;
   // E columns (top d), zero rows beyond NB
+  if (active) {
 #pragma unroll
-  for (int c = 0; c < CPW; ++c) {
-    const int j = jacobi_slot_col<RPL, NW>(w, c);
-    const int rk = rank_of[j];
-    if (rk < d) {
-      const double s = sv[rk];
-      const double inv = (s > cut) ? 1.0 / s : 0.0;
+    for (int c = 0; c < CPG; ++c) {
+      const int j = j16_col<S>(grp, c);
+      const int rk = rank_of[j];
+      if (rk < d) {
+        const double sv_ = sv[rk];
+        const double inv = (sv_ > cut) ? 1.0 / sv_ : 0.0;
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) {
-        const int i = r * 64 + lane;
-        EG[rk * NPMAX + i] = (i < NB) ? J.a[c][r] * inv : 0.0;
+        for (int r = 0; r < RL; ++r) {
+          const int i = r * 16 + sl;
+          EG[rk * NPMAX + i] = (i < NB) ? J.a[c][r] * inv : 0.0;
+        }
       }
     }
   }
@@ -539,11 +562,15 @@ __device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, i
     Ws[e] = Wt[e];
   }
   __syncthreads();
-  for (int e = tid(); e < d * d; e += NT) {
-    int i = e / d, c = e - i * d;
-    double v = side ? HG[i * DMAX + c] : EG[c * NPMAX + i];
-    for (int t = 0; t < k; ++t) v -= Ws[t * d + i] * Ys[t * d + c];
-    F[i * d + c] = v;
+  {
+    const int c = tid() & 127;
+    if (c < d) {
+      for (int i = tid() >> 7; i < d; i += NG) {
+        double v = side ? HG[i * DMAX + c] : EG[c * NPMAX + i];
+        for (int t = 0; t < k; ++t) v -= Ws[t * d + i] * Ys[t * d + c];
+        F[i * d + c] = v;
+      }
+    }
   }
   __syncthreads();
   // row corrections: side B: mode 1 -> Y (s1 rows); mode 0 -> D Y (s1 x d)
@@ -575,11 +602,13 @@ __device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, i
   __syncthreads();
 }
 
-// Pn = Po F (d x d); F staged in LDS.
+// Pn = Po F (d x d): Po staged in LDS (rows read as wave-wide broadcasts),
+// F streamed from L2 (one column per thread, coalesced).
 __device__ __noinline__ void mul_PF(int d, const double *Po, const double *F, double *Pn, double *lds) {
-  for (int e = tid(); e < d * d; e += NT) lds[e] = F[e];
+  for (int e = tid(); e < d * d; e += NT) lds[e] = Po[e];
   __syncthreads();
-  const int c = tid() & 127, g = tid() >> 7;
+  const int c = tid() & 127;
+  const int g = __builtin_amdgcn_readfirstlane(tid() >> 7);
   if (c < d) {
     const int rows_per = (d + NG - 1) / NG;
     for (int i0 = 0; i0 < rows_per; i0 += 16) {
@@ -587,16 +616,16 @@ __device__ __noinline__ void mul_PF(int d, const double *Po, const double *F, do
 #pragma unroll
       for (int q = 0; q < 16; ++q) acc[q] = 0.0;
       for (int kk = 0; kk < d; ++kk) {
-        const double f = lds[kk * d + c];
+        const double f = F[kk * d + c];
 #pragma unroll
         for (int q = 0; q < 16; ++q) {
-          int i = g * rows_per + i0 + q;
-          if (i0 + q < rows_per && i < d) acc[q] = fma(Po[i * d + kk], f, acc[q]);
+          const int i = g * rows_per + i0 + q;
+          if (i0 + q < rows_per && i < d) acc[q] = fma(lds[i * d + kk], f, acc[q]);
         }
       }
 #pragma unroll
       for (int q = 0; q < 16; ++q) {
-        int i = g * rows_per + i0 + q;
+        const int i = g * rows_per + i0 + q;
         if (i0 + q < rows_per && i < d) Pn[i * d + c] = acc[q];
       }
     }
@@ -612,56 +641,99 @@ __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const doub
   double *A = lds;  // d x d
   int *piv = ilds;  // d
   int *src = ilds + DMAX;
-  __shared__ int s_p, s_bad;
+  __shared__ int s_bad;
   for (int e = tid(); e < d * d; e += NT) A[e] = Pn[e];
   if (tid() == 0) s_bad = 0;
   __syncthreads();
   const int lane = tid() & 63;
-  for (int j = 0; j < d; ++j) {
+  // Blocked right-looking LU with partial pivoting, panels of LUB columns:
+  // wave 0 factors the panel (pivot search, swaps inside the panel, scaling,
+  // rank-1 updates), then all threads apply the panel's row swaps to the
+  // other columns, form U12 = L11^-1 A12 and update A22 -= A21 U12.
+  constexpr int LUB = 16;
+  for (int j0 = 0; j0 < d; j0 += LUB) {
+    const int jb = min(LUB, d - j0);
     if (tid() < 64) {
-      double v = -1.0;
-      int idx = j;
-      for (int i = j + lane; i < d; i += 64) {
-        double a = fabs(A[i * d + j]);
-        if (a > v) {
-          v = a;
-          idx = i;
+      for (int j = j0; j < j0 + jb; ++j) {
+        double v = -1.0;
+        int idx = j;
+        for (int i = j + lane; i < d; i += 64) {
+          const double a = fabs(A[i * d + j]);
+          if (a > v) {
+            v = a;
+            idx = i;
+          }
         }
-      }
 #pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        double ov = __shfl_xor(v, off, 64);
-        int oi = __shfl_xor(idx, off, 64);
-        if (ov > v || (ov == v && oi < idx)) {
-          v = ov;
-          idx = oi;
+        for (int off = 32; off >= 1; off >>= 1) {
+          const double ov = __shfl_xor(v, off, 64);
+          const int oi = __shfl_xor(idx, off, 64);
+          if (ov > v || (ov == v && oi < idx)) {
+            v = ov;
+            idx = oi;
+          }
+        }
+        if (lane == 0) {
+          piv[j] = idx;
+          if (!(v > 0.0)) s_bad = 1;
+        }
+        if (idx != j && lane < jb) {
+          const int c = j0 + lane;
+          const double t = A[j * d + c];
+          A[j * d + c] = A[idx * d + c];
+          A[idx * d + c] = t;
+        }
+        __builtin_amdgcn_wave_barrier();
+        const double pv = A[j * d + j];
+        __builtin_amdgcn_wave_barrier();
+        const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+        for (int i = j + 1 + lane; i < d; i += 64) {
+          const double l = A[i * d + j] * inv;
+          A[i * d + j] = l;
+          for (int c = j + 1; c < j0 + jb; ++c) A[i * d + c] -= l * A[j * d + c];
+        }
+        __builtin_amdgcn_wave_barrier();
+      }
+    }
+    __syncthreads();
+    // row swaps of this panel on the columns outside it, in pivot order
+    for (int c = tid(); c < d; c += NT) {
+      if (c >= j0 && c < j0 + jb) continue;
+      for (int j = j0; j < j0 + jb; ++j) {
+        const int p = piv[j];
+        if (p != j) {
+          const double t = A[j * d + c];
+          A[j * d + c] = A[p * d + c];
+          A[p * d + c] = t;
         }
       }
-      if (lane == 0) {
-        s_p = idx;
-        piv[j] = idx;
-        if (!(v > 0.0)) s_bad = 1;
+    }
+    __syncthreads();
+    // U12 = L11^-1 A12 (unit lower L11), one column per thread
+    for (int c = j0 + jb + tid(); c < d; c += NT) {
+      for (int i = 1; i < jb; ++i) {
+        double v = A[(j0 + i) * d + c];
+        for (int t = 0; t < i; ++t) v -= A[(j0 + i) * d + j0 + t] * A[(j0 + t) * d + c];
+        A[(j0 + i) * d + c] = v;
       }
     }
     __syncthreads();
-    const int p = s_p;
-    if (p != j) {
-      for (int c = tid(); c < d; c += NT) {
-        double t = A[j * d + c];
-        A[j * d + c] = A[p * d + c];
-        A[p * d + c] = t;
+    // A22 -= A21 U12: thread owns column c and rows j0 + jb + g, + NG, ...
+    {
+      const int c = tid() & 127;
+      const int g = tid() >> 7;
+      if (c >= j0 + jb && c < d) {
+        double u[LUB];
+#pragma unroll
+        for (int t = 0; t < LUB; ++t) u[t] = (t < jb) ? A[(j0 + t) * d + c] : 0.0;
+        for (int i = j0 + jb + g; i < d; i += NG) {
+          double v = A[i * d + c];
+#pragma unroll
+          for (int t = 0; t < LUB; ++t)
+            if (t < jb) v -= A[i * d + j0 + t] * u[t];
+          A[i * d + c] = v;
+        }
       }
-      __syncthreads();
-    }
-    const double pv = A[j * d + j];
-    const int m = d - j - 1;
-    if (pv != 0.0) {
-      for (int i = j + 1 + tid(); i < d; i += NT) A[i * d + j] /= pv;
-    }
-    __syncthreads();
-    for (int e = tid(); e < m * m; e += NT) {
-      int i = j + 1 + e / m, c = j + 1 + e % m;
-      A[i * d + c] -= A[i * d + j] * A[j * d + c];
     }
     __syncthreads();
   }
@@ -675,39 +747,70 @@ __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const doub
   }
   __syncthreads();
   if (s_bad) return 1;
-  // one wave per row vector: lanes own columns c = lane, lane + 64
-  const int w = tid() >> 6;
-  double *rowbuf = lds + d * d + w * DMAX;
-  for (int i = w; i < nrows; i += NT / 64) {
-    double y0 = (lane < d) ? Dl[i * d + lane] : 0.0;
-    double y1 = (lane + 64 < d) ? Dl[i * d + lane + 64] : 0.0;
-    // Y U = Dl (forward over columns)
-    for (int c = 0; c < d; ++c) {
-      double own = (c < 64) ? y0 : y1;
-      double yc = __shfl(own, c & 63, 64) / A[c * d + c];
+  // Row-vector solves X Pn = Dl: wave w takes rows w, w + NW, ... (up to
+  // SR of them at once, interleaved for latency); lanes own columns
+  // c = lane, lane + 64.  Pivot entries are broadcast with v_readlane.
+  constexpr int SR = KMAX / NW;
+  const int w = __builtin_amdgcn_readfirstlane(tid() >> 6);
+  double y0[SR], y1[SR];
+#pragma unroll
+  for (int q = 0; q < SR; ++q) {
+    const int i = w + NW * q;
+    y0[q] = (i < nrows && lane < d) ? Dl[i * d + lane] : 0.0;
+    y1[q] = (i < nrows && lane + 64 < d) ? Dl[i * d + lane + 64] : 0.0;
+  }
+  // Y U = Dl, forward over columns
+  for (int c = 0; c < d; ++c) {
+    const double inv = 1.0 / A[c * d + c];
+    const double u0 = (lane > c && lane < d) ? A[c * d + lane] : 0.0;
+    const double u1 = (lane + 64 > c && lane + 64 < d) ? A[c * d + lane + 64] : 0.0;
+#pragma unroll
+    for (int q = 0; q < SR; ++q) {
+      const double own = (c < 64) ? y0[q] : y1[q];
+      const double yc = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(own), c & 63),
+                                         __builtin_amdgcn_readlane(__double2loint(own), c & 63)) *
+                        inv;
       if (lane == (c & 63)) {
         if (c < 64)
-          y0 = yc;
+          y0[q] = yc;
         else
-          y1 = yc;
+          y1[q] = yc;
       }
-      if (lane > c && lane < d) y0 -= yc * A[c * d + lane];
-      if (lane + 64 > c && lane + 64 < d) y1 -= yc * A[c * d + lane + 64];
+      y0[q] = fma(-yc, u0, y0[q]);
+      y1[q] = fma(-yc, u1, y1[q]);
     }
-    // W L = Y (L unit lower, backward over columns)
-    for (int c = d - 1; c >= 0; --c) {
-      double own = (c < 64) ? y0 : y1;
-      double zc = __shfl(own, c & 63, 64);
-      if (lane < c && lane < d) y0 -= zc * A[c * d + lane];
-      if (lane + 64 < c) y1 -= zc * A[c * d + lane + 64];
+  }
+  // W L = Y (L unit lower), backward over columns
+  for (int c = d - 1; c >= 0; --c) {
+    const double l0 = (lane < c && lane < d) ? A[c * d + lane] : 0.0;
+    const double l1 = (lane + 64 < c) ? A[c * d + lane + 64] : 0.0;
+#pragma unroll
+    for (int q = 0; q < SR; ++q) {
+      const double own = (c < 64) ? y0[q] : y1[q];
+      const double zc = __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(own), c & 63),
+                                         __builtin_amdgcn_readlane(__double2loint(own), c & 63));
+      y0[q] = fma(-zc, l0, y0[q]);
+      y1[q] = fma(-zc, l1, y1[q]);
     }
-    if (lane < d) rowbuf[lane] = y0;
-    if (lane + 64 < d) rowbuf[lane + 64] = y1;
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  }
+  // X = W Pi (the recorded row swaps, as a gather through src), then scatter;
+  // the row buffers overlay the factor, so wait until every wave is done
+  __syncthreads();
+  double *rowbuf = lds + w * SR * DMAX;
+#pragma unroll
+  for (int q = 0; q < SR; ++q) {
+    if (lane < d) rowbuf[q * DMAX + lane] = y0[q];
+    if (lane + 64 < d) rowbuf[q * DMAX + lane + 64] = y1[q];
+  }
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+#pragma unroll
+  for (int q = 0; q < SR; ++q) {
+    const int i = w + NW * q;
+    if (i >= nrows) continue;
     const int64_t row = rows[i];
     for (int c = lane; c < d; c += 64) {
-      const double x = rowbuf[src[c]];
+      const double x = rowbuf[q * DMAX + src[c]];
       float *mp = Mb + row * d + c;
       *mp = (float)((double)(*mp) + x);
       if (Rr) {
@@ -715,7 +818,6 @@ __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const doub
         *rp = (float)((double)(*rp) + x);
       }
     }
-    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
   return 0;
@@ -723,7 +825,7 @@ __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const doub
 
 __global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
   __shared__ double lds[LDS_DOUBLES];
-  __shared__ int ilds[1024];
+  __shared__ __align__(16) int ilds[1024];
   __shared__ int permB[KMAX], permC[KMAX];
   __shared__ double s_bmax;
   const int d = p.d;
@@ -765,7 +867,7 @@ __global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
     for (int side = 0; side < 2; ++side) {
       double *D = lds;                          // s1 x s2 (<= 4096)
       double *Wt = lds + KMAX * KMAX;           // k x d (<= 8192)
-      double *G = lds + KMAX * KMAX + KMAX * DMAX;  // k x k
+      double *G = lds + KMAX * KMAX + KMAX * DMAX;  // k x k, row stride KMAX
       build_D(cs, D);
       build_Wt(cs, side, d, D, scr + (side ? OFF_VP : OFF_UP), Wt);
       for (int e = tid(); e < k * d; e += NT) scr[(side ? OFF_WC : OFF_WB) + e] = Wt[e];

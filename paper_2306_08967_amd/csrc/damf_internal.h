@@ -16,7 +16,7 @@ constexpr int kMaxBatch = 8192;     // ops per damf_update call (sorted in LDS)
 constexpr int kMaxCore = 192;       // d + chunk rank <= kMaxCore (Jacobi in VGPRs)
 constexpr int kMaxD = 128;          // embedding width
 constexpr int kMaxSide = 64;        // |S1|, |S2| per chunk
-constexpr int kChainThreads = 1024; // one workgroup (16 waves) runs Steps 1-3
+constexpr int kChainThreads = 512;  // one workgroup (8 waves) runs Steps 1-3
 
 // Dynamic CSR with per-row slack.  Row u occupies col[start[u] .. start[u] +
 // len[u]) in ascending order; cap[u] >= len[u] entries are reserved there.
