@@ -66,7 +66,8 @@ typedef struct {
   int32_t max_side;      /* r_max: max(|S1|,|S2|) <= r_max; d + r_max <= 192  */
   double tau;            /* residual Gram eigenvalue drop threshold           */
   int32_t auto_enhance;  /* 1: damf_update runs Step 4 before returning       */
-  int32_t reserved0;
+  int32_t reorth_every;  /* > 0: damf_update re-orthogonalises after every
+                            reorth_every-th batch that changed A; 0: never */
   double graph_slack;    /* CSR pool capacity = slack * m_init + 2^20 entries */
   void *hip_stream;      /* hipStream_t to run on; NULL = a context stream    */
 } damf_config;
@@ -93,6 +94,7 @@ typedef struct {
                                1 Jacobi sweeps, 2 core SVD (incl. 1), 3 basis
                                completion, 4 rotations/row corrections,
                                5 P <- P F, 6 LU solve + scatter, 7 Grams   */
+  double ms_reorth;       /* re-orthogonalisation run by this batch (0: none)  */
 } damf_batch_info;
 
 /* Statistics of the initialisation (damf_init / damf_init_factors). */
@@ -143,6 +145,27 @@ damf_status damf_update(damf_ctx *ctx, int64_t k, const int32_t *src,
 
 /* Step 4 (Sec. 4.4): push PPR residuals until max |R| <= eps. */
 damf_status damf_enhance(damf_ctx *ctx);
+
+/* Flush of the lazy projections (Sec. 4.1, the lazy update equation):
+ * U_b <- U_b P_U, Z_b <- Z_b P_U, R <- R P_U, V_b <- V_b P_V, P_U = P_V = I.
+ * X, Y, Z and the PPR invariant are unchanged up to FP32 rounding of the
+ * rotated bases.  Cost: one n x d by d x d MFMA product per basis.
+ * Errors: DAMF_E_STATE (poisoned), DAMF_E_DEVICE (poisons the context). */
+damf_status damf_flush(damf_ctx *ctx);
+
+/* FP64 re-orthogonalisation of the factorisation, keeping U Sigma V^T
+ * (Sec. 4.1: U and V are the orthonormal factors of the t-SVD, which FP32
+ * rounding over many updates erodes).  With U = U_b P_U, V = V_b P_V:
+ * U^T U = R_U^T R_U and V^T V = R_V^T R_V (FP64 Grams, Cholesky), then
+ * R_U Sigma R_V^T = Ut S Vt^T (FP64 Jacobi SVD), U <- U R_U^-1 Ut,
+ * V <- V R_V^-1 Vt, Sigma <- S, with Z_b and R rotated like U_b and the
+ * projections reset to I.  Directions with S = 0 (rank(A) < d) are completed
+ * to orthonormal columns.  Max |R| may exceed eps afterwards: damf_update
+ * re-orthogonalises before its Step 4; a direct caller runs damf_enhance.
+ * Errors: DAMF_E_NUMERIC when a Cholesky pivot of U^T U or V^T V is below
+ * 0.25 (a basis far from orthonormal, not rounding drift): the state is left
+ * unchanged and the context stays usable.  DAMF_E_DEVICE poisons it. */
+damf_status damf_reorthogonalize(damf_ctx *ctx);
 
 /* Rows of X, Y or Z for q nodes (nodes == NULL: all n rows, q must be n):
  * out is q x d row-major float32.  Row of X = U_b[u] P_U Sigma^(1/2)

@@ -40,7 +40,7 @@ class DamfConfig(C.Structure):
         ("max_side", C.c_int32),
         ("tau", C.c_double),
         ("auto_enhance", C.c_int32),
-        ("reserved0", C.c_int32),
+        ("reorth_every", C.c_int32),
         ("graph_slack", C.c_double),
         ("hip_stream", C.c_void_p),
     ]
@@ -65,6 +65,7 @@ class DamfBatchInfo(C.Structure):
         ("push_bytes", C.c_double),
         ("sweeps", C.c_int64),
         ("chain_phase_ms", C.c_double * 8),
+        ("ms_reorth", C.c_double),
     ]
 
     def as_dict(self):
@@ -115,6 +116,8 @@ def lib():
                                     C.POINTER(p)]
     L.damf_update.argtypes = [p, C.c_int64, p, p, p, C.c_int32, C.POINTER(DamfBatchInfo)]
     L.damf_enhance.argtypes = [p]
+    L.damf_flush.argtypes = [p]
+    L.damf_reorthogonalize.argtypes = [p]
     L.damf_query.argtypes = [p, C.c_int, C.c_int64, p, p, C.c_int32]
     L.damf_singular_values.argtypes = [p, p]
     L.damf_export_csr.argtypes = [p, C.c_int32, p, p, C.POINTER(C.c_int64)]
@@ -128,7 +131,8 @@ def lib():
     L.damf_last_error.restype = C.c_char_p
     L.damf_status_string.argtypes = [C.c_int]
     L.damf_status_string.restype = C.c_char_p
-    for name in ("damf_init", "damf_init_factors", "damf_update", "damf_enhance", "damf_query",
+    for name in ("damf_init", "damf_init_factors", "damf_update", "damf_enhance", "damf_flush",
+                 "damf_reorthogonalize", "damf_query",
                  "damf_singular_values", "damf_export_csr", "damf_export_state",
                  "damf_residual_max", "damf_sync", "damf_get_init_info"):
         getattr(L, name).restype = C.c_int
@@ -219,6 +223,12 @@ class Context:
 
     def enhance(self):
         self._check(lib().damf_enhance(self._h))
+
+    def flush(self):
+        self._check(lib().damf_flush(self._h))
+
+    def reorthogonalize(self):
+        self._check(lib().damf_reorthogonalize(self._h))
 
     def query(self, which, nodes=None, out=None):
         if nodes is None:

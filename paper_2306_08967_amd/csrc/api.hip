@@ -59,6 +59,7 @@ damf_status check_config(const damf_config *cfg) {
   if (cfg->oversample < 0 || cfg->power_iters < 0) return DAMF_E_INVALID_ARG;
   if (cfg->d + cfg->oversample > kMaxCore) return DAMF_E_INVALID_ARG;
   if (!(cfg->graph_slack >= 1.0)) return DAMF_E_INVALID_ARG;
+  if (cfg->reorth_every < 0) return DAMF_E_INVALID_ARG;
   return DAMF_OK;
 }
 
@@ -369,6 +370,20 @@ damf_status damf_update(damf_ctx *c, int64_t k, const int32_t *src, const int32_
     API_HIP(c, launch_chain(c, h.n_chunks), "chain");
     API_HIP(c, hipEventRecord(c->ev[5], s), "event");
   }
+  // re-orthogonalisation due: before Step 4, so the push restores max |R| <= eps
+  bool reorth_refused = false;
+  double ms_reorth = 0.0;
+  if (h.n_net > 0 && c->cfg.reorth_every > 0 &&
+      ++c->batches_since_reorth >= c->cfg.reorth_every) {
+    c->batches_since_reorth = 0;
+    API_HIP(c, hipEventRecord(c->ev[6], s), "event");
+    int bad = 0;
+    API_HIP(c, reorthogonalize(c, &bad), "re-orthogonalisation");
+    API_HIP(c, hipEventRecord(c->ev[7], s), "event");
+    API_HIP(c, hipEventSynchronize(c->ev[7]), "event");
+    ms_reorth = ms_between(c->ev[6], c->ev[7]);
+    reorth_refused = bad != 0;
+  }
   API_HIP(c, hipEventRecord(c->ev[2], s), "event");
   int64_t rounds = 0, pushes = 0, edges = 0;
   c->push_ms = 0.0;
@@ -406,8 +421,12 @@ damf_status damf_update(damf_ctx *c, int64_t k, const int32_t *src, const int32_
     info->sweeps = h.n_net > 0 ? w.cstats_host->sweeps : 0;
     for (int i = 0; i < 8; ++i)
       info->chain_phase_ms[i] = h.n_net > 0 ? (double)w.cstats_host->phase_ticks[i] / c->wall_khz : 0.0;
+    info->ms_reorth = ms_reorth;
   }
   (void)t0;
+  if (reorth_refused)
+    return fail(c, DAMF_E_NUMERIC,
+                "batch applied; re-orthogonalisation refused: basis far from orthonormal");
   return DAMF_OK;
 }
 
@@ -418,6 +437,23 @@ damf_status damf_enhance(damf_ctx *c) {
   int64_t r, p, e;
   API_HIP(c, ppr_push(c, nullptr, 0, &r, &p, &e), "PPR push");
   API_HIP(c, hipStreamSynchronize(c->stream), "PPR push");
+  return DAMF_OK;
+}
+
+damf_status damf_flush(damf_ctx *c) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  API_HIP(c, flush_projections(c), "flush");
+  return DAMF_OK;
+}
+
+damf_status damf_reorthogonalize(damf_ctx *c) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  int bad = 0;
+  API_HIP(c, reorthogonalize(c, &bad), "re-orthogonalisation");
+  if (bad) return fail(c, DAMF_E_NUMERIC, "re-orthogonalisation refused: basis far from orthonormal");
+  c->batches_since_reorth = 0;
   return DAMF_OK;
 }
 

@@ -126,6 +126,7 @@ struct damf_ctx {
   damf_init_info init_info{};
   double push_ms = 0.0, push_bytes = 0.0;  // accumulated by ppr_push
   double wall_khz = 100000.0;               // device wall-clock rate (kHz)
+  int64_t batches_since_reorth = 0;
 };
 
 namespace damf {
@@ -160,6 +161,10 @@ hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B,
                      int d, float *C, int ldc, hipStream_t s);
 hipError_t tsqr_public(float *A, int64_t m, int l, int ld, float *Rtop,
                        hipStream_t s);
+
+// ---- reorth.hip
+hipError_t flush_projections(damf_ctx *c);
+hipError_t reorthogonalize(damf_ctx *c, int *numeric_bad);
 
 // ---- query.hip
 hipError_t launch_query(damf_ctx *c, int which, int64_t q,

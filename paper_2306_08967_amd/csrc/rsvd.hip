@@ -350,10 +350,11 @@ constexpr int GK = 16;
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-__global__ __launch_bounds__(256) void gemm_tall_kernel(const float *__restrict__ A, int64_t n,
-                                                        int l, int lda,
+// C (n x d) = A (n x l) B (l x d), d <= 128.  C may be A itself (lda == ldc):
+// each workgroup owns whole rows and has read all of them before it writes.
+__global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t n, int l, int lda,
                                                         const float *__restrict__ B, int d,
-                                                        float *__restrict__ C, int ldc) {
+                                                        float *C, int ldc) {
   __shared__ float As[GM][GK + 1];
   __shared__ float Bs[GK][128 + 4];
   const int lane = threadIdx.x & 63;
