@@ -2,7 +2,7 @@
 // UpdateEmbeddingE) for every chunk of a batch, in one workgroup.
 //
 // Chunks depend on each other through Sigma and the projections, so they run
-// one after another inside a single 1024-thread workgroup that keeps the
+// one after another inside a single 512-thread workgroup that keeps the
 // small dense state in LDS / L2 and the core matrix in VGPRs.  For a chunk
 // with rows S1, columns S2 and dA = I[:,S1] D I[:,S2]^T the kernel computes,
 // in the U-form (U = U_b P_U, V = V_b P_V):
