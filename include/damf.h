@@ -45,7 +45,9 @@ typedef enum {
   DAMF_E_OOM = 3,          /* device allocation failed                       */
   DAMF_E_DEVICE = 4,       /* a HIP call failed                              */
   DAMF_E_NUMERIC = 5,      /* non-finite value or failed factorisation       */
-  DAMF_E_STATE = 6         /* context poisoned by an earlier device error    */
+  DAMF_E_STATE = 6,        /* context poisoned by an earlier device error    */
+  DAMF_E_BUSY = 7,         /* server admission cap reached (damf_serve.h)    */
+  DAMF_E_TIMEOUT = 8       /* wait ended before the request completed        */
 } damf_status;
 
 typedef enum { DAMF_X = 0, DAMF_Y = 1, DAMF_Z = 2 } damf_which;
@@ -142,6 +144,28 @@ damf_status damf_init_factors(const damf_config *cfg, int64_t m,
 damf_status damf_update(damf_ctx *ctx, int64_t k, const int32_t *src,
                         const int32_t *dst, const int8_t *op, int32_t flags,
                         damf_batch_info *info);
+
+/* Per-request results of damf_update_requests. */
+typedef struct {
+  int64_t net_entries;    /* nonzero entries of the request's net change       */
+  int64_t chunks;         /* chunks the request was cut into                   */
+} damf_request_stats;
+
+/* Several requests in one update step, with the result of applying them one
+ * after another by damf_update without Step 4 in between (Algorithm 2 applied
+ * to each request's events in order).  Request i is ops [sum_{j<i} req_ops[j],
+ * sum_{j<=i} req_ops[j]) of src/dst/op.  Each request's net change is taken
+ * against the graph the earlier requests leave, and its chunks never contain
+ * another request's edits, so U, Sigma, V after the step are those of the
+ * one-by-one sequence; the graph is edited once with the step's net change and
+ * Step 4 runs once (auto_enhance).  nreq in 1..256, sum of req_ops <= 8192;
+ * req_ops is a host array.  per_request (nullable, host, nreq entries)
+ * receives each request's net entries and chunks.  Errors as damf_update. */
+damf_status damf_update_requests(damf_ctx *ctx, int32_t nreq, const int64_t *req_ops,
+                                 const int32_t *src, const int32_t *dst,
+                                 const int8_t *op, int32_t flags,
+                                 damf_batch_info *info,
+                                 damf_request_stats *per_request);
 
 /* Step 4 (Sec. 4.4): push PPR residuals until max |R| <= eps. */
 damf_status damf_enhance(damf_ctx *ctx);

@@ -7,6 +7,8 @@ from ._damf import (  # noqa: F401
     DamfError,
     DAMF_DEVICE_PTRS,
     LIB_PATH,
+    Server,
     default_config,
     lib,
+    server_config,
 )

@@ -22,6 +22,8 @@ DAMF_E_OOM = 3
 DAMF_E_DEVICE = 4
 DAMF_E_NUMERIC = 5
 DAMF_E_STATE = 6
+DAMF_E_BUSY = 7
+DAMF_E_TIMEOUT = 8
 DAMF_DEVICE_PTRS = 1
 WHICH = {"X": 0, "Y": 1, "Z": 2}
 
@@ -89,6 +91,61 @@ class DamfInitInfo(C.Structure):
         return {k: getattr(self, k) for k, _ in self._fields_}
 
 
+class DamfRequestStats(C.Structure):
+    _fields_ = [("net_entries", C.c_int64), ("chunks", C.c_int64)]
+
+
+class DamfServerConfig(C.Structure):
+    _fields_ = [
+        ("admit_bytes", C.c_int64),
+        ("max_step_ops", C.c_int32),
+        ("max_step_requests", C.c_int32),
+        ("overlap_push", C.c_int32),
+        ("start_paused", C.c_int32),
+    ]
+
+
+class DamfRequestInfo(C.Structure):
+    _fields_ = [
+        ("ticket", C.c_int64),
+        ("ops", C.c_int64),
+        ("step", C.c_int64),
+        ("step_requests", C.c_int32),
+        ("status", C.c_int32),
+        ("net_entries", C.c_int64),
+        ("chunks", C.c_int64),
+        ("submit_us", C.c_double),
+        ("start_us", C.c_double),
+        ("done_us", C.c_double),
+        ("latency_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class DamfServerStats(C.Structure):
+    _fields_ = [
+        ("requests_done", C.c_int64),
+        ("ops_done", C.c_int64),
+        ("steps", C.c_int64),
+        ("busy_rejects", C.c_int64),
+        ("admitted_bytes_peak", C.c_int64),
+        ("elapsed_s", C.c_double),
+        ("ops_per_s", C.c_double),
+        ("latency_p50_ms", C.c_double),
+        ("latency_p99_ms", C.c_double),
+        ("latency_mean_ms", C.c_double),
+        ("latency_max_ms", C.c_double),
+        ("mean_requests_per_step", C.c_double),
+        ("mean_ops_per_step", C.c_double),
+        ("push_overlapped_ms", C.c_double),
+    ]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
 class DamfError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"damf status {status}: {msg}")
@@ -115,7 +172,21 @@ def lib():
     L.damf_init_factors.argtypes = [C.POINTER(DamfConfig), C.c_int64, p, p, p, p, p, C.c_int32,
                                     C.POINTER(p)]
     L.damf_update.argtypes = [p, C.c_int64, p, p, p, C.c_int32, C.POINTER(DamfBatchInfo)]
+    L.damf_update_requests.argtypes = [p, C.c_int32, C.POINTER(C.c_int64), p, p, p, C.c_int32,
+                                       C.POINTER(DamfBatchInfo), C.POINTER(DamfRequestStats)]
     L.damf_enhance.argtypes = [p]
+    L.damf_server_config_default.argtypes = [C.POINTER(DamfServerConfig)]
+    L.damf_server_config_default.restype = None
+    L.damf_server_create.argtypes = [p, C.POINTER(DamfServerConfig), C.POINTER(p)]
+    L.damf_submit.argtypes = [p, C.c_int64, p, p, p, C.POINTER(C.c_int64)]
+    L.damf_wait.argtypes = [p, C.c_int64, C.c_int64, C.POINTER(DamfRequestInfo)]
+    L.damf_server_resume.argtypes = [p]
+    L.damf_server_get_stats.argtypes = [p, C.POINTER(DamfServerStats)]
+    L.damf_server_destroy.argtypes = [p]
+    L.damf_server_destroy.restype = None
+    for name in ("damf_update_requests", "damf_server_create", "damf_submit", "damf_wait",
+                 "damf_server_resume", "damf_server_get_stats"):
+        getattr(L, name).restype = C.c_int
     L.damf_flush.argtypes = [p]
     L.damf_reorthogonalize.argtypes = [p]
     L.damf_query.argtypes = [p, C.c_int, C.c_int64, p, p, C.c_int32]
@@ -221,6 +292,29 @@ class Context:
                                       C.c_int32(DAMF_DEVICE_PTRS if dev else 0), C.byref(info)))
         return info.as_dict()
 
+    def update_requests(self, requests):
+        """Apply [(src, dst, op), ...] as one step; returns (batch info, per-request stats)."""
+        nreq = len(requests)
+        sizes = (C.c_int64 * nreq)(*[len(r[0]) for r in requests])
+        if requests and _is_torch(requests[0][0]):
+            import torch
+            src = torch.cat([r[0] for r in requests]).contiguous()
+            dst = torch.cat([r[1] for r in requests]).contiguous()
+            op = torch.cat([r[2] for r in requests]).contiguous()
+        else:
+            src = np.concatenate([np.asarray(r[0], dtype=np.int32) for r in requests])
+            dst = np.concatenate([np.asarray(r[1], dtype=np.int32) for r in requests])
+            op = np.concatenate([np.asarray(r[2], dtype=np.int8) for r in requests])
+        ps, dev, ka1 = _ptr(src, np.int32)
+        pd, _, ka2 = _ptr(dst, np.int32)
+        po, _, ka3 = _ptr(op, np.int8)
+        info = DamfBatchInfo()
+        per = (DamfRequestStats * nreq)()
+        self._check(lib().damf_update_requests(self._h, C.c_int32(nreq), sizes, ps, pd, po,
+                                               C.c_int32(DAMF_DEVICE_PTRS if dev else 0),
+                                               C.byref(info), per))
+        return info.as_dict(), [dict(net_entries=x.net_entries, chunks=x.chunks) for x in per]
+
     def enhance(self):
         self._check(lib().damf_enhance(self._h))
 
@@ -286,6 +380,84 @@ class Context:
     def close(self):
         if self._h:
             lib().damf_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+
+def server_config(**kw):
+    cfg = DamfServerConfig()
+    lib().damf_server_config_default(C.byref(cfg))
+    for k, v in kw.items():
+        if not hasattr(cfg, k):
+            raise KeyError(k)
+        setattr(cfg, k, v)
+    return cfg
+
+
+class Server:
+    """Continuous-batching update server on a Context (include/damf_serve.h).
+
+    While it runs, the context belongs to the server: call no Context method
+    until close().
+    """
+
+    def __init__(self, ctx, **kw):
+        self.ctx = ctx
+        cfg = server_config(**kw)
+        h = C.c_void_p()
+        st = lib().damf_server_create(ctx._h, C.byref(cfg), C.byref(h))
+        if st != DAMF_OK:
+            raise DamfError(st, lib().damf_status_string(st).decode())
+        self._h = h
+
+    def submit(self, src, dst, op):
+        """Admit a request; returns its ticket, or None when the admission cap is reached."""
+        src = np.ascontiguousarray(src, dtype=np.int32)
+        dst = np.ascontiguousarray(dst, dtype=np.int32)
+        op = np.ascontiguousarray(op, dtype=np.int8)
+        t = C.c_int64()
+        st = lib().damf_submit(self._h, C.c_int64(len(src)), src.ctypes.data_as(C.c_void_p),
+                               dst.ctypes.data_as(C.c_void_p), op.ctypes.data_as(C.c_void_p),
+                               C.byref(t))
+        if st == DAMF_E_BUSY:
+            return None
+        if st != DAMF_OK:
+            raise DamfError(st, lib().damf_status_string(st).decode())
+        return t.value
+
+    def wait(self, ticket, timeout_us=-1):
+        info = DamfRequestInfo()
+        st = lib().damf_wait(self._h, C.c_int64(ticket), C.c_int64(timeout_us), C.byref(info))
+        if st != DAMF_OK:
+            raise DamfError(st, lib().damf_status_string(st).decode())
+        return info.as_dict()
+
+    def resume(self):
+        st = lib().damf_server_resume(self._h)
+        if st != DAMF_OK:
+            raise DamfError(st, lib().damf_status_string(st).decode())
+
+    def stats(self):
+        out = DamfServerStats()
+        st = lib().damf_server_get_stats(self._h, C.byref(out))
+        if st != DAMF_OK:
+            raise DamfError(st, lib().damf_status_string(st).decode())
+        return out.as_dict()
+
+    def close(self):
+        if self._h:
+            lib().damf_server_destroy(self._h)
             self._h = None
 
     def __del__(self):

@@ -81,6 +81,12 @@ damf_status alloc_state(damf_ctx *c) {
   API_HIP(c, dalloc(&w.ops_dst, kMaxBatch), "alloc ws");
   API_HIP(c, dalloc(&w.ops_op, kMaxBatch), "alloc ws");
   API_HIP(c, dalloc(&w.units, kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.unit_seg, kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.units_comb, kMaxBatch), "alloc ws");
+  API_HIP(c, dalloc(&w.seg_end, kMaxRequests), "alloc ws");
+  API_HIP(c, dalloc(&w.seg_stats, 2 * kMaxRequests), "alloc ws");
+  API_HIP(c, hipHostMalloc((void **)&w.seg_stats_host, 3 * kMaxRequests * sizeof(int32_t)), "alloc pinned");
+  API_HIP(c, dalloc(&w.pend_rows, 4 * kMaxBatch + 1), "alloc ws");
   API_HIP(c, dalloc(&w.chunk_ent, 2 * kMaxBatch), "alloc ws");
   API_HIP(c, dalloc(&w.net, 2 * kMaxBatch), "alloc ws");
   API_HIP(c, dalloc(&w.net_t, 2 * kMaxBatch), "alloc ws");
@@ -123,13 +129,15 @@ void free_ctx(damf_ctx *c) {
                   c->ws.net, c->ws.net_t, c->ws.rows_out, c->ws.rowpos_out, c->ws.rows_in,
                   c->ws.rowpos_in, c->ws.chunks, c->ws.chunk_s1, c->ws.chunk_s2, c->ws.hdr,
                   c->ws.cstats, c->ws.scratch, c->ws.counters, c->ws.stamp, c->ws.cand,
-                  c->ws.cand2, c->ws.frontier};
+                  c->ws.cand2, c->ws.frontier, c->ws.unit_seg, c->ws.units_comb,
+                  c->ws.seg_end, c->ws.seg_stats, c->ws.pend_rows};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->ws.hdr_host) (void)hipHostFree(c->ws.hdr_host);
   if (c->ws.cstats_host) (void)hipHostFree(c->ws.cstats_host);
   if (c->ws.counters_host) (void)hipHostFree(c->ws.counters_host);
   if (c->ws.dscratch_host) (void)hipHostFree(c->ws.dscratch_host);
+  if (c->ws.seg_stats_host) (void)hipHostFree(c->ws.seg_stats_host);
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->ev_k)
@@ -210,6 +218,183 @@ double ms_between(hipEvent_t a, hipEvent_t b) {
 
 }  // namespace
 
+namespace damf {
+
+damf_status api_fail(damf_ctx *c, damf_status s, const char *msg) { return fail(c, s, msg); }
+damf_status api_dev_fail(damf_ctx *c, hipError_t e, const char *where) {
+  return dev_fail(c, e, where);
+}
+
+damf_status step_prepare(damf_ctx *c, int64_t k, const int32_t *src, const int32_t *dst,
+                         const int8_t *op, int32_t flags, int nseg, const int32_t *seg_end,
+                         BatchHeader *h) {
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  if (k < 1 || k > kMaxBatch) return fail(c, DAMF_E_INVALID_ARG, "batch size out of range");
+  if (!src || !dst || !op) return fail(c, DAMF_E_INVALID_ARG, "null op arrays");
+  if (nseg < 1 || nseg > kMaxRequests || seg_end[nseg - 1] != k)
+    return fail(c, DAMF_E_INVALID_ARG, "bad request segments");
+  for (int i = 1; i < nseg; ++i)
+    if (seg_end[i] < seg_end[i - 1]) return fail(c, DAMF_E_INVALID_ARG, "bad request segments");
+  hipStream_t s = c->stream;
+  Workspace &w = c->ws;
+  if (flags & DAMF_DEVICE_PTRS) {
+    API_HIP(c, hipMemcpyAsync(w.ops_src, src, k * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "copy ops");
+    API_HIP(c, hipMemcpyAsync(w.ops_dst, dst, k * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "copy ops");
+    API_HIP(c, hipMemcpyAsync(w.ops_op, op, k * sizeof(int8_t), hipMemcpyDeviceToDevice, s), "copy ops");
+  } else {
+    for (int64_t i = 0; i < k; ++i)
+      if (src[i] < 0 || dst[i] < 0 || src[i] >= c->n || dst[i] >= c->n || (op[i] != 1 && op[i] != -1))
+        return fail(c, DAMF_E_OUT_OF_RANGE, "op id or type out of range");
+    API_HIP(c, hipMemcpyAsync(w.ops_src, src, k * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy ops");
+    API_HIP(c, hipMemcpyAsync(w.ops_dst, dst, k * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy ops");
+    API_HIP(c, hipMemcpyAsync(w.ops_op, op, k * sizeof(int8_t), hipMemcpyHostToDevice, s), "copy ops");
+  }
+  std::memcpy(w.seg_stats_host + 2 * kMaxRequests, seg_end, nseg * sizeof(int32_t));
+  API_HIP(c, hipMemcpyAsync(w.seg_end, w.seg_stats_host + 2 * kMaxRequests, nseg * sizeof(int32_t),
+                            hipMemcpyHostToDevice, s), "copy segments");
+  API_HIP(c, hipEventRecord(c->ev[0], s), "event");
+  API_HIP(c, launch_batch_prepare(c, (int)k, nseg), "batch prepare");
+  API_HIP(c, hipMemcpyAsync(w.hdr_host, w.hdr, sizeof(BatchHeader), hipMemcpyDeviceToHost, s), "header");
+  API_HIP(c, hipMemcpyAsync(w.seg_stats_host, w.seg_stats, 2 * nseg * sizeof(int32_t),
+                            hipMemcpyDeviceToHost, s), "request stats");
+  API_HIP(c, hipStreamSynchronize(s), "batch prepare");
+  *h = *w.hdr_host;
+  if (h->bad_ops > 0) return fail(c, DAMF_E_OUT_OF_RANGE, "op id or type out of range");
+  API_HIP(c, hipEventRecord(c->ev[1], s), "event");
+  return DAMF_OK;
+}
+
+damf_status step_graph(damf_ctx *c, const BatchHeader &h) {
+  if (h.n_net <= 0) return DAMF_OK;
+  Workspace &w = c->ws;
+  if (c->ppr_on) API_HIP(c, ppr_fixup(c, h.n_rows_out), "PPR structural fix-up");
+  API_HIP(c, launch_csr_edit(c, c->out, w.net, w.rows_out, w.rowpos_out, h.n_rows_out, false), "CSR edit");
+  API_HIP(c, launch_csr_edit(c, c->in, w.net_t, w.rows_in, w.rowpos_in, h.n_rows_in, true), "CSR^T edit");
+  return DAMF_OK;
+}
+
+damf_status step_chain(damf_ctx *c, const BatchHeader &h) {
+  if (h.n_chunks <= 0) return DAMF_OK;
+  hipStream_t s = c->stream;
+  API_HIP(c, hipEventRecord(c->ev[4], s), "event");
+  API_HIP(c, launch_chain(c, h.n_chunks), "chain");
+  API_HIP(c, hipEventRecord(c->ev[5], s), "event");
+  return DAMF_OK;
+}
+
+damf_status step_finish(damf_ctx *c, const BatchHeader &h) {
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  API_HIP(c, hipMemcpyAsync(w.cstats_host, w.cstats, sizeof(ChainStats), hipMemcpyDeviceToHost, s), "stats");
+  API_HIP(c, hipMemcpyAsync(w.hdr_host, w.hdr, sizeof(BatchHeader), hipMemcpyDeviceToHost, s), "header");
+  API_HIP(c, hipStreamSynchronize(s), "update");
+  if (w.hdr_host->pool_overflow) {
+    c->poisoned = true;
+    return fail(c, DAMF_E_OOM, "graph pool exhausted");
+  }
+  if (h.n_chunks > 0 && w.cstats_host->numeric_error) {
+    c->poisoned = true;
+    return fail(c, DAMF_E_NUMERIC, "singular projection in the lazy update");
+  }
+  return DAMF_OK;
+}
+
+void step_info(damf_ctx *c, const BatchHeader &h, int64_t k, damf_batch_info *info) {
+  Workspace &w = c->ws;
+  const bool ch = h.n_chunks > 0;
+  info->ops = k;
+  info->net_entries = h.n_net;
+  info->chunks = h.n_chunks;
+  info->max_core = ch ? w.cstats_host->max_core : 0;
+  info->dropped = ch ? w.cstats_host->dropped : 0;
+  info->ms_prepare = ms_between(c->ev[0], c->ev[1]);
+  info->ms_chain_kernel = ch ? ms_between(c->ev[4], c->ev[5]) : 0.0;
+  info->chain_flops = ch ? w.cstats_host->flops : 0.0;
+  info->sweeps = ch ? w.cstats_host->sweeps : 0;
+  for (int i = 0; i < 8; ++i)
+    info->chain_phase_ms[i] = ch ? (double)w.cstats_host->phase_ticks[i] / c->wall_khz : 0.0;
+}
+
+damf_status step_push_rows(damf_ctx *c, const BatchHeader &h, int nseg, int64_t *count) {
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  *count = 0;
+  if (h.n_rows_out > 0)
+    API_HIP(c, hipMemcpyAsync(w.pend_rows, w.rows_out, h.n_rows_out * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s), "push rows");
+  *count = h.n_rows_out;
+  if (nseg > 1 && h.s1_total > 0) {
+    API_HIP(c, hipMemcpyAsync(w.pend_rows + *count, w.chunk_s1, h.s1_total * sizeof(int32_t),
+                              hipMemcpyDeviceToDevice, s), "push rows");
+    *count += h.s1_total;
+  }
+  return DAMF_OK;
+}
+
+damf_status update_impl(damf_ctx *c, int64_t k, const int32_t *src, const int32_t *dst,
+                        const int8_t *op, int32_t flags, int nseg, const int32_t *seg_end,
+                        damf_batch_info *info, damf_request_stats *per_request) {
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  if (k < 0 || k > kMaxBatch) return fail(c, DAMF_E_INVALID_ARG, "batch size out of range");
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (info) info->ops = k;
+  if (per_request) std::memset(per_request, 0, nseg * sizeof(damf_request_stats));
+  if (k == 0) return DAMF_OK;
+  hipStream_t s = c->stream;
+  BatchHeader h{};
+  damf_status st = step_prepare(c, k, src, dst, op, flags, nseg, seg_end, &h);
+  if (st != DAMF_OK) return st;
+  if (per_request)
+    for (int i = 0; i < nseg; ++i) {
+      per_request[i].net_entries = c->ws.seg_stats_host[2 * i];
+      per_request[i].chunks = c->ws.seg_stats_host[2 * i + 1];
+    }
+  if ((st = step_graph(c, h)) != DAMF_OK) return st;
+  if ((st = step_chain(c, h)) != DAMF_OK) return st;
+  // re-orthogonalisation due: before Step 4, so the push restores max |R| <= eps
+  bool reorth_refused = false;
+  double ms_reorth = 0.0;
+  if (h.n_chunks > 0 && c->cfg.reorth_every > 0 &&
+      ++c->batches_since_reorth >= c->cfg.reorth_every) {
+    c->batches_since_reorth = 0;
+    API_HIP(c, hipEventRecord(c->ev[6], s), "event");
+    int bad = 0;
+    API_HIP(c, reorthogonalize(c, &bad), "re-orthogonalisation");
+    API_HIP(c, hipEventRecord(c->ev[7], s), "event");
+    API_HIP(c, hipEventSynchronize(c->ev[7]), "event");
+    ms_reorth = ms_between(c->ev[6], c->ev[7]);
+    reorth_refused = bad != 0;
+  }
+  API_HIP(c, hipEventRecord(c->ev[2], s), "event");
+  int64_t rounds = 0, pushes = 0, edges = 0;
+  c->push_ms = 0.0;
+  c->push_bytes = 0.0;
+  if (c->ppr_on && c->cfg.auto_enhance) {
+    int64_t nrows = 0;
+    if ((st = step_push_rows(c, h, nseg, &nrows)) != DAMF_OK) return st;
+    API_HIP(c, ppr_push(c, s, c->ws.pend_rows, nrows, &rounds, &pushes, &edges), "PPR push");
+  }
+  API_HIP(c, hipEventRecord(c->ev[3], s), "event");
+  if ((st = step_finish(c, h)) != DAMF_OK) return st;
+  if (info) {
+    step_info(c, h, k, info);
+    info->push_rounds = rounds;
+    info->pushes = pushes;
+    info->push_edges = edges;
+    info->ms_chain = ms_between(c->ev[1], c->ev[2]);
+    info->ms_enhance = ms_between(c->ev[2], c->ev[3]);
+    info->ms_push_kernel = c->push_ms;
+    info->push_bytes = c->push_bytes;
+    info->ms_reorth = ms_reorth;
+  }
+  if (reorth_refused)
+    return fail(c, DAMF_E_NUMERIC,
+                "batch applied; re-orthogonalisation refused: basis far from orthonormal");
+  return DAMF_OK;
+}
+
+}  // namespace damf
+
 extern "C" {
 
 void damf_config_default(damf_config *cfg) {
@@ -240,6 +425,8 @@ const char *damf_status_string(damf_status s) {
     case DAMF_E_DEVICE: return "device error";
     case DAMF_E_NUMERIC: return "numerical failure";
     case DAMF_E_STATE: return "context poisoned by an earlier device error";
+    case DAMF_E_BUSY: return "admission cap reached";
+    case DAMF_E_TIMEOUT: return "timed out";
   }
   return "unknown status";
 }
@@ -334,100 +521,26 @@ damf_status damf_init(const damf_config *cfg, int64_t m, const int32_t *src, con
 damf_status damf_update(damf_ctx *c, int64_t k, const int32_t *src, const int32_t *dst,
                         const int8_t *op, int32_t flags, damf_batch_info *info) {
   if (!c) return DAMF_E_INVALID_ARG;
-  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
-  if (k < 0 || k > kMaxBatch) return fail(c, DAMF_E_INVALID_ARG, "batch size out of range");
-  if (info) std::memset(info, 0, sizeof(*info));
-  if (info) info->ops = k;
-  if (k == 0) return DAMF_OK;
-  if (!src || !dst || !op) return fail(c, DAMF_E_INVALID_ARG, "null op arrays");
-  hipStream_t s = c->stream;
-  Workspace &w = c->ws;
-  auto t0 = std::chrono::steady_clock::now();
-  if (flags & DAMF_DEVICE_PTRS) {
-    API_HIP(c, hipMemcpyAsync(w.ops_src, src, k * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "copy ops");
-    API_HIP(c, hipMemcpyAsync(w.ops_dst, dst, k * sizeof(int32_t), hipMemcpyDeviceToDevice, s), "copy ops");
-    API_HIP(c, hipMemcpyAsync(w.ops_op, op, k * sizeof(int8_t), hipMemcpyDeviceToDevice, s), "copy ops");
-  } else {
-    for (int64_t i = 0; i < k; ++i)
-      if (src[i] < 0 || dst[i] < 0 || src[i] >= c->n || dst[i] >= c->n || (op[i] != 1 && op[i] != -1))
-        return fail(c, DAMF_E_OUT_OF_RANGE, "op id or type out of range");
-    API_HIP(c, hipMemcpyAsync(w.ops_src, src, k * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy ops");
-    API_HIP(c, hipMemcpyAsync(w.ops_dst, dst, k * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy ops");
-    API_HIP(c, hipMemcpyAsync(w.ops_op, op, k * sizeof(int8_t), hipMemcpyHostToDevice, s), "copy ops");
+  const int32_t seg_end = (int32_t)std::max<int64_t>(k, 0);
+  return update_impl(c, k, src, dst, op, flags, 1, &seg_end, info, nullptr);
+}
+
+damf_status damf_update_requests(damf_ctx *c, int32_t nreq, const int64_t *req_ops,
+                                 const int32_t *src, const int32_t *dst, const int8_t *op,
+                                 int32_t flags, damf_batch_info *info,
+                                 damf_request_stats *per_request) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (nreq < 1 || nreq > kMaxRequests || !req_ops)
+    return fail(c, DAMF_E_INVALID_ARG, "request count out of range");
+  std::vector<int32_t> seg_end(nreq);
+  int64_t k = 0;
+  for (int i = 0; i < nreq; ++i) {
+    if (req_ops[i] < 0) return fail(c, DAMF_E_INVALID_ARG, "negative request size");
+    k += req_ops[i];
+    if (k > kMaxBatch) return fail(c, DAMF_E_INVALID_ARG, "batch size out of range");
+    seg_end[i] = (int32_t)k;
   }
-  API_HIP(c, hipEventRecord(c->ev[0], s), "event");
-  API_HIP(c, launch_batch_prepare(c, (int)k), "batch prepare");
-  API_HIP(c, hipMemcpyAsync(w.hdr_host, w.hdr, sizeof(BatchHeader), hipMemcpyDeviceToHost, s), "header");
-  API_HIP(c, hipStreamSynchronize(s), "batch prepare");
-  const BatchHeader h = *w.hdr_host;
-  if (h.bad_ops > 0) return fail(c, DAMF_E_OUT_OF_RANGE, "op id or type out of range");
-  API_HIP(c, hipEventRecord(c->ev[1], s), "event");
-  if (h.n_net > 0) {
-    if (c->ppr_on) API_HIP(c, ppr_fixup(c, h.n_rows_out), "PPR structural fix-up");
-    API_HIP(c, launch_csr_edit(c, c->out, w.net, w.rows_out, w.rowpos_out, h.n_rows_out, false), "CSR edit");
-    API_HIP(c, launch_csr_edit(c, c->in, w.net_t, w.rows_in, w.rowpos_in, h.n_rows_in, true), "CSR^T edit");
-    API_HIP(c, hipEventRecord(c->ev[4], s), "event");
-    API_HIP(c, launch_chain(c, h.n_chunks), "chain");
-    API_HIP(c, hipEventRecord(c->ev[5], s), "event");
-  }
-  // re-orthogonalisation due: before Step 4, so the push restores max |R| <= eps
-  bool reorth_refused = false;
-  double ms_reorth = 0.0;
-  if (h.n_net > 0 && c->cfg.reorth_every > 0 &&
-      ++c->batches_since_reorth >= c->cfg.reorth_every) {
-    c->batches_since_reorth = 0;
-    API_HIP(c, hipEventRecord(c->ev[6], s), "event");
-    int bad = 0;
-    API_HIP(c, reorthogonalize(c, &bad), "re-orthogonalisation");
-    API_HIP(c, hipEventRecord(c->ev[7], s), "event");
-    API_HIP(c, hipEventSynchronize(c->ev[7]), "event");
-    ms_reorth = ms_between(c->ev[6], c->ev[7]);
-    reorth_refused = bad != 0;
-  }
-  API_HIP(c, hipEventRecord(c->ev[2], s), "event");
-  int64_t rounds = 0, pushes = 0, edges = 0;
-  c->push_ms = 0.0;
-  c->push_bytes = 0.0;
-  if (c->ppr_on && c->cfg.auto_enhance) {
-    API_HIP(c, ppr_push(c, w.rows_out, h.n_rows_out, &rounds, &pushes, &edges), "PPR push");
-  }
-  API_HIP(c, hipEventRecord(c->ev[3], s), "event");
-  API_HIP(c, hipMemcpyAsync(w.cstats_host, w.cstats, sizeof(ChainStats), hipMemcpyDeviceToHost, s), "stats");
-  API_HIP(c, hipMemcpyAsync(w.hdr_host, w.hdr, sizeof(BatchHeader), hipMemcpyDeviceToHost, s), "header");
-  API_HIP(c, hipStreamSynchronize(s), "update");
-  if (w.hdr_host->pool_overflow) {
-    c->poisoned = true;
-    return fail(c, DAMF_E_OOM, "graph pool exhausted");
-  }
-  if (h.n_net > 0 && w.cstats_host->numeric_error) {
-    c->poisoned = true;
-    return fail(c, DAMF_E_NUMERIC, "singular projection in the lazy update");
-  }
-  if (info) {
-    info->net_entries = h.n_net;
-    info->chunks = h.n_chunks;
-    info->max_core = h.n_net > 0 ? w.cstats_host->max_core : 0;
-    info->dropped = h.n_net > 0 ? w.cstats_host->dropped : 0;
-    info->push_rounds = rounds;
-    info->pushes = pushes;
-    info->push_edges = edges;
-    info->ms_prepare = ms_between(c->ev[0], c->ev[1]);
-    info->ms_chain = ms_between(c->ev[1], c->ev[2]);
-    info->ms_enhance = ms_between(c->ev[2], c->ev[3]);
-    info->ms_chain_kernel = h.n_net > 0 ? ms_between(c->ev[4], c->ev[5]) : 0.0;
-    info->chain_flops = h.n_net > 0 ? w.cstats_host->flops : 0.0;
-    info->ms_push_kernel = c->push_ms;
-    info->push_bytes = c->push_bytes;
-    info->sweeps = h.n_net > 0 ? w.cstats_host->sweeps : 0;
-    for (int i = 0; i < 8; ++i)
-      info->chain_phase_ms[i] = h.n_net > 0 ? (double)w.cstats_host->phase_ticks[i] / c->wall_khz : 0.0;
-    info->ms_reorth = ms_reorth;
-  }
-  (void)t0;
-  if (reorth_refused)
-    return fail(c, DAMF_E_NUMERIC,
-                "batch applied; re-orthogonalisation refused: basis far from orthonormal");
-  return DAMF_OK;
+  return update_impl(c, k, src, dst, op, flags, nreq, seg_end.data(), info, per_request);
 }
 
 damf_status damf_enhance(damf_ctx *c) {
@@ -435,7 +548,7 @@ damf_status damf_enhance(damf_ctx *c) {
   if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
   if (!c->ppr_on) return DAMF_OK;
   int64_t r, p, e;
-  API_HIP(c, ppr_push(c, nullptr, 0, &r, &p, &e), "PPR push");
+  API_HIP(c, ppr_push(c, c->stream, nullptr, 0, &r, &p, &e), "PPR push");
   API_HIP(c, hipStreamSynchronize(c->stream), "PPR push");
   return DAMF_OK;
 }

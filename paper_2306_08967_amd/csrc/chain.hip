@@ -813,10 +813,7 @@ __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const doub
       const double x = rowbuf[q * DMAX + src[c]];
       float *mp = Mb + row * d + c;
       *mp = (float)((double)(*mp) + x);
-      if (Rr) {
-        float *rp = Rr + row * d + c;
-        *rp = (float)((double)(*rp) + x);
-      }
+      if (Rr) atomicAdd(Rr + row * d + c, (float)x);  // a push may run concurrently
     }
   }
   __syncthreads();

@@ -17,6 +17,7 @@ constexpr int kMaxCore = 192;       // d + chunk rank <= kMaxCore (Jacobi in VGP
 constexpr int kMaxD = 128;          // embedding width
 constexpr int kMaxSide = 64;        // |S1|, |S2| per chunk
 constexpr int kChainThreads = 512;  // one workgroup (8 waves) runs Steps 1-3
+constexpr int kMaxRequests = 256;   // request segments per batch
 
 // Dynamic CSR with per-row slack.  Row u occupies col[start[u] .. start[u] +
 // len[u]) in ascending order; cap[u] >= len[u] entries are reserved there.
@@ -57,7 +58,7 @@ struct BatchHeader {
   int32_t n_rows_in;      // distinct rows touched in A^T
   int32_t max_s;          // largest |S1| or |S2|
   int32_t pool_overflow;  // CSR rows that found no pool space (set by edits)
-  int32_t pad;
+  int32_t s1_total;       // entries of all chunks' S1 lists
 };
 
 // Per-chunk results written by the chain kernel (for batch info).
@@ -74,7 +75,13 @@ struct Workspace {
   // batch preparation
   int32_t *ops_src = nullptr, *ops_dst = nullptr;
   int8_t *ops_op = nullptr;
-  uint64_t *units = nullptr;     // canonical edit units of the batch
+  uint64_t *units = nullptr;     // edit units per request, (request, edge) order
+  int32_t *unit_seg = nullptr;   // request of each unit
+  uint64_t *units_comb = nullptr;  // units of the whole batch's net change
+  int32_t *seg_end = nullptr;    // request segments (exclusive op ends)
+  int32_t *seg_stats = nullptr;  // per request: net entries, chunks
+  int32_t *seg_stats_host = nullptr;  // pinned
+  int32_t *pend_rows = nullptr;  // first push candidates of a deferred Step 4
   NetEntry *chunk_ent = nullptr; // entries of each chunk, chunk after chunk
   NetEntry *net = nullptr;       // sorted by (row, col)
   NetEntry *net_t = nullptr;     // same entries sorted by (col, row)
@@ -131,6 +138,28 @@ struct damf_ctx {
 
 namespace damf {
 
+// ---- api.hip: the steps of one update, shared by damf_update and the server
+damf_status api_fail(damf_ctx *c, damf_status s, const char *msg);
+damf_status api_dev_fail(damf_ctx *c, hipError_t e, const char *where);
+// Copies ops and request segments to the device, validates, prepares the
+// batch and reads its header back (no state changes).
+damf_status step_prepare(damf_ctx *c, int64_t k, const int32_t *src, const int32_t *dst,
+                         const int8_t *op, int32_t flags, int nseg, const int32_t *seg_end,
+                         BatchHeader *h);
+// Structural PPR fix-up and CSR edits of A and A^T (asynchronous).
+damf_status step_graph(damf_ctx *c, const BatchHeader &h);
+// Steps 1-3 over every chunk (asynchronous).
+damf_status step_chain(damf_ctx *c, const BatchHeader &h);
+// Waits for the stream, checks pool overflow and numeric failure.
+damf_status step_finish(damf_ctx *c, const BatchHeader &h);
+void step_info(damf_ctx *c, const BatchHeader &h, int64_t k, damf_batch_info *info);
+// First-round Step 4 candidates into ws.pend_rows: rows of the net change and,
+// with several requests, every chunk's S1 rows (rows whose R got a signal).
+damf_status step_push_rows(damf_ctx *c, const BatchHeader &h, int nseg, int64_t *count);
+damf_status update_impl(damf_ctx *c, int64_t k, const int32_t *src, const int32_t *dst,
+                        const int8_t *op, int32_t flags, int nseg, const int32_t *seg_end,
+                        damf_batch_info *info, damf_request_stats *per_request);
+
 // ---- graph.hip
 hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows,
                      const int32_t *d_cols, int64_t m, double slack);
@@ -140,7 +169,7 @@ hipError_t csr_export(damf_ctx *c, const Csr &g, int64_t *h_indptr,
 hipError_t launch_validate_edges(const int32_t *src, const int32_t *dst,
                                  int64_t m, int64_t n, int32_t *bad,
                                  hipStream_t s);
-hipError_t launch_batch_prepare(damf_ctx *c, int k);
+hipError_t launch_batch_prepare(damf_ctx *c, int k, int nseg);
 hipError_t launch_csr_edit(damf_ctx *c, Csr &g, const NetEntry *net,
                            const int32_t *rows, const int32_t *rowpos,
                            int nrows, bool transposed);
@@ -151,7 +180,7 @@ hipError_t launch_chain(damf_ctx *c, int n_chunks);
 // ---- ppr.hip
 hipError_t ppr_init(damf_ctx *c);
 hipError_t ppr_fixup(damf_ctx *c, int n_rows);
-hipError_t ppr_push(damf_ctx *c, const int32_t *first_rows, int64_t nfirst,
+hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64_t nfirst,
                     int64_t *rounds, int64_t *pushes, int64_t *edges);
 hipError_t ppr_residual_max(damf_ctx *c, double *out);
 

@@ -489,7 +489,12 @@ struct PrepParams {
   int32_t directed;
   int32_t r, r_max;
   Csr out;
-  uint64_t *units;   // canonical unit keys (u << 33 | v << 1 | insert)
+  const int32_t *seg_end;  // request segments: op ranges [seg_end[s-1], seg_end[s]); last == k
+  int32_t nseg;
+  uint64_t *units;       // per-request units (u << 33 | v << 1 | insert), (segment, edge) order
+  int32_t *unit_seg;     // segment of each unit
+  uint64_t *units_comb;  // units of the whole batch's net change, edge order
+  int32_t *seg_stats;    // per segment: net entries, chunks
   NetEntry *net, *net_t;
   int32_t *rows_out, *rowpos_out, *rows_in, *rowpos_in;
   ChunkDesc *chunks;
@@ -498,9 +503,11 @@ struct PrepParams {
   BatchHeader *hdr;
 };
 
-// LDS layout: phase 1 uses keys (8192 x u64) + idx (8192 x u16) + delta;
-// phase 2 reuses the same bytes for up to 16384 entry keys.
-constexpr int kPrepLdsBytes = 2 * kMaxBatch * 8;
+// LDS layout: phase 1 uses keys (8192 x u64) + idx (8192 x u16) + two delta
+// arrays (8192 x i8 each) + the unit order buffer (8192 x u32); phase 2
+// reuses the same bytes for up to 16384 entry keys.
+constexpr int kPrepLdsBytes = kMaxBatch * (8 + 2 + 1 + 1 + 4);
+static_assert(kPrepLdsBytes >= 2 * kMaxBatch * 8, "entry keys must fit");
 
 
 // Sort `ne` entry keys (hi << 33 | lo << 1 | insert) held in LDS and write
@@ -553,18 +560,62 @@ __device__ __forceinline__ uint64_t entry_key(int32_t hi, int32_t lo, int ins) {
   return ((uint64_t)(uint32_t)hi << 33) | ((uint64_t)(uint32_t)lo << 1) | (uint64_t)(ins & 1);
 }
 
+// ascending bitonic sort of P (power of two) uint32 values in LDS
+__device__ void bitonic_u32(uint32_t *a, int P) {
+  for (int k = 2; k <= P; k <<= 1) {
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      for (int i = threadIdx.x; i < P; i += kPrepThreads) {
+        int q = i ^ j;
+        if (q > i) {
+          uint32_t x = a[i], y = a[q];
+          bool up = (i & k) == 0;
+          if ((x > y) == up) {
+            a[i] = y;
+            a[q] = x;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
+// The batch is a sequence of request segments applied in order.  Each
+// request's net change is taken against the graph its predecessors leave
+// (edge-set semantics: the last op of a request on an edge decides), its
+// units are chunked on their own (a chunk never spans two requests), and the
+// graph edits use the net change of the whole batch.  With one segment this
+// is the plain batch.
 __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams p) {
   __shared__ __align__(16) unsigned char lds[kPrepLdsBytes];
   __shared__ int wbuf[16];
   __shared__ int s_bad;
+  __shared__ int s_segend[kMaxRequests];
   uint64_t *key = reinterpret_cast<uint64_t *>(lds);
   uint16_t *idx = reinterpret_cast<uint16_t *>(lds + kMaxBatch * 8);
   int8_t *dl = reinterpret_cast<int8_t *>(lds + kMaxBatch * 10);
+  int8_t *dlc = reinterpret_cast<int8_t *>(lds + kMaxBatch * 11);
+  uint32_t *order = reinterpret_cast<uint32_t *>(lds + kMaxBatch * 12);
   const int k = p.k;
+  const int nseg = p.nseg;
   int P = 1;
   while (P < k) P <<= 1;
   if (threadIdx.x == 0) s_bad = 0;
+  for (int s = threadIdx.x; s < nseg; s += kPrepThreads) s_segend[s] = p.seg_end[s];
+  for (int s = threadIdx.x; s < 2 * nseg; s += kPrepThreads) p.seg_stats[s] = 0;
   __syncthreads();
+  // segment of op i: the first s with seg_end[s] > i
+  auto seg_of = [&](int i) {
+    int lo = 0, hi = nseg - 1;
+    while (lo < hi) {
+      int mid = (lo + hi) >> 1;
+      if (s_segend[mid] > i)
+        hi = mid;
+      else
+        lo = mid + 1;
+    }
+    return lo;
+  };
   // ---- phase 1: validate and sort ops by (canonical edge, order)
   for (int i = threadIdx.x; i < P; i += kPrepThreads) {
     uint64_t kk = ~0ull;
@@ -616,48 +667,105 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
       __syncthreads();
     }
   }
-  // last op per edge decides; compare with presence in A
+  // Per (edge, request) group: the group's last op against the state before
+  // the group (the previous group's last op on the edge, else presence in A).
+  // Per edge: the last op against presence in A (the batch's net change).
   for (int i = threadIdx.x; i < k; i += kPrepThreads) {
-    int8_t d = 0;
-    if (i == k - 1 || key[i + 1] != key[i]) {
-      int32_t u = (int32_t)(key[i] >> 33), v = (int32_t)((key[i] >> 2) & 0x7fffffffu);
-      int o = p.op[idx[i]];
-      bool present = csr_has(p.out, u, v);
-      if (o == 1 && !present) d = 1;
-      if (o == -1 && present) d = -1;
+    int8_t d = 0, dc = 0;
+    const uint64_t kk = key[i];
+    const int sg = seg_of(idx[i]);
+    const bool run_last = (i == k - 1) || key[i + 1] != kk;
+    const bool grp_last = run_last || seg_of(idx[i + 1]) != sg;
+    if (grp_last) {
+      const int32_t u = (int32_t)(kk >> 33), v = (int32_t)((kk >> 2) & 0x7fffffffu);
+      int g0 = i;
+      while (g0 > 0 && key[g0 - 1] == kk && seg_of(idx[g0 - 1]) == sg) --g0;
+      const bool after = p.op[idx[i]] == 1;
+      bool before;
+      int pres = -1;
+      if (g0 > 0 && key[g0 - 1] == kk) {
+        before = p.op[idx[g0 - 1]] == 1;
+      } else {
+        pres = csr_has(p.out, u, v) ? 1 : 0;
+        before = pres != 0;
+      }
+      d = (int8_t)((int)after - (int)before);
+      if (run_last) {
+        if (pres < 0) pres = csr_has(p.out, u, v) ? 1 : 0;
+        dc = (int8_t)((int)after - pres);
+      }
     }
     dl[i] = d;
+    dlc[i] = dc;
   }
   __syncthreads();
-  // compact edit units in canonical order
-  int n_units = 0;
+  // compact the units (edge order) with their segment, and the batch's units
+  int n_units = 0, n_comb = 0;
   for (int base = 0; base < k; base += kPrepThreads) {
     int i = base + threadIdx.x;
     int f = (i < k) && dl[i] != 0;
-    int tot = 0;
+    int fc = (i < k) && dlc[i] != 0;
+    int tot = 0, totc = 0;
     int pos = block_scan_excl(f, wbuf, &tot);
-    if (f) {
+    int posc = block_scan_excl(fc, wbuf, &totc);
+    if (f || fc) {
       int32_t u = (int32_t)(key[i] >> 33), v = (int32_t)((key[i] >> 2) & 0x7fffffffu);
-      p.units[n_units + pos] = entry_key(u, v, dl[i] > 0);
+      if (f) {
+        p.units[n_units + pos] = entry_key(u, v, dl[i] > 0);
+        order[n_units + pos] = ((uint32_t)seg_of(idx[i]) << 16) | (uint32_t)(n_units + pos);
+      }
+      if (fc) p.units_comb[n_comb + posc] = entry_key(u, v, dlc[i] > 0);
     }
     n_units += tot;
+    n_comb += totc;
   }
   __syncthreads();
-  // ---- phase 2: entries of the net change sorted by (row, col)
+  // units into (segment, edge) order: a stable sort by segment
+  if (nseg > 1) {
+    int P2 = 1;
+    while (P2 < n_units) P2 <<= 1;
+    for (int i = n_units + threadIdx.x; i < P2; i += kPrepThreads) order[i] = 0xffffffffu;
+    __syncthreads();
+    bitonic_u32(order, P2);
+  }
+  {
+    constexpr int PER = kMaxBatch / kPrepThreads;
+    uint64_t uk[PER];
+    int us[PER];
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = threadIdx.x + q * kPrepThreads;
+      if (t < n_units) {
+        uk[q] = p.units[order[t] & 0xffffu];
+        us[q] = (int)(order[t] >> 16);
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int t = threadIdx.x + q * kPrepThreads;
+      if (t < n_units) {
+        p.units[t] = uk[q];
+        p.unit_seg[t] = us[q];
+      }
+    }
+  }
+  __syncthreads();
+  // ---- phase 2: entries of the batch's net change sorted by (row, col)
   uint64_t *ent = reinterpret_cast<uint64_t *>(lds);
   int ne = 0;
-  for (int base = 0; base < n_units; base += kPrepThreads) {
+  for (int base = 0; base < n_comb; base += kPrepThreads) {
     int i = base + threadIdx.x;
     int cnt = 0;
     uint64_t uk = 0;
-    if (i < n_units) {
-      uk = p.units[i];
+    if (i < n_comb) {
+      uk = p.units_comb[i];
       int32_t u = (int32_t)(uk >> 33), v = (int32_t)((uk >> 1) & 0x7fffffffu);
       cnt = (p.directed || u == v) ? 1 : 2;
     }
     int tot = 0;
     int pos = block_scan_excl(cnt, wbuf, &tot);
-    if (i < n_units) {
+    if (i < n_comb) {
       int32_t u = (int32_t)(uk >> 33), v = (int32_t)((uk >> 1) & 0x7fffffffu);
       int ins = (int)(uk & 1u);
       ent[ne + pos] = entry_key(u, v, ins);
@@ -675,11 +783,11 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
   __syncthreads();
   int n_rows_in = emit_sorted_entries(ent, ne, true, p.net_t, p.rows_in, p.rowpos_in, wbuf);
   // ---- phase 4: greedy chunking of the units (one wave, sequential)
-  __shared__ int s_nchunks, s_maxs;
+  __shared__ int s_nchunks, s_maxs, s_s1tot;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     int32_t s1v = -1, s2v = -1;  // lane-held members of S1 and S2
-    int s1 = 0, s2 = 0, cur_units = 0, e_start = 0, e_cnt = 0;
+    int s1 = 0, s2 = 0, cur_units = 0, e_start = 0, e_cnt = 0, cur_seg = 0;
     int nchunks = 0, maxs = 0, s1_total = 0, s2_total = 0;
     auto close = [&](void) {
       // sort the lane-held lists by rank and write them out
@@ -700,6 +808,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
         c.e_off = e_start;
         c.ne = e_cnt;
         p.chunks[nchunks] = c;
+        p.seg_stats[2 * cur_seg + 1] += 1;
       }
       maxs = max(maxs, max(s1, s2));
       s1_total += s1;
@@ -713,6 +822,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
     };
     for (int t = 0; t < n_units; ++t) {
       uint64_t uk = p.units[t];
+      const int sg = p.unit_seg[t];
       int32_t u = (int32_t)(uk >> 33), v = (int32_t)((uk >> 1) & 0x7fffffffu);
       int ins = (int)(uk & 1u);
       bool pair = !p.directed && u != v;
@@ -730,7 +840,10 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
       };
       int n1 = count_new(r0, r1x, s1v, s1), n2 = count_new(c0, c1x, s2v, s2);
       int ns1 = s1 + n1, ns2 = s2 + n2;
-      if (cur_units > 0 && !(min(ns1, ns2) <= p.r && max(ns1, ns2) <= p.r_max)) close();
+      if (cur_units > 0 &&
+          (sg != cur_seg || !(min(ns1, ns2) <= p.r && max(ns1, ns2) <= p.r_max)))
+        close();
+      cur_seg = sg;
       // add members
       auto add = [&](int32_t a, int32_t &mine, int &cnt) {
         bool in = __ballot(lane < cnt && mine == a) != 0ull;
@@ -756,6 +869,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
           en.col = u;
           p.chunk_ent[e_start + e_cnt + 1] = en;
         }
+        p.seg_stats[2 * sg] += pair ? 2 : 1;
       }
       e_cnt += pair ? 2 : 1;
       ++cur_units;
@@ -764,6 +878,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
     if (lane == 0) {
       s_nchunks = nchunks;
       s_maxs = maxs;
+      s_s1tot = s1_total;
     }
   }
   __syncthreads();
@@ -775,11 +890,12 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
     h.n_rows_out = n_rows_out;
     h.n_rows_in = n_rows_in;
     h.max_s = s_maxs;
+    h.s1_total = s_s1tot;
     *p.hdr = h;
   }
 }
 
-hipError_t launch_batch_prepare(damf_ctx *c, int k) {
+hipError_t launch_batch_prepare(damf_ctx *c, int k, int nseg) {
   PrepParams p;
   p.src = c->ws.ops_src;
   p.dst = c->ws.ops_dst;
@@ -790,7 +906,12 @@ hipError_t launch_batch_prepare(damf_ctx *c, int k) {
   p.r = c->cfg.max_core_rank;
   p.r_max = c->cfg.max_side;
   p.out = c->out;
+  p.seg_end = c->ws.seg_end;
+  p.nseg = nseg;
   p.units = c->ws.units;
+  p.unit_seg = c->ws.unit_seg;
+  p.units_comb = c->ws.units_comb;
+  p.seg_stats = c->ws.seg_stats;
   p.net = c->ws.net;
   p.net_t = c->ws.net_t;
   p.rows_out = c->ws.rows_out;

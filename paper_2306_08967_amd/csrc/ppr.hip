@@ -87,8 +87,9 @@ __global__ __launch_bounds__(256) void pull_round_kernel(Csr g, const float *__r
   }
 }
 
-// Structural fix-up for each changed out-row u (before the CSR edit and
-// before the chain kernel changes U_b):
+// Structural fix-up for each changed out-row u (before the CSR edit; before
+// or after the chain kernel, which adds the same change to U_b and R, so
+// alpha (R - X) is unchanged; never while a push runs):
 //   P Z_b[u] from the invariant, (alpha (R - X) + Z_b)[u] / (1 - alpha)
 //   P'Z_b[u] = (deg_old P Z_b[u] + sum_added Z_b[v] - sum_removed Z_b[v]) / deg_new
 __global__ __launch_bounds__(256) void fixup_kernel(Csr g, const NetEntry *net,
@@ -120,9 +121,12 @@ __global__ __launch_bounds__(256) void fixup_kernel(Csr g, const NetEntry *net,
 }
 
 // Frontier selection: candidates with max |R| > eps (compared in FP64).
-// Appends are compacted per block (one global atomic per block).
+// Appends are compacted per block (one global atomic per block).  With
+// dedup_round >= 0 a candidate listed twice is taken once (stamp exchange):
+// a node pushed twice in one round would race on its Z_b row.
 __global__ __launch_bounds__(256) void select_kernel(const int32_t *cand, int64_t ncand,
                                                      const float *R, int d, double eps,
+                                                     int32_t *stamp, int32_t dedup_round,
                                                      int32_t *frontier, int64_t *counters) {
   __shared__ int s_cnt;
   __shared__ int32_t s_list[kRowsPerBlock];
@@ -131,8 +135,17 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t *cand, int64_
   if (threadIdx.x == 0) s_cnt = 0;
   __syncthreads();
   const int64_t j = (int64_t)blockIdx.x * kRowsPerBlock + w;
-  if (j < ncand) {
-    const int32_t v = cand ? cand[j] : (int32_t)j;
+  bool take = j < ncand;
+  int32_t v = 0;
+  if (take) {
+    v = cand ? cand[j] : (int32_t)j;
+    if (dedup_round >= 0) {
+      int first = 0;
+      if (lane == 0) first = atomicExch(&stamp[v], dedup_round) != dedup_round;
+      take = __shfl(first, 0, 64) != 0;
+    }
+  }
+  if (take) {
     float m = 0.f;
     for (int c = lane; c < d; c += 64) m = fmaxf(m, fabsf(R[(int64_t)v * d + c]));
     m = wave_max(m);
@@ -288,10 +301,10 @@ hipError_t ppr_fixup(damf_ctx *c, int n_rows) {
 }
 
 // first_rows: candidate rows of the first round (device list), or nullptr to
-// start from every node.
-hipError_t ppr_push(damf_ctx *c, const int32_t *first_rows, int64_t nfirst, int64_t *rounds,
-                    int64_t *pushes, int64_t *edges) {
-  hipStream_t s = c->stream;
+// start from every node.  Runs on stream s (the server overlaps it with the
+// next step's chain kernel; R is only ever changed by atomics meanwhile).
+hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64_t nfirst,
+                    int64_t *rounds, int64_t *pushes, int64_t *edges) {
   Workspace &w = c->ws;
   const int d = c->d;
   *rounds = *pushes = *edges = 0;
@@ -300,11 +313,15 @@ hipError_t ppr_push(damf_ctx *c, const int32_t *first_rows, int64_t nfirst, int6
   if (first_rows && ncand > 0)
     DAMF_HIP(hipMemcpyAsync(cand, first_rows, ncand * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   bool all = (first_rows == nullptr);
+  bool first = true;
   while (ncand > 0) {
     DAMF_HIP(hipMemsetAsync(w.counters, 0, 4 * sizeof(int64_t), s));
-    select_kernel<<<ceil_div(ncand, kRowsPerBlock), 256, 0, s>>>(all ? nullptr : cand, ncand, c->R,
-                                                                  d, c->cfg.eps, front, w.counters);
+    // the caller's list may repeat rows; later rounds' lists are unique by stamp
+    const int32_t dedup = (first && !all) ? (int32_t)(++c->round_counter & 0x7fffffff) : -1;
+    select_kernel<<<ceil_div(ncand, kRowsPerBlock), 256, 0, s>>>(
+        all ? nullptr : cand, ncand, c->R, d, c->cfg.eps, w.stamp, dedup, front, w.counters);
     all = false;
+    first = false;
     DAMF_HIP(hipGetLastError());
     DAMF_HIP(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DAMF_HIP(hipStreamSynchronize(s));

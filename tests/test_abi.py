@@ -1,4 +1,5 @@
 """The C-ABI library loads and exports every entry point the header declares (CPU only)."""
+import glob
 import os
 import re
 import ctypes
@@ -7,12 +8,17 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 HEADER = os.path.join(ROOT, "include", "damf.h")
+SERVE_HEADER = os.path.join(ROOT, "include", "damf_serve.h")
+HEADERS = sorted(glob.glob(os.path.join(ROOT, "include", "*.h")))
 
 
 def _declared():
-    text = open(HEADER).read()
-    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
-    return sorted(set(re.findall(r"\b(damf_[a-z_]+)\s*\(", text)))
+    names = set()
+    for h in HEADERS:
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        names |= set(re.findall(r"\b(damf_[a-z_]+)\s*\(", text))
+    return sorted(names)
 
 
 @pytest.fixture(scope="module")
@@ -26,7 +32,9 @@ def libdamf():
 
 def test_header_declares_core_calls():
     names = _declared()
-    for must in ("damf_init", "damf_update", "damf_enhance", "damf_query"):
+    for must in ("damf_init", "damf_update", "damf_enhance", "damf_query", "damf_flush",
+                 "damf_reorthogonalize", "damf_update_requests", "damf_server_create",
+                 "damf_submit", "damf_wait", "damf_server_destroy"):
         assert must in names
 
 
@@ -55,9 +63,14 @@ def test_struct_layouts_match_header(tmp_path):
     cc = shutil.which("gcc") or shutil.which("cc")
     if cc is None:
         pytest.skip("no C compiler")
-    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"', "int main(void) {"]
+    lines = ['#include <stdio.h>', '#include <stddef.h>', f'#include "{HEADER}"',
+             f'#include "{SERVE_HEADER}"', "int main(void) {"]
     pairs = (("damf_config", _damf.DamfConfig), ("damf_batch_info", _damf.DamfBatchInfo),
-             ("damf_init_info", _damf.DamfInitInfo))
+             ("damf_init_info", _damf.DamfInitInfo),
+             ("damf_request_stats", _damf.DamfRequestStats),
+             ("damf_server_config", _damf.DamfServerConfig),
+             ("damf_request_info", _damf.DamfRequestInfo),
+             ("damf_server_stats", _damf.DamfServerStats))
     for cname, py in pairs:
         lines.append(f'printf("%zu\\n", sizeof({cname}));')
         for f, _ in py._fields_:
