@@ -49,6 +49,13 @@ def parse():
     ap.add_argument("--r", type=int, default=64)
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 skips the oracle leg")
     ap.add_argument("--cpu-batches", type=int, default=1)
+    ap.add_argument("--mode", choices=("update", "serve"), default="update",
+                    help="update: batches through damf_update (default); serve: the server")
+    ap.add_argument("--serve-n", type=int, default=10_000_000)
+    ap.add_argument("--serve-m", type=int, default=200_000_000)
+    ap.add_argument("--serve-requests", type=int, default=6000)
+    ap.add_argument("--serve-sat", type=int, default=400)
+    ap.add_argument("--serve-seconds", type=float, default=12.0)
     return ap.parse_args()
 
 
@@ -97,8 +104,200 @@ def cpu_baseline(w, batches, d, r):
     }
 
 
+def rmat_edges_gpu(n, m, seed, a=0.57, b=0.19, c=0.19):
+    """R-MAT edge set drawn on the GPU (torch): scale ceil(log2 n), ids >= n, self-loops and
+    duplicates dropped and redrawn until m distinct edges remain, then shuffled."""
+    import math
+
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    scale = max(1, math.ceil(math.log2(n)))
+    keys = torch.empty(0, dtype=torch.int64, device="cuda")
+    while keys.numel() < m:
+        cnt = int((m - keys.numel()) * 1.8) + 4096
+        s = torch.zeros(cnt, dtype=torch.int64, device="cuda")
+        t = torch.zeros_like(s)
+        for _ in range(scale):
+            x = torch.rand(cnt, generator=g, device="cuda")
+            right = ((x >= a) & (x < a + b)) | (x >= a + b + c)
+            down = x >= a + b
+            s = (s << 1) | down.to(torch.int64)
+            t = (t << 1) | right.to(torch.int64)
+            del x, right, down
+        ok = (s < n) & (t < n) & (s != t)
+        k = (s[ok] << 32) | t[ok]
+        del s, t, ok
+        keys = torch.unique(torch.cat([keys, k]))
+        del k
+    keys = keys[torch.randperm(keys.numel(), generator=g, device="cuda")[:m]]
+    return (keys >> 32).to(torch.int32), (keys & 0xFFFFFFFF).to(torch.int32)
+
+
+def rmat_requests(n, count, seed, src_dev, dst_dev, median=100.0, sigma=1.0, max_k=8192,
+                  ins_frac=0.9, a=0.57, b=0.19, c=0.19):
+    """Request stream: sizes round(LogNormal(ln median, sigma)) clipped to [1, max_k];
+    inserts drawn by R-MAT, deletes of uniformly chosen initial edges."""
+    import math
+
+    import torch
+    rng = np.random.default_rng(seed)
+    sizes = np.clip(np.round(rng.lognormal(np.log(median), sigma, count)), 1, max_k).astype(np.int64)
+    total = int(sizes.sum())
+    is_ins = rng.random(total) < ins_frac
+    n_ins = int(is_ins.sum())
+    scale = max(1, math.ceil(math.log2(n)))
+    ins_s, ins_t = np.zeros(0, np.int64), np.zeros(0, np.int64)
+    while len(ins_s) < n_ins:
+        cnt = 2 * (n_ins - len(ins_s)) + 1024
+        s_ = np.zeros(cnt, np.int64)
+        t_ = np.zeros(cnt, np.int64)
+        for _ in range(scale):
+            x = rng.random(cnt)
+            s_ = (s_ << 1) | (x >= a + b)
+            t_ = (t_ << 1) | (((x >= a) & (x < a + b)) | (x >= a + b + c))
+        ok = (s_ < n) & (t_ < n) & (s_ != t_)
+        ins_s = np.concatenate([ins_s, s_[ok]])
+        ins_t = np.concatenate([ins_t, t_[ok]])
+    idx = torch.from_numpy(rng.integers(0, src_dev.numel(), total - n_ins)).cuda()
+    del_s = src_dev[idx].cpu().numpy()
+    del_t = dst_dev[idx].cpu().numpy()
+    src = np.zeros(total, np.int32)
+    dst = np.zeros(total, np.int32)
+    op = np.where(is_ins, 1, -1).astype(np.int8)
+    src[is_ins], dst[is_ins] = ins_s[:n_ins], ins_t[:n_ins]
+    src[~is_ins], dst[~is_ins] = del_s, del_t
+    reqs, at = [], 0
+    for k in sizes:
+        reqs.append((src[at:at + k], dst[at:at + k], op[at:at + k]))
+        at += k
+    return reqs
+
+
+def serve_phase(P, ctx, reqs, rate_req_s, seed, **server_kw):
+    """Open loop (rate_req_s > 0: Poisson arrivals) or closed loop (all at once)."""
+    import threading
+    rng = np.random.default_rng(seed)
+    infos, tickets = [], []
+    with P.Server(ctx, **server_kw) as srv:
+        def submitter():
+            t_next = time.perf_counter()
+            for r in reqs:
+                if rate_req_s > 0:
+                    t_next += rng.exponential(1.0 / rate_req_s)
+                    dt = t_next - time.perf_counter()
+                    if dt > 0:
+                        time.sleep(dt)
+                t = srv.submit(*r)
+                while t is None:
+                    time.sleep(1e-4)
+                    t = srv.submit(*r)
+                tickets.append(t)
+
+        th = threading.Thread(target=submitter)
+        th.start()
+        i = 0
+        while th.is_alive() or i < len(tickets):
+            if i < len(tickets):
+                infos.append(srv.wait(tickets[i]))
+                i += 1
+            else:
+                time.sleep(1e-4)
+        th.join()
+        st = srv.stats()
+    lat = np.array([x["latency_ms"] for x in infos])
+    ops = sum(x["ops"] for x in infos)
+    span = (max(x["done_us"] for x in infos) - min(x["submit_us"] for x in infos)) * 1e-6
+    return {
+        "requests": len(infos), "ops": int(ops), "seconds": span, "ops_per_s": ops / span,
+        "latency_ms": {"p50": pct(lat, 50), "p99": pct(lat, 99), "mean": float(lat.mean()),
+                       "max": float(lat.max())},
+        "steps": int(st["steps"]), "mean_requests_per_step": st["mean_requests_per_step"],
+        "mean_ops_per_step": st["mean_ops_per_step"],
+        "push_beside_chain_ms": st["push_overlapped_ms"],
+    }
+
+
+def serve_main(args):
+    """Serving form: continuous batching of a Poisson stream of uneven requests."""
+    import torch
+
+    from paper_2306_08967_amd import Context, default_config
+    import paper_2306_08967_amd as P
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n, m, d = args.serve_n, args.serve_m, args.d
+    t0 = time.perf_counter()
+    src, dst = rmat_edges_gpu(n, m, args.seed)
+    torch.cuda.synchronize()
+    log(f"serve workload: R-MAT n={n} m={m} on the GPU in {time.perf_counter() - t0:.1f}s")
+    cfg = default_config(n, d, directed=True, alpha=0.15, eps=1e-5, oversample=10,
+                         power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64)
+    t0 = time.perf_counter()
+    ctx = Context.init(cfg, src, dst)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    log(f"init {init_s:.1f}s: {ctx.init_info()}")
+    reqs = rmat_requests(n, args.serve_requests, args.seed + 7, src, dst)
+    del src, dst
+    torch.cuda.empty_cache()
+    mean_k = float(np.mean([len(r[0]) for r in reqs]))
+    log(f"{len(reqs)} requests, mean {mean_k:.0f} ops")
+    at = 0
+
+    def take(cnt):
+        nonlocal at
+        out = reqs[at:at + cnt]
+        at += cnt
+        assert len(out) == cnt, "request pool exhausted"
+        return out
+
+    # warm-up, then saturation: everything submitted at once (closed loop)
+    serve_phase(P, ctx, take(40), 0.0, 1)
+    sat = serve_phase(P, ctx, take(args.serve_sat), 0.0, 2)
+    log(f"saturation: {sat['ops_per_s']:.0f} ops/s, {sat['mean_requests_per_step']:.1f} req/step")
+    phases = []
+    for i, frac in enumerate((0.5, 0.8, 0.95)):
+        rate = frac * sat["ops_per_s"] / mean_k
+        cnt = int(rate * args.serve_seconds)
+        r = serve_phase(P, ctx, take(cnt), rate, 10 + i)
+        r.update(load=frac, offered_req_s=rate, offered_ops_s=rate * mean_k, coalescing=True)
+        phases.append(r)
+        log(f"load {frac}: p50 {r['latency_ms']['p50']:.1f} ms p99 {r['latency_ms']['p99']:.1f} ms "
+            f"{r['ops_per_s']:.0f} ops/s, {r['mean_requests_per_step']:.2f} req/step")
+    # the same offered load without coalescing: one request per step (a queue alone)
+    rate = 0.5 * sat["ops_per_s"] / mean_k
+    cnt = int(rate * args.serve_seconds)
+    q = serve_phase(P, ctx, take(cnt), rate, 20, max_step_requests=1)
+    q.update(load=0.5, offered_req_s=rate, offered_ops_s=rate * mean_k, coalescing=False)
+    phases.append(q)
+    log(f"queue only at 0.5: p50 {q['latency_ms']['p50']:.1f} ms p99 {q['latency_ms']['p99']:.1f} ms")
+    ctx.close()
+    line = {
+        "metric": "serving edge-updates/s at saturation; p50/p99 request latency under Poisson load",
+        "value": sat["ops_per_s"], "unit": "edge-updates/s", "n_gpus": 1,
+        "steps": sat["steps"], "warmup": 40, "ms_per_step": sat["seconds"] * 1e3 / max(sat["steps"], 1),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "R-MAT (0.57, 0.19, 0.19) directed, ids < n, no loops/duplicates; "
+                               "requests round(LogNormal(ln 100, 1)) clipped 1..8192 ops, "
+                               "90% R-MAT inserts / 10% deletes of initial edges; "
+                               "alpha=0.15 eps=1e-5",
+                   "n": n, "m": m, "d": d, "chunk_rank": args.r},
+        "saturation": sat, "load_phases": phases, "init_s": init_s,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     args = parse()
+    if args.mode == "serve":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        serve_main(args)
+        return
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (got --gpus {args.gpus}); the multi-GPU sharding "
               "of this path is a design note, not built.", file=sys.stderr)

@@ -70,7 +70,10 @@ typedef struct {
   int32_t auto_enhance;  /* 1: damf_update runs Step 4 before returning       */
   int32_t reorth_every;  /* > 0: damf_update re-orthogonalises after every
                             reorth_every-th batch that changed A; 0: never */
-  double graph_slack;    /* CSR pool capacity = slack * m_init + 2^20 entries */
+  double graph_slack;    /* CSR pool: rows reserve len + len/4 + 4 entries; the
+                            pool holds max(reservations, slack * m) plus a
+                            free quarter of the reservations; compacted when
+                            less than an eighth is free                      */
   void *hip_stream;      /* hipStream_t to run on; NULL = a context stream    */
 } damf_config;
 

@@ -87,6 +87,8 @@ damf_status alloc_state(damf_ctx *c) {
   API_HIP(c, dalloc(&w.seg_stats, 2 * kMaxRequests), "alloc ws");
   API_HIP(c, hipHostMalloc((void **)&w.seg_stats_host, 3 * kMaxRequests * sizeof(int32_t)), "alloc pinned");
   API_HIP(c, dalloc(&w.pend_rows, 4 * kMaxBatch + 1), "alloc ws");
+  API_HIP(c, dalloc(&w.edit_stage, (size_t)kEditStagePool), "alloc ws");
+  API_HIP(c, dalloc(&w.edit_stage_top, 1), "alloc ws");
   API_HIP(c, dalloc(&w.chunk_ent, 2 * kMaxBatch), "alloc ws");
   API_HIP(c, dalloc(&w.net, 2 * kMaxBatch), "alloc ws");
   API_HIP(c, dalloc(&w.net_t, 2 * kMaxBatch), "alloc ws");
@@ -130,7 +132,8 @@ void free_ctx(damf_ctx *c) {
                   c->ws.rowpos_in, c->ws.chunks, c->ws.chunk_s1, c->ws.chunk_s2, c->ws.hdr,
                   c->ws.cstats, c->ws.scratch, c->ws.counters, c->ws.stamp, c->ws.cand,
                   c->ws.cand2, c->ws.frontier, c->ws.unit_seg, c->ws.units_comb,
-                  c->ws.seg_end, c->ws.seg_stats, c->ws.pend_rows};
+                  c->ws.seg_end, c->ws.seg_stats, c->ws.pend_rows, c->ws.edit_stage,
+                  c->ws.edit_stage_top, c->ws.hbuf, c->ws.hnode, c->ws.hseg};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->ws.hdr_host) (void)hipHostFree(c->ws.hdr_host);
@@ -267,6 +270,20 @@ damf_status step_prepare(damf_ctx *c, int64_t k, const int32_t *src, const int32
 damf_status step_graph(damf_ctx *c, const BatchHeader &h) {
   if (h.n_net <= 0) return DAMF_OK;
   Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  // make room first if the rows that outgrow their reservation could
+  // overflow a pool
+  API_HIP(c, launch_csr_need(c, c->out, w.net, w.rows_out, w.rowpos_out, h.n_rows_out, w.counters + 10), "pool need");
+  API_HIP(c, launch_csr_need(c, c->in, w.net_t, w.rows_in, w.rowpos_in, h.n_rows_in, w.counters + 11), "pool need");
+  API_HIP(c, hipMemcpyAsync(w.counters_host + 10, w.counters + 10, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s), "pool need");
+  API_HIP(c, hipMemcpyAsync(w.counters_host + 8, c->out.top, sizeof(int64_t), hipMemcpyDeviceToHost, s), "pool");
+  API_HIP(c, hipMemcpyAsync(w.counters_host + 9, c->in.top, sizeof(int64_t), hipMemcpyDeviceToHost, s), "pool");
+  API_HIP(c, hipStreamSynchronize(s), "pool need");
+  const int64_t need_out = w.counters_host[10], need_in = w.counters_host[11];
+  if (c->out.pool_cap - w.counters_host[8] < need_out)
+    API_HIP(c, csr_compact(c, c->out, c->cfg.graph_slack, 2 * need_out), "CSR compaction");
+  if (c->in.pool_cap - w.counters_host[9] < need_in)
+    API_HIP(c, csr_compact(c, c->in, c->cfg.graph_slack, 2 * need_in), "CSR^T compaction");
   if (c->ppr_on) API_HIP(c, ppr_fixup(c, h.n_rows_out), "PPR structural fix-up");
   API_HIP(c, launch_csr_edit(c, c->out, w.net, w.rows_out, w.rowpos_out, h.n_rows_out, false), "CSR edit");
   API_HIP(c, launch_csr_edit(c, c->in, w.net_t, w.rows_in, w.rowpos_in, h.n_rows_in, true), "CSR^T edit");
@@ -287,11 +304,19 @@ damf_status step_finish(damf_ctx *c, const BatchHeader &h) {
   hipStream_t s = c->stream;
   API_HIP(c, hipMemcpyAsync(w.cstats_host, w.cstats, sizeof(ChainStats), hipMemcpyDeviceToHost, s), "stats");
   API_HIP(c, hipMemcpyAsync(w.hdr_host, w.hdr, sizeof(BatchHeader), hipMemcpyDeviceToHost, s), "header");
+  API_HIP(c, hipMemcpyAsync(w.counters_host + 8, c->out.top, sizeof(int64_t), hipMemcpyDeviceToHost, s), "pool");
+  API_HIP(c, hipMemcpyAsync(w.counters_host + 9, c->in.top, sizeof(int64_t), hipMemcpyDeviceToHost, s), "pool");
   API_HIP(c, hipStreamSynchronize(s), "update");
   if (w.hdr_host->pool_overflow) {
     c->poisoned = true;
     return fail(c, DAMF_E_OOM, "graph pool exhausted");
   }
+  // rows that moved left their old space behind: compact a pool once less
+  // than an eighth of it is free
+  if (c->out.pool_cap - w.counters_host[8] < c->out.pool_cap / 8)
+    API_HIP(c, csr_compact(c, c->out, c->cfg.graph_slack, 0), "CSR compaction");
+  if (c->in.pool_cap - w.counters_host[9] < c->in.pool_cap / 8)
+    API_HIP(c, csr_compact(c, c->in, c->cfg.graph_slack, 0), "CSR^T compaction");
   if (h.n_chunks > 0 && w.cstats_host->numeric_error) {
     c->poisoned = true;
     return fail(c, DAMF_E_NUMERIC, "singular projection in the lazy update");

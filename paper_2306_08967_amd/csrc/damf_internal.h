@@ -18,6 +18,7 @@ constexpr int kMaxD = 128;          // embedding width
 constexpr int kMaxSide = 64;        // |S1|, |S2| per chunk
 constexpr int kChainThreads = 512;  // one workgroup (8 waves) runs Steps 1-3
 constexpr int kMaxRequests = 256;   // request segments per batch
+constexpr int64_t kEditStagePool = 1 << 24;  // staging entries for long-row edits
 
 // Dynamic CSR with per-row slack.  Row u occupies col[start[u] .. start[u] +
 // len[u]) in ascending order; cap[u] >= len[u] entries are reserved there.
@@ -82,6 +83,12 @@ struct Workspace {
   int32_t *seg_stats = nullptr;  // per request: net entries, chunks
   int32_t *seg_stats_host = nullptr;  // pinned
   int32_t *pend_rows = nullptr;  // first push candidates of a deferred Step 4
+  float *hbuf = nullptr;         // Step 4: taken residuals of heavy frontier nodes
+  int32_t *hnode = nullptr;      // their node ids
+  void *hseg = nullptr;          // (heavy node, segment) pairs (int2)
+  int64_t heavy_cap = 0, hseg_cap = 0;
+  int32_t *edit_stage = nullptr;     // staging pool for in-place edits of long rows
+  int64_t *edit_stage_top = nullptr; // its bump counter (reset per edit launch)
   NetEntry *chunk_ent = nullptr; // entries of each chunk, chunk after chunk
   NetEntry *net = nullptr;       // sorted by (row, col)
   NetEntry *net_t = nullptr;     // same entries sorted by (col, row)
@@ -170,6 +177,9 @@ hipError_t launch_validate_edges(const int32_t *src, const int32_t *dst,
                                  int64_t m, int64_t n, int32_t *bad,
                                  hipStream_t s);
 hipError_t launch_batch_prepare(damf_ctx *c, int k, int nseg);
+hipError_t csr_compact(damf_ctx *c, Csr &g, double slack, int64_t min_free);
+hipError_t launch_csr_need(damf_ctx *c, const Csr &g, const NetEntry *net, const int32_t *rows,
+                           const int32_t *rowpos, int nrows, int64_t *need);
 hipError_t launch_csr_edit(damf_ctx *c, Csr &g, const NetEntry *net,
                            const int32_t *rows, const int32_t *rowpos,
                            int nrows, bool transposed);
@@ -183,6 +193,25 @@ hipError_t ppr_fixup(damf_ctx *c, int n_rows);
 hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64_t nfirst,
                     int64_t *rounds, int64_t *pushes, int64_t *edges);
 hipError_t ppr_residual_max(damf_ctx *c, double *out);
+
+// ---- spmm.hip: Y = A X with long rows split into fixed segments
+struct SpmmPlan {
+  int64_t nlong = 0, nseg = 0;     // rows longer than one segment, their segments
+  int32_t *long_row = nullptr;     // long rows
+  int64_t *long_seg0 = nullptr;    // first segment of each long row
+  int32_t *seg_row = nullptr, *seg_idx = nullptr;  // row and index of each segment
+  float *part = nullptr;           // partial row sums, nseg x ld_max
+  int ld_max = 0;
+};
+hipError_t spmm_plan_build(damf_ctx *c, const Csr &g, int kmax, SpmmPlan *p);
+void spmm_plan_free(SpmmPlan &p);
+hipError_t csr_spmm(const Csr &g, const SpmmPlan &p, const float *X, float *Y, int64_t n, int k,
+                    int ld, hipStream_t s);
+// One PPR propagation round: Rnew = (1 - alpha) D^-1 A Rold, Z += alpha Rold,
+// max |Rnew| into *maxbits (float bits, atomicMax).
+hipError_t ppr_pull_round(const Csr &g, const SpmmPlan &p, const float *Rold, float *Rnew,
+                          float *Z, int64_t n, int d, float alpha, unsigned *maxbits,
+                          hipStream_t s);
 
 // ---- rsvd.hip
 hipError_t rsvd_init(damf_ctx *c);

@@ -9,6 +9,8 @@
 // deleting an absent one change nothing.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <climits>
 
 #include "common.h"
@@ -234,22 +236,23 @@ __global__ __launch_bounds__(1024) void sort_rows_large_kernel(const int32_t *bi
   int32_t r = big[blockIdx.x];
   int32_t L = len[r];
   if (L > kLargeRow) {
-    // rows beyond LDS: bitonic network in global memory (rare: hub rows)
+    // rows beyond LDS: sorting network in global memory (rare: hub rows).
+    // Every comparator is ascending (i < p): the first one of each merge
+    // stage pairs i with its mirror i ^ (k - 1), the rest pair i with i ^ j.
+    // Positions >= L are a virtual +inf pad that no comparator moves, so
+    // nothing is ever written past the row.
     int32_t *seg = tmp + off[r];
     int P = 1;
     while (P < L) P <<= 1;
-    // pad is virtual: indices >= L compare as +inf
     for (int k = 2; k <= P; k <<= 1) {
       for (int j = k >> 1; j > 0; j >>= 1) {
         for (int i = threadIdx.x; i < P; i += 1024) {
-          int p = i ^ j;
-          if (p > i) {
-            int32_t a = (i < L) ? seg[i] : INT_MAX;
-            int32_t b = (p < L) ? seg[p] : INT_MAX;
-            bool up = (i & k) == 0;
-            if ((a > b) == up) {
-              if (i < L) seg[i] = b;
-              if (p < L) seg[p] = a;
+          const int p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
+          if (p > i && p < L) {
+            const int32_t a = seg[i], b = seg[p];
+            if (a > b) {
+              seg[i] = b;
+              seg[p] = a;
             }
           }
         }
@@ -292,6 +295,14 @@ __global__ void set_caps_kernel(int64_t n, const int32_t *len, int32_t *cap) {
   if (r >= n) return;
   int32_t l = len[r];
   cap[r] = l + (l >> 2) + 4;
+}
+
+// Pool entries for `used` reserved entries and `edges` edges: at least
+// slack * edges, and always a free quarter of the reservations (at least 2^20)
+// for rows that outgrow their reservation.
+int64_t pool_capacity(int64_t used, int64_t edges, double slack) {
+  const int64_t want = (int64_t)(slack * (double)edges) + (1 << 20);
+  return used + (want > used ? want - used : 0) + std::max<int64_t>(1 << 20, used / 4);
 }
 
 hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows, const int32_t *d_cols,
@@ -342,8 +353,7 @@ hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows, const int32_t *
   int64_t pool_used = 0;
   DAMF_HIP(hipMemcpyAsync(&pool_used, total, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   DAMF_HIP(hipStreamSynchronize(s));
-  int64_t want = (int64_t)(slack * (double)m2) + (1 << 20);
-  g.pool_cap = pool_used + (want > pool_used ? want - pool_used : 0) + (1 << 20);
+  g.pool_cap = pool_capacity(pool_used, m2, slack);
   DAMF_HIP(hipMalloc(&g.col, g.pool_cap * sizeof(int32_t)));
   copy_rows_kernel<<<ceil_div(n, 4), 256, 0, s>>>(n, off, tmpcol, g.start, g.len, g.col);
   DAMF_HIP(hipGetLastError());
@@ -935,13 +945,21 @@ hipError_t launch_batch_prepare(damf_ctx *c, int k, int nseg) {
 constexpr int kEditThreads = 256;
 constexpr int kEditStage = 8192;
 
+// A row that keeps fitting its reservation is edited in place: it is staged
+// (LDS up to kEditStage entries, else a slice of the global staging pool) and
+// written back.  A row that outgrows its reservation, or finds the staging
+// pool full, moves to fresh pool space (the old space is reclaimed by the
+// next compaction).
 __global__ __launch_bounds__(kEditThreads) void csr_edit_kernel(Csr g, const NetEntry *ent,
                                                                 const int32_t *rows,
                                                                 const int32_t *rowpos,
                                                                 int transposed,
-                                                                int32_t *overflow) {
+                                                                int32_t *overflow,
+                                                                int32_t *gstage,
+                                                                int64_t *gstage_top,
+                                                                int64_t gstage_cap) {
   __shared__ int32_t stage[kEditStage];
-  __shared__ int64_t s_newstart;
+  __shared__ int64_t s_newstart, s_gstage;
   __shared__ int32_t s_newcap;
   const int j = blockIdx.x;
   const int32_t R = rows[j];
@@ -953,9 +971,20 @@ __global__ __launch_bounds__(kEditThreads) void csr_edit_kernel(Csr g, const Net
   const int tot_ins = E[nr - 1].pad + (E[nr - 1].delta > 0) - base_ins;
   const int32_t newL = L + tot_ins - (nr - tot_ins);
   auto val = [&](int q) { return transposed ? E[q].row : E[q].col; };
-  const bool inplace = (newL <= C) && (L <= kEditStage);
+  const bool fits = newL <= C;
+  const bool lds = fits && (L <= kEditStage);
   if (threadIdx.x == 0) {
-    if (inplace) {
+    s_gstage = -1;
+    bool move = !fits;
+    if (fits && !lds) {
+      const int64_t at = (int64_t)atomicAdd((unsigned long long *)gstage_top,
+                                            (unsigned long long)L);
+      if (at + L <= gstage_cap)
+        s_gstage = at;
+      else
+        move = true;
+    }
+    if (!move) {
       s_newstart = S;
       s_newcap = C;
     } else {
@@ -970,13 +999,17 @@ __global__ __launch_bounds__(kEditThreads) void csr_edit_kernel(Csr g, const Net
       }
     }
   }
+  __syncthreads();
   const int32_t *old = g.col + S;
-  if (inplace) {
+  const int64_t gs = s_gstage;
+  if (lds) {
     for (int i = threadIdx.x; i < L; i += kEditThreads) stage[i] = old[i];
+  } else if (gs >= 0) {
+    for (int i = threadIdx.x; i < L; i += kEditThreads) gstage[gs + i] = old[i];
   }
   __syncthreads();
   if (s_newcap < 0) return;
-  const int32_t *src = inplace ? stage : old;
+  const int32_t *src = lds ? stage : (gs >= 0 ? gstage + gs : old);
   int32_t *dstrow = g.col + s_newstart;
   for (int i = threadIdx.x; i < L; i += kEditThreads) {
     int32_t x = src[i];
@@ -1013,12 +1046,76 @@ __global__ __launch_bounds__(kEditThreads) void csr_edit_kernel(Csr g, const Net
   }
 }
 
+// Pool space the edit of these rows may take: every row that outgrows its
+// reservation moves to newL + newL/2 + 8 fresh entries.
+__global__ void csr_need_kernel(Csr g, const NetEntry *ent, const int32_t *rows,
+                                const int32_t *rowpos, int nrows, int64_t *need) {
+  const int j = blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t v = 0;
+  if (j < nrows) {
+    const int32_t R = rows[j];
+    const int e0 = rowpos[j], nr = rowpos[j + 1] - e0;
+    const NetEntry *E = ent + e0;
+    const int tot_ins = E[nr - 1].pad + (E[nr - 1].delta > 0) - E[0].pad;
+    const int32_t newL = g.len[R] + tot_ins - (nr - tot_ins);
+    if (newL > g.cap[R]) v = newL + (newL >> 1) + 8;
+  }
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long *)need, (unsigned long long)v);
+}
+
+hipError_t launch_csr_need(damf_ctx *c, const Csr &g, const NetEntry *net, const int32_t *rows,
+                           const int32_t *rowpos, int nrows, int64_t *need) {
+  DAMF_HIP(hipMemsetAsync(need, 0, sizeof(int64_t), c->stream));
+  if (nrows <= 0) return hipSuccess;
+  csr_need_kernel<<<ceil_div(nrows, 256), 256, 0, c->stream>>>(g, net, rows, rowpos, nrows, need);
+  return hipGetLastError();
+}
+
 hipError_t launch_csr_edit(damf_ctx *c, Csr &g, const NetEntry *net, const int32_t *rows,
                            const int32_t *rowpos, int nrows, bool transposed) {
   if (nrows <= 0) return hipSuccess;
+  DAMF_HIP(hipMemsetAsync(c->ws.edit_stage_top, 0, sizeof(int64_t), c->stream));
   csr_edit_kernel<<<nrows, kEditThreads, 0, c->stream>>>(
-      g, net, rows, rowpos, transposed ? 1 : 0, &c->ws.hdr->pool_overflow);
+      g, net, rows, rowpos, transposed ? 1 : 0, &c->ws.hdr->pool_overflow, c->ws.edit_stage,
+      c->ws.edit_stage_top, kEditStagePool);
   return hipGetLastError();
+}
+
+// Rebuilds the pool compactly: every row gets a fresh reservation
+// (len + len/4 + 4) at its prefix-sum position, the space left by moved rows
+// is dropped, and the pool is sized as at build time for the current edges
+// with at least min_free free entries.
+hipError_t csr_compact(damf_ctx *c, Csr &g, double slack, int64_t min_free) {
+  hipStream_t s = c->stream;
+  const int64_t n = c->n;
+  int64_t *nstart = nullptr, *tmp_sums = nullptr, *total = nullptr;
+  int32_t *ncol = nullptr;
+  DAMF_HIP(hipMalloc(&nstart, n * sizeof(int64_t)));
+  DAMF_HIP(hipMalloc(&tmp_sums, (ceil_div(n, 1024) + 1) * sizeof(int64_t)));
+  DAMF_HIP(hipMalloc(&total, 2 * sizeof(int64_t)));
+  DAMF_HIP(hipMemsetAsync(total + 1, 0, sizeof(int64_t), s));
+  sum_len_kernel<<<ceil_div(n, 256), 256, 0, s>>>(n, g.len, total + 1);
+  DAMF_HIP(exclusive_scan(CapOf{g.len}, n, nstart, tmp_sums, total, s));
+  int64_t h[2] = {0, 0};
+  DAMF_HIP(hipMemcpyAsync(h, total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+  DAMF_HIP(hipStreamSynchronize(s));
+  const int64_t pool_used = h[0], nnz = h[1];
+  const int64_t cap = std::max(pool_capacity(pool_used, nnz, slack), pool_used + min_free);
+  DAMF_HIP(hipMalloc(&ncol, cap * sizeof(int32_t)));
+  copy_rows_kernel<<<ceil_div(n, 4), 256, 0, s>>>(n, g.start, g.col, nstart, g.len, ncol);
+  set_caps_kernel<<<ceil_div(n, 256), 256, 0, s>>>(n, g.len, g.cap);
+  DAMF_HIP(hipGetLastError());
+  DAMF_HIP(hipMemcpyAsync(g.start, nstart, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
+  DAMF_HIP(hipMemcpyAsync(g.top, &h[0], sizeof(int64_t), hipMemcpyHostToDevice, s));
+  DAMF_HIP(hipStreamSynchronize(s));
+  (void)hipFree(g.col);
+  g.col = ncol;
+  g.pool_cap = cap;
+  (void)hipFree(nstart);
+  (void)hipFree(tmp_sums);
+  (void)hipFree(total);
+  return hipSuccess;
 }
 
 }  // namespace damf

@@ -30,63 +30,6 @@ namespace {
 
 constexpr int kRowsPerBlock = 4;  // one wave per row
 
-// One synchronous propagation round over all rows (pull form, out-CSR).
-// Waves stride over rows; the block's max |R'| goes out with one atomic.
-__global__ __launch_bounds__(256) void pull_round_kernel(Csr g, const float *__restrict__ Rold,
-                                                         float *__restrict__ Rnew,
-                                                         float *__restrict__ Z, int64_t n, int d,
-                                                         float alpha, unsigned *maxbits) {
-  __shared__ float bmax[4];
-  const int lane = threadIdx.x & 63;
-  const bool c0 = lane < d, c1 = lane + 64 < d;
-  float m = 0.f;
-  const int64_t stride = (int64_t)gridDim.x * kRowsPerBlock;
-  for (int64_t u = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6); u < n; u += stride) {
-    const int32_t L = g.len[u];
-    const int32_t *row = g.col + g.start[u];
-    float a0 = 0.f, a1 = 0.f;
-    int32_t e = 0;
-    for (; e + 4 <= L; e += 4) {
-      const int64_t v0 = row[e], v1 = row[e + 1], v2 = row[e + 2], v3 = row[e + 3];
-      if (c0) {
-        a0 += Rold[v0 * d + lane] + Rold[v1 * d + lane];
-        a0 += Rold[v2 * d + lane] + Rold[v3 * d + lane];
-      }
-      if (c1) {
-        a1 += Rold[v0 * d + lane + 64] + Rold[v1 * d + lane + 64];
-        a1 += Rold[v2 * d + lane + 64] + Rold[v3 * d + lane + 64];
-      }
-    }
-    for (; e < L; ++e) {
-      const int64_t v = row[e];
-      if (c0) a0 += Rold[v * d + lane];
-      if (c1) a1 += Rold[v * d + lane + 64];
-    }
-    const float scale = (L > 0) ? (1.f - alpha) / (float)L : 0.f;
-    if (c0) {
-      const int64_t i = u * d + lane;
-      Z[i] += alpha * Rold[i];
-      const float r = a0 * scale;
-      Rnew[i] = r;
-      m = fmaxf(m, fabsf(r));
-    }
-    if (c1) {
-      const int64_t i = u * d + lane + 64;
-      Z[i] += alpha * Rold[i];
-      const float r = a1 * scale;
-      Rnew[i] = r;
-      m = fmaxf(m, fabsf(r));
-    }
-  }
-  m = wave_max(m);
-  if (lane == 0) bmax[threadIdx.x >> 6] = m;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const float b = fmaxf(fmaxf(bmax[0], bmax[1]), fmaxf(bmax[2], bmax[3]));
-    if (b > 0.f) atomicMax(maxbits, __float_as_uint(b));
-  }
-}
-
 // Structural fix-up for each changed out-row u (before the CSR edit; before
 // or after the chain kernel, which adds the same change to U_b and R, so
 // alpha (R - X) is unchanged; never while a push runs):
@@ -158,16 +101,71 @@ __global__ __launch_bounds__(256) void select_kernel(const int32_t *cand, int64_
   if (threadIdx.x < s_cnt) frontier[s_base + threadIdx.x] = s_list[threadIdx.x];
 }
 
+constexpr int kCandBuf = 1024;  // per-block LDS list of new candidates
+
+// Spreads (1 - alpha) r / deg(u) into R[u] for the in-neighbours u in
+// row[0 .. cnt) of a pushed node (cnt <= 64, one neighbour per lane for the
+// first-touch stamp).  New candidates go to the block's LDS list (overflow
+// straight to next_cand).
+__device__ __forceinline__ void spread64(const int32_t *row, int cnt, const int32_t *outdeg,
+                                         float *R, int d, float alpha, float r0, float r1,
+                                         int32_t round, int32_t *stamp, int32_t *s_list,
+                                         int *s_cnt, int32_t *next_cand, int64_t *counters) {
+  const int lane = threadIdx.x & 63;
+  const bool c0 = lane < d, c1 = lane + 64 < d;
+  const int32_t myu = (lane < cnt) ? row[lane] : -1;
+  bool fresh = false;
+  if (myu >= 0) fresh = atomicExch(&stamp[myu], round) != round;
+  const unsigned long long fm = __ballot(fresh);
+  if (fm) {
+    int base = 0;
+    if (lane == 0) base = atomicAdd(s_cnt, __popcll(fm));
+    base = __shfl(base, 0, 64);
+    if (fresh) {
+      const int at = base + __popcll(fm & ((1ull << lane) - 1ull));
+      if (at < kCandBuf) {
+        s_list[at] = myu;
+      } else {
+        const unsigned long long g = atomicAdd((unsigned long long *)&counters[2], 1ull);
+        next_cand[g] = myu;
+      }
+    }
+  }
+  for (int q = 0; q < cnt; ++q) {
+    const int32_t u = __shfl(myu, q, 64);
+    const float sc = (1.f - alpha) / (float)outdeg[u];
+    if (c0) atomicAdd(&R[(int64_t)u * d + lane], sc * r0);
+    if (c1) atomicAdd(&R[(int64_t)u * d + lane + 64], sc * r1);
+  }
+}
+
+__device__ __forceinline__ void flush_candidates(const int32_t *s_list, int s_cnt,
+                                                 unsigned long long s_edges,
+                                                 int32_t *next_cand, int64_t *counters,
+                                                 unsigned long long *s_base) {
+  const int cnt = min(s_cnt, kCandBuf);
+  if (threadIdx.x == 0) {
+    *s_base = cnt ? atomicAdd((unsigned long long *)&counters[2], (unsigned long long)cnt) : 0;
+    if (s_edges) atomicAdd((unsigned long long *)&counters[3], s_edges);
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < cnt; i += 256) next_cand[*s_base + i] = s_list[i];
+}
+
 // Push every frontier node: take R[v] atomically, Z_b[v] += alpha R[v], and
 // spread (1 - alpha) R[v] / deg(u) to each in-neighbour u (in-CSR row v).
-// New candidates (first touch of u in this round, by stamp) are gathered in
-// LDS and appended with one global atomic per block.
-constexpr int kCandBuf = 1024;
+// A node with more than kHeavy in-neighbours is not spread here: its taken
+// residual goes to hbuf and its row to segments of kSegEdges neighbours that
+// spread_heavy_kernel spreads with one wave each.  Counters: [1] frontier,
+// [2] next candidates, [3] edges, [4] heavy nodes, [5] heavy segments.
+constexpr int kHeavy = 2048;
+constexpr int kSegEdges = 256;
 __global__ __launch_bounds__(256) void push_kernel(Csr gin, const int32_t *outdeg,
                                                    const int32_t *frontier, int64_t nf, float *R,
                                                    float *Z, int d, float alpha, int32_t round,
                                                    int32_t *stamp, int32_t *next_cand,
-                                                   int64_t *counters) {
+                                                   int64_t *counters, float *hbuf,
+                                                   int32_t *hnode, int2 *hseg) {
   __shared__ int32_t s_list[kCandBuf];
   __shared__ int s_cnt;
   __shared__ unsigned long long s_edges, s_base;
@@ -194,44 +192,65 @@ __global__ __launch_bounds__(256) void push_kernel(Csr gin, const int32_t *outde
     }
     const int32_t L = gin.len[v];
     const int32_t *row = gin.col + gin.start[v];
-    for (int32_t e0 = 0; e0 < L; e0 += 64) {
-      // one neighbour per lane for the stamp check, then the wave updates rows
-      const int32_t myu = (e0 + lane < L) ? row[e0 + lane] : -1;
-      bool fresh = false;
-      if (myu >= 0) fresh = atomicExch(&stamp[myu], round) != round;
-      const unsigned long long fm = __ballot(fresh);
-      if (fm) {
-        int base = 0;
-        if (lane == 0) base = atomicAdd(&s_cnt, __popcll(fm));
-        base = __shfl(base, 0, 64);
-        if (fresh) {
-          const int at = base + __popcll(fm & ((1ull << lane) - 1ull));
-          if (at < kCandBuf) {
-            s_list[at] = myu;
-          } else {
-            const unsigned long long g = atomicAdd((unsigned long long *)&counters[2], 1ull);
-            next_cand[g] = myu;
-          }
-        }
+    if (L > kHeavy) {
+      int h = 0, sg = 0;
+      const int ns = (L + kSegEdges - 1) / kSegEdges;
+      if (lane == 0) {
+        h = (int)atomicAdd((unsigned long long *)&counters[4], 1ull);
+        sg = (int)atomicAdd((unsigned long long *)&counters[5], (unsigned long long)ns);
       }
-      const int cnt = min(64, L - e0);
-      for (int q = 0; q < cnt; ++q) {
-        const int32_t u = __shfl(myu, q, 64);
-        const float s = (1.f - alpha) / (float)outdeg[u];
-        if (c0) atomicAdd(&R[(int64_t)u * d + lane], s * r0);
-        if (c1) atomicAdd(&R[(int64_t)u * d + lane + 64], s * r1);
-      }
+      h = __shfl(h, 0, 64);
+      sg = __shfl(sg, 0, 64);
+      if (c0) hbuf[(int64_t)h * d + lane] = r0;
+      if (c1) hbuf[(int64_t)h * d + lane + 64] = r1;
+      if (lane == 0) hnode[h] = v;
+      for (int q = lane; q < ns; q += 64) hseg[sg + q] = make_int2(h, q);
+    } else {
+      for (int32_t e0 = 0; e0 < L; e0 += 64)
+        spread64(row + e0, min(64, L - e0), outdeg, R, d, alpha, r0, r1, round, stamp, s_list,
+                 &s_cnt, next_cand, counters);
+      if (lane == 0) atomicAdd(&s_edges, (unsigned long long)L);
     }
-    if (lane == 0) atomicAdd(&s_edges, (unsigned long long)L);
   }
   __syncthreads();
-  const int cnt = min(s_cnt, kCandBuf);
+  flush_candidates(s_list, s_cnt, s_edges, next_cand, counters, &s_base);
+}
+
+// One wave per segment of a heavy node's in-row (grid-stride over the
+// segments the push kernel listed; the count is read on the device).
+__global__ __launch_bounds__(256) void spread_heavy_kernel(Csr gin, const int32_t *outdeg,
+                                                           float *R, int d, float alpha,
+                                                           int32_t round, int32_t *stamp,
+                                                           int32_t *next_cand, int64_t *counters,
+                                                           const float *hbuf,
+                                                           const int32_t *hnode,
+                                                           const int2 *hseg) {
+  __shared__ int32_t s_list[kCandBuf];
+  __shared__ int s_cnt;
+  __shared__ unsigned long long s_edges, s_base;
+  const int lane = threadIdx.x & 63;
   if (threadIdx.x == 0) {
-    s_base = cnt ? atomicAdd((unsigned long long *)&counters[2], (unsigned long long)cnt) : 0;
-    if (s_edges) atomicAdd((unsigned long long *)&counters[3], s_edges);
+    s_cnt = 0;
+    s_edges = 0;
   }
   __syncthreads();
-  for (int i = threadIdx.x; i < cnt; i += 256) next_cand[s_base + i] = s_list[i];
+  const int64_t nseg = counters[5];
+  for (int64_t sgi = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6); sgi < nseg;
+       sgi += (int64_t)gridDim.x * kRowsPerBlock) {
+    const int2 sg = hseg[sgi];
+    const int32_t v = hnode[sg.x];
+    const float r0 = (lane < d) ? hbuf[(int64_t)sg.x * d + lane] : 0.f;
+    const float r1 = (lane + 64 < d) ? hbuf[(int64_t)sg.x * d + lane + 64] : 0.f;
+    const int32_t L = gin.len[v];
+    const int32_t b = sg.y * kSegEdges, e = min(L, b + kSegEdges);
+    const int32_t *row = gin.col + gin.start[v];
+    for (int32_t e0 = b; e0 < e; e0 += 64)
+      spread64(row + e0, min(64, e - e0), outdeg, R, d, alpha, r0, r1, round, stamp, s_list,
+               &s_cnt, next_cand, counters);
+    if (lane == 0) atomicAdd(&s_edges, (unsigned long long)(e - b));
+  }
+  __syncthreads();
+  flush_candidates(s_list, s_cnt, s_edges, next_cand, counters, &s_base);
 }
 
 __global__ void abs_max_kernel(const float *R, int64_t count, unsigned *maxbits) {
@@ -262,6 +281,8 @@ hipError_t ppr_init(damf_ctx *c) {
   abs_max_kernel<<<1024, 256, 0, s>>>(c->R, (int64_t)n * d, maxbits);
   DAMF_HIP(hipMemcpyAsync(&h, maxbits, sizeof(unsigned), hipMemcpyDeviceToHost, s));
   DAMF_HIP(hipStreamSynchronize(s));
+  SpmmPlan plan;
+  DAMF_HIP(spmm_plan_build(c, c->out, d, &plan));
   float *Rcur = c->R, *Rnxt = Rn;
   for (int round = 0; round < 100000; ++round) {
     float mx;
@@ -269,9 +290,7 @@ hipError_t ppr_init(damf_ctx *c) {
     if (!((double)mx > c->cfg.eps)) break;
     DAMF_HIP(hipMemsetAsync(maxbits, 0, sizeof(unsigned), s));
     DAMF_HIP(hipEventRecord(c->ev_k[0], s));
-    const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n, kRowsPerBlock), 8192);
-    pull_round_kernel<<<grid, 256, 0, s>>>(c->out, Rcur, Rnxt, c->Zb, n, d, alpha, maxbits);
-    DAMF_HIP(hipGetLastError());
+    DAMF_HIP(ppr_pull_round(c->out, plan, Rcur, Rnxt, c->Zb, n, d, alpha, maxbits, s));
     DAMF_HIP(hipEventRecord(c->ev_k[1], s));
     DAMF_HIP(hipMemcpyAsync(&h, maxbits, sizeof(unsigned), hipMemcpyDeviceToHost, s));
     DAMF_HIP(hipStreamSynchronize(s));
@@ -288,6 +307,7 @@ hipError_t ppr_init(damf_ctx *c) {
   }
   if (Rcur != c->R) DAMF_HIP(hipMemcpyAsync(c->R, Rcur, bytes, hipMemcpyDeviceToDevice, s));
   DAMF_HIP(hipStreamSynchronize(s));
+  spmm_plan_free(plan);
   DAMF_HIP(hipFree(Rn));
   return hipSuccess;
 }
@@ -312,10 +332,29 @@ hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64
   int32_t *cand = w.cand, *next = w.cand2, *front = w.frontier;
   if (first_rows && ncand > 0)
     DAMF_HIP(hipMemcpyAsync(cand, first_rows, ncand * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  // heavy-node buffers: at most edges / kHeavy nodes have more than kHeavy
+  // in-neighbours, and their rows hold at most edges / kSegEdges + nodes segments
+  const int64_t edges_cap = c->in.pool_cap;
+  const int64_t hcap = edges_cap / kHeavy + 64;
+  const int64_t scap = edges_cap / kSegEdges + hcap;
+  if (w.heavy_cap < hcap || w.hseg_cap < scap) {
+    (void)hipFree(w.hbuf);
+    (void)hipFree(w.hnode);
+    (void)hipFree(w.hseg);
+    w.hbuf = nullptr;
+    w.hnode = nullptr;
+    w.hseg = nullptr;
+    w.heavy_cap = w.hseg_cap = 0;
+    DAMF_HIP(hipMalloc(&w.hbuf, hcap * d * sizeof(float)));
+    DAMF_HIP(hipMalloc(&w.hnode, hcap * sizeof(int32_t)));
+    DAMF_HIP(hipMalloc(&w.hseg, scap * sizeof(int2)));
+    w.heavy_cap = hcap;
+    w.hseg_cap = scap;
+  }
   bool all = (first_rows == nullptr);
   bool first = true;
   while (ncand > 0) {
-    DAMF_HIP(hipMemsetAsync(w.counters, 0, 4 * sizeof(int64_t), s));
+    DAMF_HIP(hipMemsetAsync(w.counters, 0, 6 * sizeof(int64_t), s));
     // the caller's list may repeat rows; later rounds' lists are unique by stamp
     const int32_t dedup = (first && !all) ? (int32_t)(++c->round_counter & 0x7fffffff) : -1;
     select_kernel<<<ceil_div(ncand, kRowsPerBlock), 256, 0, s>>>(
@@ -329,9 +368,12 @@ hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64
     if (nf == 0) break;
     const int32_t round = (int32_t)(++c->round_counter & 0x7fffffff);
     DAMF_HIP(hipEventRecord(c->ev_k[0], s));
-    push_kernel<<<ceil_div(nf, kRowsPerBlock), 256, 0, s>>>(c->in, c->out.len, front, nf, c->R,
-                                                            c->Zb, d, (float)c->cfg.alpha, round,
-                                                            w.stamp, next, w.counters);
+    push_kernel<<<ceil_div(nf, kRowsPerBlock), 256, 0, s>>>(
+        c->in, c->out.len, front, nf, c->R, c->Zb, d, (float)c->cfg.alpha, round, w.stamp, next,
+        w.counters, w.hbuf, w.hnode, reinterpret_cast<int2 *>(w.hseg));
+    spread_heavy_kernel<<<1024, 256, 0, s>>>(c->in, c->out.len, c->R, d, (float)c->cfg.alpha,
+                                             round, w.stamp, next, w.counters, w.hbuf, w.hnode,
+                                             reinterpret_cast<const int2 *>(w.hseg));
     DAMF_HIP(hipGetLastError());
     DAMF_HIP(hipEventRecord(c->ev_k[1], s));
     DAMF_HIP(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));

@@ -7,7 +7,7 @@
 //   B^T = A^T Q = Q2 R2,   svd(R2^T) = Ut S Vt^T,
 //   U = Q Ut[:, :d],  V = Q2 Vt[:, :d],  Sigma = S[:d]
 //
-// Kernels: sketch generation, CSR SpMM of width l = d + p, tall-skinny
+// Kernels: sketch generation, CSR SpMM of width l = d + p (spmm.hip), tall-skinny
 // Householder QR (recursive TSQR over blocks of 512 rows), an FP64 one-sided
 // Jacobi SVD of the l x l factor in one workgroup, and the n x l by l x d
 // rotation GEMM on MFMA (FP32 in, FP32 accumulate).
@@ -42,37 +42,6 @@ __global__ void sketch_kernel(float *Om, int64_t n, int l, int ld, uint64_t seed
   const int j = (int)(e - i * l);
   const uint64_t ctr = (seed << 40) ^ ((uint64_t)i * (uint64_t)l + (uint64_t)j);
   Om[i * ld + j] = (splitmix64_out(ctr) >> 63) ? -1.f : 1.f;
-}
-
-// ---------------------------------------------------------------- SpMM
-// Y[u][0..l) = sum over the CSR row u of X[v][0..l); one wave per row, lanes
-// own columns lane, lane + 64, lane + 128.
-__global__ __launch_bounds__(256) void spmm_kernel(Csr g, const float *__restrict__ X,
-                                                   float *__restrict__ Y, int64_t n, int l,
-                                                   int ld) {
-  const int lane = threadIdx.x & 63;
-  const int64_t u = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (u >= n) return;
-  const int32_t L = g.len[u];
-  const int32_t *row = g.col + g.start[u];
-  const bool c0 = lane < l, c1 = lane + 64 < l, c2 = lane + 128 < l;
-  float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-  int32_t e = 0;
-  for (; e + 2 <= L; e += 2) {
-    const int64_t v0 = row[e], v1 = row[e + 1];
-    if (c0) a0 += X[v0 * ld + lane] + X[v1 * ld + lane];
-    if (c1) a1 += X[v0 * ld + lane + 64] + X[v1 * ld + lane + 64];
-    if (c2) a2 += X[v0 * ld + lane + 128] + X[v1 * ld + lane + 128];
-  }
-  for (; e < L; ++e) {
-    const int64_t v = row[e];
-    if (c0) a0 += X[v * ld + lane];
-    if (c1) a1 += X[v * ld + lane + 64];
-    if (c2) a2 += X[v * ld + lane + 128];
-  }
-  if (c0) Y[u * ld + lane] = a0;
-  if (c1) Y[u * ld + lane + 64] = a1;
-  if (c2) Y[u * ld + lane + 128] = a2;
 }
 
 // ---------------------------------------------------------------- TSQR
@@ -460,11 +429,6 @@ hipError_t tsqr(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) 
   return err;
 }
 
-hipError_t spmm(const Csr &g, const float *X, float *Y, int64_t n, int l, int ld, hipStream_t s) {
-  spmm_kernel<<<ceil_div(n, 4), 256, 0, s>>>(g, X, Y, n, l, ld);
-  return hipGetLastError();
-}
-
 }  // namespace
 
 hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B, int d, float *C,
@@ -495,15 +459,21 @@ hipError_t rsvd_init(damf_ctx *c) {
   DAMF_HIP(hipMalloc(&Hf, (size_t)l * d * sizeof(float)));
   sketch_kernel<<<ceil_div(n * l, 256), 256, 0, s>>>(T, n, l, ld, c->cfg.seed);
   DAMF_HIP(hipGetLastError());
-  DAMF_HIP(spmm(c->out, T, Y, n, l, ld, s));  // Y = A Omega
+  SpmmPlan pout, pin;
+  DAMF_HIP(spmm_plan_build(c, c->out, ld, &pout));
+  DAMF_HIP(spmm_plan_build(c, c->in, ld, &pin));
+  DAMF_HIP(csr_spmm(c->out, pout, T, Y, n, l, ld, s));  // Y = A Omega
   DAMF_HIP(tsqr(Y, n, l, ld, Rt, s));
   for (int it = 0; it < c->cfg.power_iters; ++it) {
-    DAMF_HIP(spmm(c->in, Y, T, n, l, ld, s));  // A^T Q
+    DAMF_HIP(csr_spmm(c->in, pin, Y, T, n, l, ld, s));  // A^T Q
     DAMF_HIP(tsqr(T, n, l, ld, Rt, s));
-    DAMF_HIP(spmm(c->out, T, Y, n, l, ld, s));  // A Q
+    DAMF_HIP(csr_spmm(c->out, pout, T, Y, n, l, ld, s));  // A Q
     DAMF_HIP(tsqr(Y, n, l, ld, Rt, s));
   }
-  DAMF_HIP(spmm(c->in, Y, T, n, l, ld, s));  // B^T = A^T Q
+  DAMF_HIP(csr_spmm(c->in, pin, Y, T, n, l, ld, s));  // B^T = A^T Q
+  DAMF_HIP(hipStreamSynchronize(s));
+  spmm_plan_free(pout);
+  spmm_plan_free(pin);
   DAMF_HIP(tsqr(T, n, l, ld, Rt, s));        // T = Q2, Rt = R2
   small_svd_kernel<<<1, 1024, 0, s>>>(Rt, l, d, E, th, H);
   DAMF_HIP(hipGetLastError());

@@ -65,3 +65,55 @@ def test_rsvd_matches_oracle_same_sketch(damf):
     _say(f"  sigma err {err_s:.2e} product err {err_p:.2e} orth {eo:.2e}")
     assert err_s <= 1e-5 and err_p <= 1e-5 and eo <= 1e-5
     ctx.close()
+
+
+def _hub_graph(n, seed):
+    """Sparse random graph plus hub rows and columns far longer than one SpMM segment."""
+    rng = np.random.default_rng(seed)
+    s = [rng.integers(0, n, 6 * n)]
+    t = [rng.integers(0, n, 6 * n)]
+    for h, deg in ((3, 9000), (17, 2500), (41, 700)):
+        s += [np.full(deg, h), rng.integers(0, n, deg)]
+        t += [rng.integers(0, n, deg), np.full(deg, h + 1)]
+    s, t = np.concatenate(s).astype(np.int32), np.concatenate(t).astype(np.int32)
+    g = EdgeSet(n, True, s, t)
+    ip, ix = g.csr()
+    src = np.repeat(np.arange(n), np.diff(ip)).astype(np.int32)
+    return src, ix.astype(np.int32)
+
+
+def test_rsvd_parity_with_hub_rows(damf):
+    """Rows split into SpMM segments (out- and in-CSR) give the oracle's randomized t-SVD."""
+    _say("case rsvd_hub_rows")
+    n, d, p, q, seed = 6000, 16, 10, 2, 9
+    s0, t0 = _hub_graph(n, 4)
+    A = sp.csr_matrix((np.ones(len(s0)), (s0, t0)), shape=(n, n))
+    assert np.diff(A.indptr).max() > 2000 and np.diff(A.tocsc().indptr).max() > 2000
+    U, s, V = tsvd_randomized(A, d, p, q, seed)
+    cfg = damf.default_config(n, d, directed=True, alpha=1.0, oversample=p, power_iters=q, seed=seed)
+    ctx = damf.Context.init(cfg, s0, t0)
+    sg = ctx.singular_values()
+    X, Y = ctx.query("X"), ctx.query("Y")
+    err_s = np.abs(sg - s).max() / s[0]
+    err_p = product_rel_err(X, Y, U * np.sqrt(s), V * np.sqrt(s))
+    _say(f"  sigma err {err_s:.2e} product err {err_p:.2e}")
+    assert err_s <= 1e-5 and err_p <= 1e-5
+    ctx.close()
+
+
+def test_ppr_init_with_hub_rows(damf):
+    """Propagation rounds over split rows keep the push invariant X - R = (Z - (1-a) P Z) / a."""
+    _say("case ppr_init_hub_rows")
+    n, d, alpha = 6000, 8, 0.15
+    s0, t0 = _hub_graph(n, 5)
+    cfg = damf.default_config(n, d, directed=True, alpha=alpha, eps=1e-6, oversample=4, seed=2)
+    ctx = damf.Context.init(cfg, s0, t0)
+    st = ctx.export_state()
+    A = sp.csr_matrix((np.ones(len(s0)), (s0, t0)), shape=(n, n))
+    deg = np.asarray(A.sum(axis=1)).ravel()
+    Pm = sp.diags(np.where(deg > 0, 1.0 / np.maximum(deg, 1), 0.0)) @ A
+    err = np.abs((st["Ub"] - st["R"]) - (st["Zb"] - (1 - alpha) * (Pm @ st["Zb"])) / alpha).max()
+    _say(f"  invariant err {err:.2e} max|R| {ctx.residual_max():.2e}")
+    assert err <= 2e-5 * max(1.0, np.abs(st["Ub"]).max())
+    assert ctx.residual_max() <= 1e-6
+    ctx.close()

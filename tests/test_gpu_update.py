@@ -184,3 +184,83 @@ def test_wide_core_parity(damf, d, r):
         assert err_s <= 1e-5 and err_p <= 1e-5
     _assert_csr(ctx, orc)
     ctx.close()
+
+
+def test_csr_build_hub_rows_beyond_lds(damf):
+    """Rows longer than the LDS sort (32768 entries) take the global sorting network."""
+    _say("case csr_hub_rows")
+    rng = np.random.default_rng(8)
+    n = 50000
+    hub_out = rng.integers(0, n, 80000)           # node 7 -> ~40k distinct targets, duplicates
+    hub_in = rng.integers(0, n, 70000)            # ~38k distinct sources -> node 11
+    mid = rng.integers(0, n, 5000)                # a row between 2048 and 32768 entries
+    s0 = np.concatenate([np.full(len(hub_out), 7), hub_in, np.full(len(mid), 3),
+                         rng.integers(0, n, 20000)]).astype(np.int32)
+    t0 = np.concatenate([hub_out, np.full(len(hub_in), 11), mid,
+                         rng.integers(0, n, 20000)]).astype(np.int32)
+    perm = rng.permutation(len(s0))
+    s0, t0 = s0[perm], t0[perm]
+    cfg = damf.default_config(n, 4, directed=True, alpha=1.0, max_core_rank=4, max_side=8,
+                              oversample=4, power_iters=1)
+    ctx = damf.Context.init(cfg, s0, t0)
+    g = EdgeSet(n, True, s0, t0)
+    for t in (False, True):
+        ip, ix = ctx.export_csr(transpose=t)
+        rp, rx = g.csr(transpose=t)
+        assert np.array_equal(ip, rp) and np.array_equal(ix, rx), t
+        assert np.diff(rp).max() > 32768, t
+    ctx.close()
+
+
+def test_csr_long_row_edits_in_place(damf):
+    """Edits of rows longer than the LDS stage go through the global staging pool."""
+    _say("case csr_long_row_edits")
+    rng = np.random.default_rng(12)
+    n = 30000
+    s0 = np.concatenate([np.full(20000, 5), rng.integers(0, n, 15000),
+                         rng.integers(0, n, 30000)]).astype(np.int32)
+    t0 = np.concatenate([rng.permutation(n)[:20000], np.full(15000, 9),
+                         rng.integers(0, n, 30000)]).astype(np.int32)
+    cfg = damf.default_config(n, 4, directed=True, alpha=1.0, max_core_rank=8, max_side=16,
+                              oversample=4, power_iters=1)
+    ctx = damf.Context.init(cfg, s0, t0)
+    g = EdgeSet(n, True, s0, t0)
+    for b in range(6):
+        k = 400
+        s = np.where(rng.random(k) < 0.5, 5, rng.integers(0, n, k)).astype(np.int32)
+        t = np.where(s == 5, rng.integers(0, n, k), np.where(rng.random(k) < 0.5, 9,
+                                                            rng.integers(0, n, k))).astype(np.int32)
+        op = rng.choice(np.array([-1, 1], dtype=np.int8), k)
+        g.apply(s, t, op)
+        ctx.update(s, t, op)
+        for tr in (False, True):
+            ip, ix = ctx.export_csr(transpose=tr)
+            rp, rx = g.csr(transpose=tr)
+            assert np.array_equal(ip, rp) and np.array_equal(ix, rx), (b, tr)
+    ctx.close()
+
+
+def test_csr_pool_compaction(damf):
+    """Rows that keep outgrowing their reservation leak pool space until a compaction."""
+    _say("case csr_pool_compaction")
+    rng = np.random.default_rng(13)
+    n = 4000
+    s0, t0 = rng.integers(0, n, 2000).astype(np.int32), rng.integers(0, n, 2000).astype(np.int32)
+    cfg = damf.default_config(n, 8, directed=True, alpha=1.0, max_core_rank=64, max_side=64,
+                              oversample=4, power_iters=1)
+    ctx = damf.Context.init(cfg, s0, t0)
+    g = EdgeSet(n, True, s0, t0)
+    for b in range(60):
+        k = 8192
+        s = rng.integers(0, n, k).astype(np.int32)
+        t = rng.integers(0, n, k).astype(np.int32)
+        op = np.ones(k, dtype=np.int8)
+        g.apply(s, t, op)
+        ctx.update(s, t, op)
+        if b % 20 == 19 or b == 59:
+            for tr in (False, True):
+                ip, ix = ctx.export_csr(transpose=tr)
+                rp, rx = g.csr(transpose=tr)
+                assert np.array_equal(ip, rp) and np.array_equal(ix, rx), (b, tr)
+            _say(f"  batch {b}: {len(ix)} edges")
+    ctx.close()
