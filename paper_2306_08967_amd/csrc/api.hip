@@ -133,7 +133,8 @@ void free_ctx(damf_ctx *c) {
                   c->ws.cstats, c->ws.scratch, c->ws.counters, c->ws.stamp, c->ws.cand,
                   c->ws.cand2, c->ws.frontier, c->ws.unit_seg, c->ws.units_comb,
                   c->ws.seg_end, c->ws.seg_stats, c->ws.pend_rows, c->ws.edit_stage,
-                  c->ws.edit_stage_top, c->ws.hbuf, c->ws.hnode, c->ws.hseg};
+                  c->ws.edit_stage_top, c->ws.hbuf, c->ws.hnode, c->ws.hseg,
+                  c->ws.push_ring, c->ws.push_log};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->ws.hdr_host) (void)hipHostFree(c->ws.hdr_host);
@@ -141,6 +142,7 @@ void free_ctx(damf_ctx *c) {
   if (c->ws.counters_host) (void)hipHostFree(c->ws.counters_host);
   if (c->ws.dscratch_host) (void)hipHostFree(c->ws.dscratch_host);
   if (c->ws.seg_stats_host) (void)hipHostFree(c->ws.seg_stats_host);
+  if (c->ws.push_log_host) (void)hipHostFree(c->ws.push_log_host);
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->ev_k)

@@ -87,6 +87,9 @@ struct Workspace {
   int32_t *hnode = nullptr;      // their node ids
   void *hseg = nullptr;          // (heavy node, segment) pairs (int2)
   int64_t heavy_cap = 0, hseg_cap = 0;
+  int64_t *push_ring = nullptr;  // per-round push counters (ring of sets)
+  int64_t *push_log = nullptr;   // per round: frontier size, edges
+  int64_t *push_log_host = nullptr;  // pinned
   int32_t *edit_stage = nullptr;     // staging pool for in-place edits of long rows
   int64_t *edit_stage_top = nullptr; // its bump counter (reset per edit launch)
   NetEntry *chunk_ent = nullptr; // entries of each chunk, chunk after chunk

@@ -29,6 +29,11 @@ namespace damf {
 namespace {
 
 constexpr int kRowsPerBlock = 4;  // one wave per row
+constexpr int kPushCounters = 8;  // per round: [1] frontier, [2] next candidates,
+                                  // [3] edges, [4] heavy nodes, [5] heavy segments
+constexpr int kPushRing = 4;      // rounds in flight share a ring of counter sets
+constexpr int kPushGroup = 4;     // rounds queued per host check
+constexpr int kMaxPushRounds = 65536;
 
 // Structural fix-up for each changed out-row u (before the CSR edit; before
 // or after the chain kernel, which adds the same change to U_b and R, so
@@ -66,39 +71,57 @@ __global__ __launch_bounds__(256) void fixup_kernel(Csr g, const NetEntry *net,
 // Frontier selection: candidates with max |R| > eps (compared in FP64).
 // Appends are compacted per block (one global atomic per block).  With
 // dedup_round >= 0 a candidate listed twice is taken once (stamp exchange):
-// a node pushed twice in one round would race on its Z_b row.
-__global__ __launch_bounds__(256) void select_kernel(const int32_t *cand, int64_t ncand,
-                                                     const float *R, int d, double eps,
-                                                     int32_t *stamp, int32_t dedup_round,
-                                                     int32_t *frontier, int64_t *counters) {
+// a node pushed twice in one round would race on its Z_b row.  The candidate
+// count comes from the previous round's counters on the device (or from the
+// host for the first round), so rounds queue without host round trips.
+// Block 0 also clears the next round's counters and logs the previous
+// round's frontier and edge counts.
+__global__ __launch_bounds__(256) void select_kernel(const int32_t *cand, const int64_t *ncand_dev,
+                                                     int64_t ncand_host, const float *R, int d,
+                                                     double eps, int32_t *stamp,
+                                                     int32_t dedup_round, int32_t *frontier,
+                                                     int64_t *cnt_r, int64_t *cnt_next,
+                                                     const int64_t *cnt_prev, int64_t *log_prev) {
   __shared__ int s_cnt;
   __shared__ int32_t s_list[kRowsPerBlock];
   __shared__ unsigned long long s_base;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  if (threadIdx.x == 0) s_cnt = 0;
-  __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * kRowsPerBlock + w;
-  bool take = j < ncand;
-  int32_t v = 0;
-  if (take) {
-    v = cand ? cand[j] : (int32_t)j;
-    if (dedup_round >= 0) {
-      int first = 0;
-      if (lane == 0) first = atomicExch(&stamp[v], dedup_round) != dedup_round;
-      take = __shfl(first, 0, 64) != 0;
+  if (blockIdx.x == 0 && threadIdx.x < kPushCounters) {
+    cnt_next[threadIdx.x] = 0;
+    if (cnt_prev && threadIdx.x == 0) {
+      log_prev[0] = cnt_prev[1];
+      log_prev[1] = cnt_prev[3];
     }
   }
-  if (take) {
-    float m = 0.f;
-    for (int c = lane; c < d; c += 64) m = fmaxf(m, fabsf(R[(int64_t)v * d + c]));
-    m = wave_max(m);
-    if (lane == 0 && (double)m > eps) s_list[atomicAdd(&s_cnt, 1)] = v;
+  const int64_t ncand = ncand_dev ? *ncand_dev : ncand_host;
+  for (int64_t base = (int64_t)blockIdx.x * kRowsPerBlock; base < ncand;
+       base += (int64_t)gridDim.x * kRowsPerBlock) {
+    if (threadIdx.x == 0) s_cnt = 0;
+    __syncthreads();
+    const int64_t j = base + w;
+    bool take = j < ncand;
+    int32_t v = 0;
+    if (take) {
+      v = cand ? cand[j] : (int32_t)j;
+      if (dedup_round >= 0) {
+        int first = 0;
+        if (lane == 0) first = atomicExch(&stamp[v], dedup_round) != dedup_round;
+        take = __shfl(first, 0, 64) != 0;
+      }
+    }
+    if (take) {
+      float m = 0.f;
+      for (int c = lane; c < d; c += 64) m = fmaxf(m, fabsf(R[(int64_t)v * d + c]));
+      m = wave_max(m);
+      if (lane == 0 && (double)m > eps) s_list[atomicAdd(&s_cnt, 1)] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0 && s_cnt > 0)
+      s_base = atomicAdd((unsigned long long *)&cnt_r[1], (unsigned long long)s_cnt);
+    __syncthreads();
+    if (threadIdx.x < s_cnt) frontier[s_base + threadIdx.x] = s_list[threadIdx.x];
+    __syncthreads();
   }
-  __syncthreads();
-  if (threadIdx.x == 0 && s_cnt > 0)
-    s_base = atomicAdd((unsigned long long *)&counters[1], (unsigned long long)s_cnt);
-  __syncthreads();
-  if (threadIdx.x < s_cnt) frontier[s_base + threadIdx.x] = s_list[threadIdx.x];
 }
 
 constexpr int kCandBuf = 1024;  // per-block LDS list of new candidates
@@ -114,6 +137,8 @@ __device__ __forceinline__ void spread64(const int32_t *row, int cnt, const int3
   const int lane = threadIdx.x & 63;
   const bool c0 = lane < d, c1 = lane + 64 < d;
   const int32_t myu = (lane < cnt) ? row[lane] : -1;
+  // the 64 scale factors load in parallel, one per lane
+  const float mysc = (myu >= 0) ? (1.f - alpha) / (float)outdeg[myu] : 0.f;
   bool fresh = false;
   if (myu >= 0) fresh = atomicExch(&stamp[myu], round) != round;
   const unsigned long long fm = __ballot(fresh);
@@ -133,7 +158,7 @@ __device__ __forceinline__ void spread64(const int32_t *row, int cnt, const int3
   }
   for (int q = 0; q < cnt; ++q) {
     const int32_t u = __shfl(myu, q, 64);
-    const float sc = (1.f - alpha) / (float)outdeg[u];
+    const float sc = __shfl(mysc, q, 64);
     if (c0) atomicAdd(&R[(int64_t)u * d + lane], sc * r0);
     if (c1) atomicAdd(&R[(int64_t)u * d + lane + 64], sc * r1);
   }
@@ -158,10 +183,10 @@ __device__ __forceinline__ void flush_candidates(const int32_t *s_list, int s_cn
 // residual goes to hbuf and its row to segments of kSegEdges neighbours that
 // spread_heavy_kernel spreads with one wave each.  Counters: [1] frontier,
 // [2] next candidates, [3] edges, [4] heavy nodes, [5] heavy segments.
-constexpr int kHeavy = 2048;
+constexpr int kHeavy = 512;
 constexpr int kSegEdges = 256;
 __global__ __launch_bounds__(256) void push_kernel(Csr gin, const int32_t *outdeg,
-                                                   const int32_t *frontier, int64_t nf, float *R,
+                                                   const int32_t *frontier, float *R,
                                                    float *Z, int d, float alpha, int32_t round,
                                                    int32_t *stamp, int32_t *next_cand,
                                                    int64_t *counters, float *hbuf,
@@ -175,8 +200,9 @@ __global__ __launch_bounds__(256) void push_kernel(Csr gin, const int32_t *outde
     s_edges = 0;
   }
   __syncthreads();
-  const int64_t j = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
-  if (j < nf) {
+  const int64_t nf = counters[1];
+  for (int64_t j = (int64_t)blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6); j < nf;
+       j += (int64_t)gridDim.x * kRowsPerBlock) {
     const int32_t v = frontier[j];
     const bool c0 = lane < d, c1 = lane + 64 < d;
     float r0 = 0.f, r1 = 0.f;
@@ -328,10 +354,9 @@ hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64
   Workspace &w = c->ws;
   const int d = c->d;
   *rounds = *pushes = *edges = 0;
-  int64_t ncand = first_rows ? nfirst : c->n;
-  int32_t *cand = w.cand, *next = w.cand2, *front = w.frontier;
-  if (first_rows && ncand > 0)
-    DAMF_HIP(hipMemcpyAsync(cand, first_rows, ncand * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  const bool all = (first_rows == nullptr);
+  const int64_t ncand0 = all ? c->n : nfirst;
+  if (ncand0 <= 0) return hipSuccess;
   // heavy-node buffers: at most edges / kHeavy nodes have more than kHeavy
   // in-neighbours, and their rows hold at most edges / kSegEdges + nodes segments
   const int64_t edges_cap = c->in.pool_cap;
@@ -351,48 +376,60 @@ hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64
     w.heavy_cap = hcap;
     w.hseg_cap = scap;
   }
-  bool all = (first_rows == nullptr);
-  bool first = true;
-  while (ncand > 0) {
-    DAMF_HIP(hipMemsetAsync(w.counters, 0, 6 * sizeof(int64_t), s));
-    // the caller's list may repeat rows; later rounds' lists are unique by stamp
-    const int32_t dedup = (first && !all) ? (int32_t)(++c->round_counter & 0x7fffffff) : -1;
-    select_kernel<<<ceil_div(ncand, kRowsPerBlock), 256, 0, s>>>(
-        all ? nullptr : cand, ncand, c->R, d, c->cfg.eps, w.stamp, dedup, front, w.counters);
-    all = false;
-    first = false;
+  if (!w.push_ring) {
+    DAMF_HIP(hipMalloc(&w.push_ring, kPushRing * kPushCounters * sizeof(int64_t)));
+    DAMF_HIP(hipMalloc(&w.push_log, 2 * (size_t)kMaxPushRounds * sizeof(int64_t)));
+    DAMF_HIP(hipHostMalloc((void **)&w.push_log_host, 2 * (size_t)kMaxPushRounds * sizeof(int64_t)));
+  }
+  int32_t *cand[2] = {w.cand, w.cand2};
+  if (!all) DAMF_HIP(hipMemcpyAsync(cand[0], first_rows, nfirst * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  DAMF_HIP(hipMemsetAsync(w.push_ring, 0, kPushRing * kPushCounters * sizeof(int64_t), s));
+  auto ring = [&](int r) { return w.push_ring + (size_t)(r % kPushRing) * kPushCounters; };
+  const int32_t id0 = (int32_t)(++c->round_counter & 0x7fffffff);  // first-round dedup stamp
+  const float alpha = (float)c->cfg.alpha;
+  DAMF_HIP(hipEventRecord(c->ev_k[0], s));
+  int r = 0;
+  int64_t *last = w.counters_host;  // pinned copy of the last queued round's counters
+  for (;;) {
+    for (int g = 0; g < kPushGroup; ++g, ++r) {
+      const int32_t round = (int32_t)((id0 + 1 + r) & 0x7fffffff);
+      select_kernel<<<2048, 256, 0, s>>>(
+          (r == 0 && all) ? nullptr : cand[r & 1], r == 0 ? nullptr : ring(r - 1) + 2, ncand0,
+          c->R, d, c->cfg.eps, w.stamp, (r == 0 && !all) ? id0 : -1, w.frontier, ring(r),
+          ring(r + 1), r == 0 ? nullptr : ring(r - 1), w.push_log + 2 * (size_t)(r > 0 ? r - 1 : 0));
+      push_kernel<<<2048, 256, 0, s>>>(c->in, c->out.len, w.frontier, c->R, c->Zb, d, alpha,
+                                       round, w.stamp, cand[(r + 1) & 1], ring(r), w.hbuf,
+                                       w.hnode, reinterpret_cast<int2 *>(w.hseg));
+      spread_heavy_kernel<<<1024, 256, 0, s>>>(c->in, c->out.len, c->R, d, alpha, round, w.stamp,
+                                               cand[(r + 1) & 1], ring(r), w.hbuf, w.hnode,
+                                               reinterpret_cast<const int2 *>(w.hseg));
+    }
     DAMF_HIP(hipGetLastError());
-    DAMF_HIP(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    DAMF_HIP(hipMemcpyAsync(last, ring(r - 1), kPushCounters * sizeof(int64_t), hipMemcpyDeviceToHost, s));
     DAMF_HIP(hipStreamSynchronize(s));
-    const int64_t nf = w.counters_host[1];
-    if (nf == 0) break;
-    const int32_t round = (int32_t)(++c->round_counter & 0x7fffffff);
-    DAMF_HIP(hipEventRecord(c->ev_k[0], s));
-    push_kernel<<<ceil_div(nf, kRowsPerBlock), 256, 0, s>>>(
-        c->in, c->out.len, front, nf, c->R, c->Zb, d, (float)c->cfg.alpha, round, w.stamp, next,
-        w.counters, w.hbuf, w.hnode, reinterpret_cast<int2 *>(w.hseg));
-    spread_heavy_kernel<<<1024, 256, 0, s>>>(c->in, c->out.len, c->R, d, (float)c->cfg.alpha,
-                                             round, w.stamp, next, w.counters, w.hbuf, w.hnode,
-                                             reinterpret_cast<const int2 *>(w.hseg));
-    DAMF_HIP(hipGetLastError());
-    DAMF_HIP(hipEventRecord(c->ev_k[1], s));
-    DAMF_HIP(hipMemcpyAsync(w.counters_host, w.counters, 4 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
-    DAMF_HIP(hipStreamSynchronize(s));
-    float kms = 0.f;
-    DAMF_HIP(hipEventElapsedTime(&kms, c->ev_k[0], c->ev_k[1]));
-    c->push_ms += kms;
+    if (last[2] == 0) break;  // no candidates left for another round
+    if (r + kPushGroup >= kMaxPushRounds) return hipErrorUnknown;
+  }
+  DAMF_HIP(hipEventRecord(c->ev_k[1], s));
+  if (r > 1)
+    DAMF_HIP(hipMemcpyAsync(w.push_log_host, w.push_log, 2 * (size_t)(r - 1) * sizeof(int64_t),
+                            hipMemcpyDeviceToHost, s));
+  DAMF_HIP(hipStreamSynchronize(s));
+  float kms = 0.f;
+  DAMF_HIP(hipEventElapsedTime(&kms, c->ev_k[0], c->ev_k[1]));
+  c->push_ms += kms;
+  c->round_counter = id0 + 1 + r;
+  for (int q = 0; q < r; ++q) {
+    const int64_t nf = (q < r - 1) ? w.push_log_host[2 * q] : last[1];
+    const int64_t ne = (q < r - 1) ? w.push_log_host[2 * q + 1] : last[3];
+    if (nf == 0) continue;
     // compulsory bytes: per pushed node R[v] and Z_b[v] read + written and
     // its in-row metadata; per traversed edge the index, deg(u), R[u] read +
     // written and the stamp word
-    c->push_bytes += (double)nf * (4.0 * 4.0 * d + 12.0) +
-                     (double)w.counters_host[3] * (4.0 + 4.0 + 2.0 * 4.0 * d + 8.0);
+    c->push_bytes += (double)nf * (4.0 * 4.0 * d + 12.0) + (double)ne * (4.0 + 4.0 + 2.0 * 4.0 * d + 8.0);
     ++*rounds;
     *pushes += nf;
-    *edges += w.counters_host[3];
-    ncand = w.counters_host[2];
-    int32_t *t = cand;
-    cand = next;
-    next = t;
+    *edges += ne;
   }
   return hipSuccess;
 }
