@@ -55,6 +55,23 @@ __device__ __forceinline__ double row_bcast(double x) {
   return dpp_d<0x150 + P>(x);  // row_newbcast
 }
 
+// 1 / sqrt(x) and 1 / x for normal positive x: the hardware estimates
+// refined by two Newton steps each (quadratic convergence from the
+// estimate's error to about one ulp).
+__device__ __forceinline__ double rsqrt_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  const double hx = 0.5 * x;
+  y = y * fma(-hx * y, y, 1.5);
+  y = y * fma(-hx * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+
 template <int NP_, int G_>
 struct J16 {
   static constexpr int NP = NP_;
@@ -109,7 +126,7 @@ __device__ __forceinline__ double j16_norm2(const double (&col)[S::RL]) {
 
 // Sweeps until one applies no rotation or all its rotations were below
 // sqrt(tol) (or max_sweeps); returns the sweep count.  lds_flag points to 4
-// ints of LDS (8-byte aligned from lds_flag + 2).  A pair is rotated when |a_i . a_j| > tol ||a_i|| ||a_j|| and
+// ints of LDS.  A pair is rotated when |a_i . a_j| > tol ||a_i|| ||a_j|| and
 // neither column is numerically zero (norm^2 below 1e-30 of the largest).
 // Every thread of the workgroup calls it; groups >= G only join barriers.
 // On return the squared norms are in lds[2 * G * NP + id].
@@ -133,10 +150,11 @@ __device__ int jacobi16_sweeps(J16Regs<S> &J, double *lds, int *lds_flag, int ma
   }
   __syncthreads();
   int sweeps = 0;
-  double offmax = 0.0;  // largest |a_i . a_j| / (||a_i|| ||a_j||) seen in the sweep
+  const double tol2 = tol * tol, conv2 = tol;  // (sqrt(tol))^2
+  int big = 0;  // some pair had |a_i . a_j| >= sqrt(tol) ||a_i|| ||a_j|| this sweep
   for (; sweeps < max_sweeps; ++sweeps) {
     int rot = 0;
-    offmax = 0.0;
+    big = 0;
     double mx = 0.0;
     for (int j = sl; j < NP; j += 16) mx = fmax(mx, nrm[j]);
     mx = row_max16(mx);
@@ -160,18 +178,20 @@ __device__ int jacobi16_sweeps(J16Regs<S> &J, double *lds, int *lds_flag, int ma
         const int ib = j16_bot_id<NP>(grp * H + pp, step);
         const double al = nrm[it], be = nrm[ib];
         const bool live = (sl < H) && al > floor2 && be > floor2;
-        const double sab = sqrt(al * be);
-        const bool doit = live && fabs(myg) > tol * sab;
-        if (live) offmax = fmax(offmax, fabs(myg) / sab);
-        const double gs = doit ? myg : 1.0;
-        const double zeta = (be - al) / (2.0 * gs);
-        double t = copysign(1.0, zeta) / (fabs(zeta) + sqrt(1.0 + zeta * zeta));
-        t = doit ? t : 0.0;
-        const double cs = 1.0 / sqrt(1.0 + t * t);
+        const double g2 = myg * myg, ab = al * be;
+        const bool doit = live && g2 > tol2 * ab;
+        big |= (live && g2 >= conv2 * ab) ? 1 : 0;
+        // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 g),
+        // as sign(be - al) 2g / (|be - al| + sqrt((be - al)^2 + 4 g^2))
+        const double dd = be - al, gg = doit ? 2.0 * myg : 0.0;
+        const double q2 = fma(dd, dd, gg * gg);
+        const double den = fabs(dd) + q2 * rsqrt_nr(q2);
+        const double t = doit ? (dd >= 0.0 ? gg : -gg) * rcp_nr(den) : 0.0;
+        const double cs = rsqrt_nr(fma(t, t, 1.0));
         const double sn = cs * t;
         if (doit) {
-          nrm[it] = al - t * myg;
-          nrm[ib] = be + t * myg;
+          nrm[it] = fma(-t, myg, al);
+          nrm[ib] = fma(t, myg, be);
         }
         rot += doit ? 1 : 0;
 #pragma unroll
@@ -246,19 +266,17 @@ __device__ int jacobi16_sweeps(J16Regs<S> &J, double *lds, int *lds_flag, int ma
     // Stop when no pair rotated, or when every rotation of this sweep was
     // below sqrt(tol): Jacobi converges quadratically, so the off-diagonal
     // left after such a sweep is O(tol) and another sweep would find nothing.
-    unsigned long long *offbits = reinterpret_cast<unsigned long long *>(lds_flag + 2);
     if (threadIdx.x == 0) {
-      *lds_flag = 0;
-      *offbits = 0ull;
+      lds_flag[0] = 0;
+      lds_flag[1] = 0;
     }
     __syncthreads();
     if (rot > 0) atomicAdd(lds_flag, rot);
-    if (offmax > 0.0) atomicMax(offbits, (unsigned long long)__double_as_longlong(offmax));
+    if (big) atomicOr(lds_flag + 1, 1);
     __syncthreads();
-    const int total = *lds_flag;
-    const double off = __longlong_as_double((long long)*offbits);
+    const int total = lds_flag[0], any_big = lds_flag[1];
     __syncthreads();
-    if (total == 0 || off < sqrt(tol)) {
+    if (total == 0 || !any_big) {
       ++sweeps;
       break;
     }
