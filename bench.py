@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--r", type=int, default=64)
     ap.add_argument("--cpu-baseline", type=int, default=1, help="0 skips the oracle leg")
     ap.add_argument("--cpu-batches", type=int, default=1)
+    ap.add_argument("--precision", type=int, default=0, choices=(0, 1),
+                    help="1: the precision form (bases as BF16 pairs, BF16 MFMA rotations)")
     ap.add_argument("--mode", choices=("update", "serve"), default="update",
                     help="update: batches through damf_update (default); serve: the server")
     ap.add_argument("--serve-n", type=int, default=10_000_000)
@@ -233,7 +235,8 @@ def serve_main(args):
     torch.cuda.synchronize()
     log(f"serve workload: R-MAT n={n} m={m} on the GPU in {time.perf_counter() - t0:.1f}s")
     cfg = default_config(n, d, directed=True, alpha=0.15, eps=1e-5, oversample=10,
-                         power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64)
+                         power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64,
+                         precision=args.precision)
     t0 = time.perf_counter()
     ctx = Context.init(cfg, src, dst)
     torch.cuda.synchronize()
@@ -317,7 +320,8 @@ def main():
     src = torch.from_numpy(w["init"][0]).cuda()
     dst = torch.from_numpy(w["init"][1]).cuda()
     cfg = default_config(n, d, directed=True, alpha=0.15, eps=1e-5, oversample=10,
-                         power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64)
+                         power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64,
+                         precision=args.precision)
     t0 = time.perf_counter()
     ctx = Context.init(cfg, src, dst)
     torch.cuda.synchronize()
@@ -325,8 +329,6 @@ def main():
     ii = ctx.init_info()
     log(f"init {init_s:.2f}s: graph {ii['ms_graph']:.0f} ms, rsvd {ii['ms_rsvd']:.0f} ms, "
         f"ppr {ii['ms_ppr']:.0f} ms ({ii['ppr_rounds']} rounds)")
-    del src, dst
-
     batches = [tuple(torch.from_numpy(np.ascontiguousarray(a)).cuda() for a in b)
                for b in w["stream"]]
     torch.cuda.synchronize()
@@ -380,6 +382,31 @@ def main():
     roofline = {"kernel": dom, "bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
                 "unit": dk["unit"], "frac": dk["frac"], "traffic": None}
 
+    accuracy = None
+    if args.precision == 1:
+        # the FP32 form replays the same stream (untimed); compare on a 1% row sample
+        log("fp32 reference replay for the accuracy report ...")
+        cfg32 = default_config(n, d, directed=True, alpha=0.15, eps=1e-5, oversample=10,
+                               power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64,
+                               precision=0)
+        ref = Context.init(cfg32, src, dst)
+        for b in range(W + K):
+            ref.update(*batches[b])
+        rng = np.random.default_rng(0)
+        rows = torch.from_numpy(np.sort(rng.choice(n, max(1, n // 100), replace=False)).astype(np.int32)).cuda()
+        out = {}
+        for which in ("X", "Y", "Z"):
+            a = ctx.query(which, rows, torch.empty((len(rows), d), device="cuda")).double().cpu().numpy()
+            r = ref.query(which, rows, torch.empty((len(rows), d), device="cuda")).double().cpu().numpy()
+            sign = np.sign((a * r).sum(axis=0))
+            sign[sign == 0] = 1.0
+            out[which] = float(np.linalg.norm(a * sign - r) / np.linalg.norm(r))
+        s_a, s_r = ctx.singular_values(), ref.singular_values()
+        accuracy = {"vs": "FP32 form on the same stream", "row_sample": int(len(rows)),
+                    "sigma_max_rel_err": float(np.max(np.abs(s_a - s_r)) / s_r[0]),
+                    "rows_rel_fro_err": out}
+        ref.close()
+    del src, dst
     line = {
         "metric": "edge-updates/s",
         "value": value,
@@ -391,11 +418,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "bf16x2" if args.precision == 1 else "f32",
         "data": "synthetic",
         "config": {"workload": "chung-lu-2.1 n=1e6 m=1e7 d=128 batch=1000 (95% ins / 5% del), "
                                "alpha=0.15 eps=1e-5",
-                   "n": n, "m": m, "d": d, "batch": args.batch, "chunk_rank": args.r},
+                   "n": n, "m": m, "d": d, "batch": args.batch, "chunk_rank": args.r,
+                   "precision": "bf16 pairs" if args.precision == 1 else "fp32"},
+        "accuracy": accuracy,
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
                        "mean": float(np.mean(lat)) * 1e3},
         "stage_ms_mean": {k: tot(k) / K for k in ("ms_prepare", "ms_chain", "ms_enhance",

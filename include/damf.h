@@ -75,6 +75,16 @@ typedef struct {
                             free quarter of the reservations; compacted when
                             less than an eighth is free                      */
   void *hip_stream;      /* hipStream_t to run on; NULL = a context stream    */
+  int32_t precision;     /* 0: bases U_b, V_b in FP32.  1: the precision form:
+                            each basis element stored as a BF16 pair
+                            hi = bf16(x), lo = bf16(x - hi) in one 32-bit word
+                            (about 16 significant bits); flush / re-
+                            orthogonalisation rotate them with BF16 MFMA
+                            (hi*hi + hi*lo + lo*hi, FP32 accumulation).  The
+                            core, Grams, projections, re-orthogonalisation and
+                            the eps test stay FP64; Z_b and the PPR residual R
+                            stay FP32 (Z_b sums many small pushes).          */
+  int32_t reserved1;
 } damf_config;
 
 /* Per-batch statistics written by damf_update when `info` is non-NULL. */

@@ -45,6 +45,8 @@ class DamfConfig(C.Structure):
         ("reorth_every", C.c_int32),
         ("graph_slack", C.c_double),
         ("hip_stream", C.c_void_p),
+        ("precision", C.c_int32),
+        ("reserved1", C.c_int32),
     ]
 
 

@@ -60,6 +60,7 @@ damf_status check_config(const damf_config *cfg) {
   if (cfg->d + cfg->oversample > kMaxCore) return DAMF_E_INVALID_ARG;
   if (!(cfg->graph_slack >= 1.0)) return DAMF_E_INVALID_ARG;
   if (cfg->reorth_every < 0) return DAMF_E_INVALID_ARG;
+  if (cfg->precision != 0 && cfg->precision != 1) return DAMF_E_INVALID_ARG;
   return DAMF_OK;
 }
 
@@ -195,6 +196,7 @@ damf_status new_ctx(const damf_config *cfg, damf_ctx **out, damf_ctx **cptr) {
   c->n = cfg->n;
   c->d = cfg->d;
   c->ppr_on = cfg->alpha < 1.0;
+  c->split = cfg->precision == 1;
   if (hipGetDevice(&c->device) != hipSuccess) {
     delete c;
     return DAMF_E_DEVICE;
@@ -484,7 +486,15 @@ damf_status damf_init_factors(const damf_config *cfg, int64_t m, const int32_t *
   std::vector<float> buf((size_t)n * d);
   for (int side = 0; side < 2; ++side) {
     const double *M = side ? V : U;
-    for (size_t i = 0; i < buf.size(); ++i) buf[i] = (float)M[i];
+    for (size_t i = 0; i < buf.size(); ++i) {
+      const float f = (float)M[i];
+      if (c->split) {
+        const uint32_t w = split_encode(f);
+        std::memcpy(&buf[i], &w, 4);
+      } else {
+        buf[i] = f;
+      }
+    }
     if (hipMemcpy(side ? c->Vb : c->Ub, buf.data(), buf.size() * sizeof(float),
                   hipMemcpyHostToDevice) != hipSuccess) {
       free_ctx(c);
@@ -656,6 +666,7 @@ damf_status damf_export_state(damf_ctx *c, double *Ub, double *Vb, double *PU, d
   const int d = c->d;
   API_HIP(c, hipStreamSynchronize(c->stream), "export");
   std::vector<float> buf;
+  bool split = c->split;
   auto pull = [&](const float *src, double *dst) -> hipError_t {
     if (!dst) return hipSuccess;
     if (!src) {
@@ -664,11 +675,20 @@ damf_status damf_export_state(damf_ctx *c, double *Ub, double *Vb, double *PU, d
     }
     buf.resize(nd);
     hipError_t e = hipMemcpy(buf.data(), src, nd * sizeof(float), hipMemcpyDeviceToHost);
-    for (size_t i = 0; i < nd; ++i) dst[i] = buf[i];
+    for (size_t i = 0; i < nd; ++i) {
+      if (split) {
+        uint32_t w;
+        std::memcpy(&w, &buf[i], 4);
+        dst[i] = split_decode(w);
+      } else {
+        dst[i] = buf[i];
+      }
+    }
     return e;
   };
   API_HIP(c, pull(c->Ub, Ub), "export U_b");
   API_HIP(c, pull(c->Vb, Vb), "export V_b");
+  split = false;  // Z_b and the residual R are FP32 in both forms
   API_HIP(c, pull(c->Zb, Zb), "export Z_b");
   API_HIP(c, pull(c->R, R), "export R");
   if (PU) API_HIP(c, hipMemcpy(PU, c->P, (size_t)d * d * sizeof(double), hipMemcpyDeviceToHost), "export P");

@@ -68,6 +68,7 @@ struct ChainParams {
   double *scr;
   double tau;
   ChainStats *stats;
+  bool split;  // U_b, V_b as BF16 pairs
 };
 
 struct ChunkState {
@@ -87,10 +88,10 @@ constexpr int NG = NT / 128;  // groups of 128 threads (one column each)
 
 // MP[i][c] = sum_q Mb[rows[i]][q] * Pm[q][c]  (rows of U or V in the current basis)
 __device__ __noinline__ void gather_project(const float *Mb, const int32_t *rows, int s, const double *Pm,
-                               int d, double *lds, double *MP) {
+                               int d, double *lds, double *MP, bool split) {
   for (int e = tid(); e < s * d; e += NT) {
     int i = e / d, q = e - i * d;
-    lds[i * d + q] = (double)Mb[(int64_t)rows[i] * d + q];
+    lds[i * d + q] = (double)basis_ld(Mb, (int64_t)rows[i] * d + q, split);
   }
   __syncthreads();
   const int c = tid() & 127, g = tid() >> 7;
@@ -637,7 +638,8 @@ __device__ __noinline__ void mul_PF(int d, const double *Po, const double *F, do
 // row vectors; adds X to M_b[rows] (and to R when given).  Returns 0, or 1 if
 // a zero pivot was met.
 __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const double *Dl, const int32_t *rows,
-                                int nrows, float *Mb, float *Rr, double *lds, int *ilds) {
+                                int nrows, float *Mb, float *Rr, double *lds, int *ilds,
+                                bool split) {
   double *A = lds;  // d x d
   int *piv = ilds;  // d
   int *src = ilds + DMAX;
@@ -811,8 +813,8 @@ __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const doub
     const int64_t row = rows[i];
     for (int c = lane; c < d; c += 64) {
       const double x = rowbuf[q * DMAX + src[c]];
-      float *mp = Mb + row * d + c;
-      *mp = (float)((double)(*mp) + x);
+      const int64_t at = row * d + c;
+      basis_st(Mb, at, (float)((double)basis_ld(Mb, at, split) + x), split);
       if (Rr) atomicAdd(Rr + row * d + c, (float)x);  // a push may run concurrently
     }
   }
@@ -857,8 +859,8 @@ __global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
     const int k = cs.k;
     // ---- Step 1: gather + project
     tick(-1);
-    gather_project(p.Ub, cs.S1, cs.s1, Pc, d, lds, scr + OFF_UP);
-    gather_project(p.Vb, cs.S2, cs.s2, Pc + d * d, d, lds, scr + OFF_VP);
+    gather_project(p.Ub, cs.S1, cs.s1, Pc, d, lds, scr + OFF_UP, p.split);
+    gather_project(p.Vb, cs.S2, cs.s2, Pc + d * d, d, lds, scr + OFF_VP, p.split);
     tick(0);
     double bmax = 1.0;
     for (int side = 0; side < 2; ++side) {
@@ -919,9 +921,9 @@ __global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
     mul_PF(d, Pc, scr + OFF_FU, Pn, lds);
     mul_PF(d, Pc + d * d, scr + OFF_FV, Pn + d * d, lds);
     tick(5);
-    numeric |= lu_solve_scatter(d, Pn, scr + OFF_DU, cs.S1, cs.s1, p.Ub, p.R, lds, ilds);
+    numeric |= lu_solve_scatter(d, Pn, scr + OFF_DU, cs.S1, cs.s1, p.Ub, p.R, lds, ilds, p.split);
     numeric |= lu_solve_scatter(d, Pn + d * d, scr + OFF_DV, cs.S2, cs.s2, p.Vb, nullptr, lds,
-                                ilds);
+                                ilds, p.split);
     tick(6);
     for (int c = tid(); c < d; c += NT) p.sigma[c] = scr[OFF_TH + c];
     double *t = Pc;
@@ -968,6 +970,7 @@ hipError_t launch_chain(damf_ctx *c, int n_chunks) {
   p.scr = c->ws.scratch;
   p.tau = c->cfg.tau;
   p.stats = c->ws.cstats;
+  p.split = c->split;
   chain_kernel<<<1, NT, 0, c->stream>>>(p);
   return hipGetLastError();
 }

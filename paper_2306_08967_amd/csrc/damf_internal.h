@@ -144,6 +144,7 @@ struct damf_ctx {
   double push_ms = 0.0, push_bytes = 0.0;  // accumulated by ppr_push
   double wall_khz = 100000.0;               // device wall-clock rate (kHz)
   int64_t batches_since_reorth = 0;
+  bool split = false;  // U_b, V_b as BF16 pairs (precision form)
 };
 
 namespace damf {

@@ -43,7 +43,7 @@ constexpr int kMaxPushRounds = 65536;
 __global__ __launch_bounds__(256) void fixup_kernel(Csr g, const NetEntry *net,
                                                     const int32_t *rows, const int32_t *rowpos,
                                                     int nrows, const float *X, const float *Z,
-                                                    float *R, int d, float alpha) {
+                                                    float *R, int d, float alpha, bool split) {
   const int lane = threadIdx.x & 63;
   const int j = blockIdx.x * kRowsPerBlock + (threadIdx.x >> 6);
   if (j >= nrows) return;
@@ -56,7 +56,7 @@ __global__ __launch_bounds__(256) void fixup_kernel(Csr g, const NetEntry *net,
   const float k = (1.f - alpha) / alpha;
   for (int c = lane; c < d; c += 64) {
     const int64_t i = (int64_t)u * d + c;
-    const float pz = (alpha * (R[i] - X[i]) + Z[i]) / (1.f - alpha);
+    const float pz = (alpha * (R[i] - basis_ld(X, i, split)) + Z[i]) / (1.f - alpha);
     float s = (float)deg_old * pz;
     for (int e = e0; e < e1; ++e) {
       const NetEntry en = net[e];
@@ -279,6 +279,12 @@ __global__ __launch_bounds__(256) void spread_heavy_kernel(Csr gin, const int32_
   flush_candidates(s_list, s_cnt, s_edges, next_cand, counters, &s_base);
 }
 
+// FP32 copy of a basis stored as BF16 pairs.
+__global__ void decode_kernel(const float *M, float *out, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) out[i] = split_decode(__float_as_uint(M[i]));
+}
+
 __global__ void abs_max_kernel(const float *R, int64_t count, unsigned *maxbits) {
   float m = 0.f;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
@@ -295,7 +301,12 @@ hipError_t ppr_init(damf_ctx *c) {
   const int64_t n = c->n;
   const int d = c->d;
   const size_t bytes = (size_t)n * d * sizeof(float);
-  DAMF_HIP(hipMemcpyAsync(c->R, c->Ub, bytes, hipMemcpyDeviceToDevice, s));
+  if (c->split) {
+    decode_kernel<<<ceil_div((int64_t)n * d, 256), 256, 0, s>>>(c->Ub, c->R, (int64_t)n * d);
+    DAMF_HIP(hipGetLastError());
+  } else {
+    DAMF_HIP(hipMemcpyAsync(c->R, c->Ub, bytes, hipMemcpyDeviceToDevice, s));
+  }
   DAMF_HIP(hipMemsetAsync(c->Zb, 0, bytes, s));
   float *Rn = nullptr;
   DAMF_HIP(hipMalloc(&Rn, bytes));
@@ -342,7 +353,7 @@ hipError_t ppr_fixup(damf_ctx *c, int n_rows) {
   if (n_rows <= 0) return hipSuccess;
   fixup_kernel<<<ceil_div(n_rows, kRowsPerBlock), 256, 0, c->stream>>>(
       c->out, c->ws.net, c->ws.rows_out, c->ws.rowpos_out, n_rows, c->Ub, c->Zb, c->R, c->d,
-      (float)c->cfg.alpha);
+      (float)c->cfg.alpha, c->split);
   return hipGetLastError();
 }
 

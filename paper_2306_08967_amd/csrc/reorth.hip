@@ -33,7 +33,7 @@ constexpr double kMinPivot = 0.25;  // G must be near I: pivots of R_U^T R_U
 // rows into part[b] (d x d, stride DM).  Thread t owns the 8 x 8 block
 // (t / 16, t % 16) of the 128 x 128 result.
 __global__ __launch_bounds__(256) void gram_partial_kernel(const float *M, int64_t n, int d,
-                                                           double *part) {
+                                                           double *part, bool split) {
   __shared__ float tile[64][DM + 4];
   const int bi = threadIdx.x >> 4, bj = threadIdx.x & 15;
   double acc[8][8];
@@ -48,7 +48,7 @@ __global__ __launch_bounds__(256) void gram_partial_kernel(const float *M, int64
     for (int e = threadIdx.x; e < 64 * DM; e += 256) {
       const int rr = e / DM, c = e - rr * DM;
       const int64_t r = base + rr;
-      tile[rr][c] = (r < r1 && c < d) ? M[r * d + c] : 0.f;
+      tile[rr][c] = (r < r1 && c < d) ? basis_ld(M, r * d + c, split) : 0.f;
     }
     __syncthreads();
     for (int rr = 0; rr < 64; ++rr) {
@@ -321,6 +321,67 @@ __global__ void reset_projection_kernel(double *P, int d, double *sigma, const d
   if (S && e < d) sigma[e] = S[e];
 }
 
+// Precision form: M <- M B in place for a basis of BF16 pairs (n x d,
+// d <= 128) and FP32 B (d x d), on BF16 MFMA (v_mfma_f32_16x16x16 bf16):
+// with M = Mh + Ml and B = Bh + Bl, M B ~ Mh Bh + Mh Bl + Ml Bh accumulated
+// in FP32, then stored again as pairs.  Each workgroup owns 64 whole rows.
+typedef short v4s16 __attribute__((ext_vector_type(4)));
+typedef float v4f32 __attribute__((ext_vector_type(4)));
+__global__ __launch_bounds__(256) void gemm_split_kernel(float *M, int64_t n, int d,
+                                                         const float *B) {
+  __shared__ uint32_t As[64][DM + 4];          // row block, as stored (pairs)
+  __shared__ uint32_t Bs[DM][DM + 4];          // B as pairs
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t row0 = (int64_t)blockIdx.x * 64;
+  const int dp = (d + 15) & ~15;  // k and n padded to the 16-wide MFMA
+  for (int e = threadIdx.x; e < 64 * DM; e += 256) {
+    const int i = e / DM, k = e - i * DM;
+    const int64_t r = row0 + i;
+    As[i][k] = (r < n && k < d) ? __float_as_uint(M[r * d + k]) : 0u;
+  }
+  for (int e = threadIdx.x; e < DM * DM; e += 256) {
+    const int k = e / DM, j = e - k * DM;
+    Bs[k][j] = (k < d && j < d) ? split_encode(B[k * d + j]) : 0u;
+  }
+  __syncthreads();
+  v4f32 acc[DM / 16];
+#pragma unroll
+  for (int t = 0; t < DM / 16; ++t) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < dp; k0 += 16) {
+    v4s16 ah, al;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const uint32_t a = As[w * 16 + (lane & 15)][k0 + 4 * (lane >> 4) + j];
+      ah[j] = (short)(a >> 16);
+      al[j] = (short)(a & 0xffffu);
+    }
+#pragma unroll
+    for (int t = 0; t < DM / 16; ++t) {
+      if (t * 16 >= dp) break;
+      v4s16 bh, bl;
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const uint32_t b = Bs[k0 + 4 * (lane >> 4) + j][t * 16 + (lane & 15)];
+        bh[j] = (short)(b >> 16);
+        bl[j] = (short)(b & 0xffffu);
+      }
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
+      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+    }
+  }
+  // every row of the block was read into LDS above, so the in-place store is safe
+#pragma unroll
+  for (int t = 0; t < DM / 16; ++t) {
+    const int j = t * 16 + (lane & 15);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = row0 + w * 16 + (lane >> 4) * 4 + q;
+      if (r < n && j < d) M[r * d + j] = __uint_as_float(split_encode(acc[t][q]));
+    }
+  }
+}
+
 template <class T>
 struct DevBuf {
   T *p = nullptr;
@@ -335,9 +396,16 @@ hipError_t rotate_bases(damf_ctx *c, const float *RotU, const float *RotV) {
   hipStream_t s = c->stream;
   const int d = c->d;
   const int64_t n = c->n;
-  DAMF_HIP(gemm_tall(c->Ub, n, d, d, RotU, d, c->Ub, d, s));
-  DAMF_HIP(gemm_tall(c->Vb, n, d, d, RotV, d, c->Vb, d, s));
-  if (c->ppr_on) {
+  auto basis = [&](float *M, const float *Rot) -> hipError_t {
+    if (c->split) {
+      gemm_split_kernel<<<ceil_div(n, 64), 256, 0, s>>>(M, n, d, Rot);
+      return hipGetLastError();
+    }
+    return gemm_tall(M, n, d, d, Rot, d, M, d, s);
+  };
+  DAMF_HIP(basis(c->Ub, RotU));
+  DAMF_HIP(basis(c->Vb, RotV));
+  if (c->ppr_on) {  // Z_b and R are FP32 in both forms
     DAMF_HIP(gemm_tall(c->Zb, n, d, d, RotU, d, c->Zb, d, s));
     DAMF_HIP(gemm_tall(c->R, n, d, d, RotU, d, c->R, d, s));
   }
@@ -379,7 +447,7 @@ hipError_t reorthogonalize(damf_ctx *c, int *numeric_bad) {
   DAMF_HIP(bad.alloc(1));
   DAMF_HIP(hipMemsetAsync(bad.p, 0, sizeof(int), s));
   for (int side = 0; side < 2; ++side) {
-    gram_partial_kernel<<<kGramParts, 256, 0, s>>>(side ? c->Vb : c->Ub, n, d, part.p);
+    gram_partial_kernel<<<kGramParts, 256, 0, s>>>(side ? c->Vb : c->Ub, n, d, part.p, c->split);
     gram_reduce_kernel<<<ceil_div(DM * DM, 256), 256, 0, s>>>(part.p, kGramParts,
                                                               G.p + (size_t)side * DM * DM);
     DAMF_HIP(hipGetLastError());

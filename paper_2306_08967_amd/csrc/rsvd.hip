@@ -365,6 +365,11 @@ __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t 
   }
 }
 
+__global__ void encode_kernel(float *M, int64_t count) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < count) M[i] = __uint_as_float(split_encode(M[i]));
+}
+
 __global__ void to_float_kernel(const double *x, float *y, int64_t count) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < count) y[i] = (float)x[i];
@@ -481,6 +486,11 @@ hipError_t rsvd_init(damf_ctx *c) {
   to_float_kernel<<<ceil_div((int64_t)l * d, 256), 256, 0, s>>>(H, Hf, (int64_t)l * d);
   DAMF_HIP(gemm_tall(Y, n, l, ld, Ef, d, c->Ub, d, s));  // U = Q Ut_d
   DAMF_HIP(gemm_tall(T, n, l, ld, Hf, d, c->Vb, d, s));  // V = Q2 Vt_d
+  if (c->split) {  // precision form: store the bases as BF16 pairs
+    encode_kernel<<<ceil_div((int64_t)n * d, 256), 256, 0, s>>>(c->Ub, (int64_t)n * d);
+    encode_kernel<<<ceil_div((int64_t)n * d, 256), 256, 0, s>>>(c->Vb, (int64_t)n * d);
+    DAMF_HIP(hipGetLastError());
+  }
   // projections = I, Sigma
   std::vector<double> P(2 * (size_t)d * d, 0.0);
   for (int sd = 0; sd < 2; ++sd)

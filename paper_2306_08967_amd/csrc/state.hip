@@ -12,13 +12,14 @@ namespace damf {
 // One wave per queried row; lanes own columns c = lane + 64 j.
 __global__ __launch_bounds__(256) void query_kernel(const float *Mb, const double *P,
                                                     const double *sigma, int d, int64_t q,
-                                                    const int32_t *nodes, float *out) {
+                                                    const int32_t *nodes, float *out,
+                                                    bool split) {
   __shared__ double row[4][kMaxD];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
   const int64_t i = (int64_t)blockIdx.x * 4 + w;
   if (i >= q) return;
   const int64_t node = nodes ? nodes[i] : i;
-  for (int k = lane; k < d; k += 64) row[w][k] = (double)Mb[node * d + k];
+  for (int k = lane; k < d; k += 64) row[w][k] = (double)basis_ld(Mb, node * d + k, split);
   __builtin_amdgcn_wave_barrier();
   __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   for (int c = lane; c < d; c += 64) {
@@ -34,7 +35,7 @@ hipError_t launch_query(damf_ctx *c, int which, int64_t q, const int32_t *d_node
   const double *P = (which == DAMF_Y) ? c->P + (size_t)c->d * c->d : c->P;
   if (q <= 0) return hipSuccess;
   query_kernel<<<ceil_div(q, 4), 256, 0, c->stream>>>(Mb, P, c->sigma, c->d, q, d_nodes,
-                                                       d_out);
+                                                       d_out, c->split && which != DAMF_Z);
   return hipGetLastError();
 }
 
