@@ -53,7 +53,8 @@ constexpr size_t OFF_DV = OFF_DU + KMAX * DMAX;
 constexpr size_t OFF_YB = OFF_DV + KMAX * DMAX;           // Y = T E_bot [t][c]
 constexpr size_t OFF_YC = OFF_YB + KMAX * DMAX;
 constexpr size_t OFF_TH = OFF_YC + KMAX * DMAX;           // theta (NPMAX)
-constexpr size_t SCRATCH_DOUBLES = OFF_TH + NPMAX + 64;
+constexpr size_t OFF_META = OFF_TH + NPMAX + 64;         // ints: rho_B, rho_C, perm_B, perm_C
+constexpr size_t SCRATCH_DOUBLES = OFF_META + (2 + 2 * KMAX) / 2 + 8;
 
 struct ChainParams {
   int d;
@@ -822,129 +823,139 @@ __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const doub
   return 0;
 }
 
-__global__ __launch_bounds__(NT) void chain_kernel(ChainParams p) {
+// A chunk runs as three kernels in stream order.  front (one workgroup per
+// side): Step 1 -- gather/project the touched rows, the residual Gram and its
+// pivoted Cholesky factor.  core (one workgroup): Step 2 -- the core SVD and
+// Sigma <- Theta.  back (one workgroup per side): Step 3 -- Y, F and the row
+// corrections, P <- P F, and the LU solve and scatter into the base rows.
+// The two sides of front and back are independent and run on two CUs.
+
+__device__ __forceinline__ ChunkState chunk_state(const ChainParams &p, int ch, const int *meta) {
+  const ChunkDesc desc = p.chunks[ch];
+  ChunkState cs;
+  cs.s1 = desc.s1;
+  cs.s2 = desc.s2;
+  cs.mode = (cs.s1 <= cs.s2) ? 1 : 0;
+  cs.k = cs.mode ? cs.s1 : cs.s2;
+  cs.S1 = p.S1 + desc.s1_off;
+  cs.S2 = p.S2 + desc.s2_off;
+  cs.ent = p.ent + desc.e_off;
+  cs.ne = desc.ne;
+  cs.rhoB = meta ? meta[0] : 0;
+  cs.rhoC = meta ? meta[1] : 0;
+  return cs;
+}
+
+// phase clocks, added to the batch statistics by the first workgroup:
+// 0 gather/project, 7 Grams + pivoted Cholesky, 2 core SVD total, 1 Jacobi
+// sweeps (inside 2), 3 basis completion, 4 Y/F/row corrections, 5 P <- P F,
+// 6 LU + solve + scatter
+struct PhaseClock {
+  uint64_t t;
+  __device__ PhaseClock() : t(wall_clock64()) {}
+  __device__ void tick(ChainStats *st, int ph) {
+    const uint64_t now = wall_clock64();
+    if (ph >= 0 && tid() == 0 && blockIdx.x == 0)
+      atomicAdd((unsigned long long *)&st->phase_ticks[ph], (unsigned long long)(now - t));
+    t = now;
+  }
+};
+
+__global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, const double *Pc) {
   __shared__ double lds[LDS_DOUBLES];
   __shared__ __align__(16) int ilds[1024];
-  __shared__ int permB[KMAX], permC[KMAX];
-  __shared__ double s_bmax;
+  const int side = blockIdx.x;
   const int d = p.d;
   double *scr = p.scr;
-  double *Pc = p.P, *Pn = p.Pnext;
-  int max_core = 0, dropped = 0, sweeps_tot = 0, numeric = 0;
-  double flops = 0.0;
-  // phase clocks (thread 0): 0 gather/project, 7 Grams + pivoted Cholesky,
-  // 2 core SVD total, 1 Jacobi sweeps (inside 2), 3 basis completion,
-  // 4 Y/F/row corrections, 5 P <- P F, 6 LU + solve + scatter
+  int *meta = reinterpret_cast<int *>(scr + OFF_META);
+  ChunkState cs = chunk_state(p, ch, nullptr);
+  const int k = cs.k;
+  PhaseClock clk;
+  gather_project(side ? p.Vb : p.Ub, side ? cs.S2 : cs.S1, side ? cs.s2 : cs.s1,
+                 Pc + side * d * d, d, lds, scr + (side ? OFF_VP : OFF_UP), p.split);
+  clk.tick(p.stats, 0);
+  double bmax = 1.0;
+  double *D = lds;                              // s1 x s2 (<= 4096)
+  double *Wt = lds + KMAX * KMAX;               // k x d (<= 8192)
+  double *G = lds + KMAX * KMAX + KMAX * DMAX;  // k x k, row stride KMAX
+  build_D(cs, D);
+  build_Wt(cs, side, d, D, scr + (side ? OFF_VP : OFF_UP), Wt);
+  for (int e = tid(); e < k * d; e += NT) scr[(side ? OFF_WC : OFF_WB) + e] = Wt[e];
+  build_gram(cs, side, d, D, Wt, G, &bmax);
+  int *perm = ilds;
+  const int rho = pivoted_cholesky(G, k, p.tau * bmax, perm);
+  store_factor(G, k, rho, perm, scr + (side ? OFF_LC : OFF_LB), scr + (side ? OFF_RC : OFF_RB));
+  for (int i = tid(); i < k; i += NT) meta[2 + side * KMAX + i] = perm[i];
+  if (tid() == 0) {
+    meta[side] = rho;
+    if (k > rho) atomicAdd(&p.stats->dropped, k - rho);
+  }
+  clk.tick(p.stats, 7);
+}
+
+__global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ __align__(16) int ilds[1024];
   __shared__ uint64_t jt[8];
+  const int d = p.d;
+  double *scr = p.scr;
+  const int *meta = reinterpret_cast<const int *>(scr + OFF_META);
+  ChunkState cs = chunk_state(p, ch, meta);
+  const int k = cs.k;
   if (tid() < 8) jt[tid()] = 0;
-  uint64_t tlast = wall_clock64();
-  auto tick = [&](int ph) {
-    if (tid() == 0) {
-      const uint64_t now = wall_clock64();
-      if (ph >= 0) jt[ph] += now - tlast;
-      tlast = now;
-    }
-  };
-  for (int ch = 0; ch < p.n_chunks; ++ch) {
-    const ChunkDesc desc = p.chunks[ch];
-    ChunkState cs;
-    cs.s1 = desc.s1;
-    cs.s2 = desc.s2;
-    cs.mode = (cs.s1 <= cs.s2) ? 1 : 0;
-    cs.k = cs.mode ? cs.s1 : cs.s2;
-    cs.S1 = p.S1 + desc.s1_off;
-    cs.S2 = p.S2 + desc.s2_off;
-    cs.ent = p.ent + desc.e_off;
-    cs.ne = desc.ne;
-    const int k = cs.k;
-    // ---- Step 1: gather + project
-    tick(-1);
-    gather_project(p.Ub, cs.S1, cs.s1, Pc, d, lds, scr + OFF_UP, p.split);
-    gather_project(p.Vb, cs.S2, cs.s2, Pc + d * d, d, lds, scr + OFF_VP, p.split);
-    tick(0);
-    double bmax = 1.0;
-    for (int side = 0; side < 2; ++side) {
-      double *D = lds;                          // s1 x s2 (<= 4096)
-      double *Wt = lds + KMAX * KMAX;           // k x d (<= 8192)
-      double *G = lds + KMAX * KMAX + KMAX * DMAX;  // k x k, row stride KMAX
-      build_D(cs, D);
-      build_Wt(cs, side, d, D, scr + (side ? OFF_VP : OFF_UP), Wt);
-      for (int e = tid(); e < k * d; e += NT) scr[(side ? OFF_WC : OFF_WB) + e] = Wt[e];
-      build_gram(cs, side, d, D, Wt, G, &bmax);
-      const double thr = p.tau * bmax;
-      int *perm = side ? permC : permB;
-      int rho = pivoted_cholesky(G, k, thr, perm);
-      store_factor(G, k, rho, perm, scr + (side ? OFF_LC : OFF_LB), scr + (side ? OFF_RC : OFF_RB));
-      if (side == 0)
-        cs.rhoB = rho;
-      else
-        cs.rhoC = rho;
-      dropped += k - rho;
-      __syncthreads();
-    }
-    (void)s_bmax;
-    tick(7);
-    // ---- Step 2: core SVD
-    const int N = d + max(cs.rhoB, cs.rhoC);
-    max_core = max(max_core, N);
-    int sw = 0;
-    tick(-1);
-    if (N <= 64)
-      core_svd<1>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
-    else if (N <= 128)
-      core_svd<2>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
-    else
-      core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
-    tick(2);
-    sweeps_tot += sw;
-    {
-      // counted FP64 work of this chunk: Jacobi (dot + rotation = 8N flops per
-      // pair, N(N-1)/2 pairs per sweep), H = K^T E, F, P F, LU and solves
-      const double Nn = (double)N, dd = (double)d, kk = (double)k;
-      flops += sw * 4.0 * Nn * Nn * (Nn - 1.0) + 2.0 * Nn * Nn * dd;
-      flops += 2.0 * (2.0 * dd * dd * kk + 2.0 * dd * dd * dd + (2.0 / 3.0) * dd * dd * dd +
-                      2.0 * 2.0 * (double)max(cs.s1, cs.s2) * dd * dd);
-      flops += 2.0 * (double)(cs.s1 + cs.s2) * dd * dd + 4.0 * kk * kk * dd;
-    }
-    if (scr[OFF_TH + d - 1] <= 1e-10 * scr[OFF_TH]) {
-      complete_basis(d, d + cs.rhoB, d + cs.rhoC, scr);
-      __syncthreads();
-    }
-    tick(3);
-    // ---- Step 3: rotations and row corrections
-    tick(-1);
-    solve_Y(0, d, k, cs.rhoB, permB, scr + OFF_LB, scr, lds);
-    solve_Y(1, d, k, cs.rhoC, permC, scr + OFF_LC, scr, lds);
-    build_F_and_delta(cs, 0, d, scr, lds);
-    build_F_and_delta(cs, 1, d, scr, lds);
-    tick(4);
-    mul_PF(d, Pc, scr + OFF_FU, Pn, lds);
-    mul_PF(d, Pc + d * d, scr + OFF_FV, Pn + d * d, lds);
-    tick(5);
-    numeric |= lu_solve_scatter(d, Pn, scr + OFF_DU, cs.S1, cs.s1, p.Ub, p.R, lds, ilds, p.split);
-    numeric |= lu_solve_scatter(d, Pn + d * d, scr + OFF_DV, cs.S2, cs.s2, p.Vb, nullptr, lds,
-                                ilds, p.split);
-    tick(6);
-    for (int c = tid(); c < d; c += NT) p.sigma[c] = scr[OFF_TH + c];
-    double *t = Pc;
-    Pc = Pn;
-    Pn = t;
+  __syncthreads();
+  PhaseClock clk;
+  const int N = d + max(cs.rhoB, cs.rhoC);
+  int sw = 0;
+  if (N <= 64)
+    core_svd<1>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
+  else if (N <= 128)
+    core_svd<2>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
+  else
+    core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
+  clk.tick(p.stats, 2);
+  if (scr[OFF_TH + d - 1] <= 1e-10 * scr[OFF_TH]) {
+    complete_basis(d, d + cs.rhoB, d + cs.rhoC, scr);
     __syncthreads();
   }
-  // current projections back into p.P
-  if (Pc != p.P) {
-    for (int e = tid(); e < 2 * d * d; e += NT) p.P[e] = Pc[e];
-  }
+  for (int c = tid(); c < d; c += NT) p.sigma[c] = scr[OFF_TH + c];
+  clk.tick(p.stats, 3);
   if (tid() == 0) {
-    ChainStats st;
-    st.max_core = max_core;
-    st.dropped = dropped;
-    st.sweeps = sweeps_tot;
-    st.numeric_error = numeric;
-    st.flops = flops;
-    for (int i = 0; i < 8; ++i) st.phase_ticks[i] = jt[i];
-    *p.stats = st;
+    // counted FP64 work of this chunk: Jacobi (dot + rotation = 8N flops per
+    // pair, N(N-1)/2 pairs per sweep), H = K^T E, F, P F, LU and solves
+    const double Nn = (double)N, dd = (double)d, kk = (double)k;
+    double flops = sw * 4.0 * Nn * Nn * (Nn - 1.0) + 2.0 * Nn * Nn * dd;
+    flops += 2.0 * (2.0 * dd * dd * kk + 2.0 * dd * dd * dd + (2.0 / 3.0) * dd * dd * dd +
+                    2.0 * 2.0 * (double)max(cs.s1, cs.s2) * dd * dd);
+    flops += 2.0 * (double)(cs.s1 + cs.s2) * dd * dd + 4.0 * kk * kk * dd;
+    atomicAdd(&p.stats->flops, flops);
+    atomicAdd(&p.stats->sweeps, sw);
+    atomicMax(&p.stats->max_core, N);
+    atomicAdd((unsigned long long *)&p.stats->phase_ticks[1], (unsigned long long)jt[1]);
   }
+}
+
+__global__ __launch_bounds__(NT) void chain_back_kernel(ChainParams p, int ch, const double *Pc,
+                                                        double *Pn) {
+  __shared__ double lds[LDS_DOUBLES];
+  __shared__ __align__(16) int ilds[1024];
+  const int side = blockIdx.x;
+  const int d = p.d;
+  double *scr = p.scr;
+  const int *meta = reinterpret_cast<const int *>(scr + OFF_META);
+  ChunkState cs = chunk_state(p, ch, meta);
+  PhaseClock clk;
+  solve_Y(side, d, cs.k, side ? cs.rhoC : cs.rhoB, meta + 2 + side * KMAX,
+          scr + (side ? OFF_LC : OFF_LB), scr, lds);
+  build_F_and_delta(cs, side, d, scr, lds);
+  clk.tick(p.stats, 4);
+  mul_PF(d, Pc + side * d * d, scr + (side ? OFF_FV : OFF_FU), Pn + side * d * d, lds);
+  clk.tick(p.stats, 5);
+  const int bad = lu_solve_scatter(d, Pn + side * d * d, scr + (side ? OFF_DV : OFF_DU),
+                                   side ? cs.S2 : cs.S1, side ? cs.s2 : cs.s1,
+                                   side ? p.Vb : p.Ub, side ? nullptr : p.R, lds, ilds, p.split);
+  if (bad && tid() == 0) atomicOr(&p.stats->numeric_error, 1);
+  clk.tick(p.stats, 6);
 }
 
 }  // namespace
@@ -953,6 +964,7 @@ size_t chain_scratch_doubles() { return SCRATCH_DOUBLES; }
 
 hipError_t launch_chain(damf_ctx *c, int n_chunks) {
   if (n_chunks <= 0) return hipSuccess;
+  hipStream_t s = c->stream;
   ChainParams p;
   p.d = c->d;
   p.n = c->n;
@@ -971,8 +983,22 @@ hipError_t launch_chain(damf_ctx *c, int n_chunks) {
   p.tau = c->cfg.tau;
   p.stats = c->ws.cstats;
   p.split = c->split;
-  chain_kernel<<<1, NT, 0, c->stream>>>(p);
-  return hipGetLastError();
+  DAMF_HIP(hipMemsetAsync(c->ws.cstats, 0, sizeof(ChainStats), s));
+  // the projections alternate between P and Pnext from chunk to chunk
+  double *Pc = c->P, *Pn = c->Pnext;
+  for (int ch = 0; ch < n_chunks; ++ch) {
+    chain_front_kernel<<<2, NT, 0, s>>>(p, ch, Pc);
+    chain_core_kernel<<<1, NT, 0, s>>>(p, ch);
+    chain_back_kernel<<<2, NT, 0, s>>>(p, ch, Pc, Pn);
+    double *t = Pc;
+    Pc = Pn;
+    Pn = t;
+  }
+  DAMF_HIP(hipGetLastError());
+  if (Pc != c->P)
+    DAMF_HIP(hipMemcpyAsync(c->P, Pc, 2 * (size_t)c->d * c->d * sizeof(double),
+                            hipMemcpyDeviceToDevice, s));
+  return hipSuccess;
 }
 
 }  // namespace damf
