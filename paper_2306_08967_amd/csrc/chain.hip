@@ -23,7 +23,7 @@
 
 #include "common.h"
 #include "damf_internal.h"
-#include "jacobi16.h"
+#include "jacobi_wave.h"
 
 namespace damf {
 
@@ -298,11 +298,10 @@ template <int RPL>
 __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double *sigma, double *scr,
                          double *lds, int *ilds, int *sweeps_out, uint64_t *ticks) {
   constexpr int NP = 64 * RPL;
-  using S = J16<NP, (NP == 64) ? 16 : 32>;
-  constexpr int CPG = S::CPG, RL = S::RL;
-  const int lane = tid() & 63, sl = lane & 15;
-  const int grp = __builtin_amdgcn_readfirstlane(tid() >> 6) * 4 + (lane >> 4);
-  const bool active = grp < S::G;
+  using S = JW<NP>;
+  static_assert(S::LDS <= LDS_DOUBLES && NT == 64 * S::NW, "Jacobi layout does not fit the workgroup");
+  const int lane = tid() & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid() >> 6);
   const int k = cs.k;
   const int NB = d + cs.rhoB, NC = d + cs.rhoC;
   const double *WBt = scr + OFF_WB, *WCt = scr + OFF_WC;
@@ -320,51 +319,48 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
     Lm[e] = v;
   }
   __syncthreads();
-  // K = diag(Sigma, 0) + L_m R_m^T, R_m = [W_C; R_C], column j held by group grp
-  J16Regs<S> J;
-  if (active) {
-    int jc[CPG];
+  // K = diag(Sigma, 0) + L_m R_m^T, R_m = [W_C; R_C]; wave w holds columns
+  // jw_col(w, c), lane l rows l + 64 r
+  JWRegs<S> J;
 #pragma unroll
-    for (int c = 0; c < CPG; ++c) {
-      jc[c] = j16_col<S>(grp, c);
+  for (int c = 0; c < S::C; ++c) {
 #pragma unroll
-      for (int r = 0; r < RL; ++r) J.a[c][r] = 0.0;
+    for (int r = 0; r < RPL; ++r) J.a[c][r] = 0.0;
+  }
+  for (int t = 0; t < k; ++t) {
+    double lm[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) lm[r] = Lm[t * NP + r * 64 + lane];
+#pragma unroll
+    for (int c = 0; c < S::C; ++c) {
+      const int j = jw_col<S>(w, c);
+      const double rm = (j < d) ? WCt[t * d + j] : ((j < NC) ? RC[(j - d) * k + t] : 0.0);
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) J.a[c][r] = fma(lm[r], rm, J.a[c][r]);
     }
-    for (int t = 0; t < k; ++t) {
-      double lm[RL];
+  }
 #pragma unroll
-      for (int r = 0; r < RL; ++r) lm[r] = Lm[t * NP + r * 16 + sl];
+  for (int c = 0; c < S::C; ++c) {
+    const int j = jw_col<S>(w, c);
 #pragma unroll
-      for (int c = 0; c < CPG; ++c) {
-        const int j = jc[c];
-        const double rm = (j < d) ? WCt[t * d + j] : ((j < NC) ? RC[(j - d) * k + t] : 0.0);
-#pragma unroll
-        for (int r = 0; r < RL; ++r) J.a[c][r] = fma(lm[r], rm, J.a[c][r]);
-      }
-    }
-#pragma unroll
-    for (int c = 0; c < CPG; ++c) {
-      const int j = jc[c];
-#pragma unroll
-      for (int r = 0; r < RL; ++r) {
-        const int i = r * 16 + sl;
-        if (i >= NB || j >= NC) J.a[c][r] = 0.0;
-        if (i == j && i < d) J.a[c][r] += sigma[i];
-        KG[j * NPMAX + i] = J.a[c][r];
-      }
+    for (int r = 0; r < RPL; ++r) {
+      const int i = r * 64 + lane;
+      if (i >= NB || j >= NC) J.a[c][r] = 0.0;
+      if (i == j && i < d) J.a[c][r] += sigma[i];
+      KG[j * NPMAX + i] = J.a[c][r];
     }
   }
   __syncthreads();
   int *flag = ilds;
   uint64_t tj0 = wall_clock64();
-  const int sweeps = jacobi16_sweeps<S>(J, lds, flag, 40, 1e-12);
+  const int sweeps = jw_sweeps<S>(J, lds, flag, 40, 1e-12);
   if (tid() == 0) ticks[1] += wall_clock64() - tj0;
   *sweeps_out = sweeps;
   // ---- singular values, descending order
   double *sv = lds;                        // NP values
   int *sid = ilds + 8;                     // NP column ids -> sorted order
   int *rank_of = ilds + 8 + 256;           // column id -> rank
-  const double *nrm = lds + 2 * S::G * S::SLOT;
+  const double *nrm = lds + S::NRM_OFF;
   __syncthreads();
   for (int j = tid(); j < NP; j += NT) {
     sv[j] = sqrt(nrm[j]);
@@ -403,19 +399,17 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
   const double smax = sv[0];
   const double cut = 1e-10 * smax;
   // E columns (top d), zero rows beyond NB
-  if (active) {
 #pragma unroll
-    for (int c = 0; c < CPG; ++c) {
-      const int j = j16_col<S>(grp, c);
-      const int rk = rank_of[j];
-      if (rk < d) {
-        const double sv_ = sv[rk];
-        const double inv = (sv_ > cut) ? 1.0 / sv_ : 0.0;
+  for (int c = 0; c < S::C; ++c) {
+    const int j = jw_col<S>(w, c);
+    const int rk = rank_of[j];
+    if (rk < d) {
+      const double sv_ = sv[rk];
+      const double inv = (sv_ > cut) ? 1.0 / sv_ : 0.0;
 #pragma unroll
-        for (int r = 0; r < RL; ++r) {
-          const int i = r * 16 + sl;
-          EG[rk * NPMAX + i] = (i < NB) ? J.a[c][r] * inv : 0.0;
-        }
+      for (int r = 0; r < RPL; ++r) {
+        const int i = r * 64 + lane;
+        EG[rk * NPMAX + i] = (i < NB) ? J.a[c][r] * inv : 0.0;
       }
     }
   }

@@ -1,0 +1,400 @@
+// jacobi_wave.h -- FP64 one-sided (Hestenes) Jacobi SVD with column blocks
+// owned by waves and rows spread over the lanes.
+//
+// Used for the rank-d t-SVD of the core in Step 2 (Sec. 4.5,
+// Rediagonalization; Theorem 2).  Rotating column pairs (a_i, a_j) until all
+// columns are orthogonal leaves the singular values as column norms and the
+// left singular vectors as normalised columns.
+//
+// Layout: the NP x NP matrix (NP = 64, 128, 192) is cut into 16 half-blocks of
+// B = NP / 16 columns.  Each of the 8 waves of the workgroup holds two of them
+// (a "top" and a "bottom" half-block, 2B columns) in VGPRs; lane l holds rows
+// l, l + 64, l + 128 of every column.  A sweep has 15 rounds: the half-blocks
+// follow the round-robin ("circle") schedule over the waves, so every pair of
+// half-blocks shares a wave in exactly one round.  In a round a wave rotates the
+// B x B cross pairs of its two half-blocks (B steps of B disjoint pairs, the
+// bottom block turned by one column per step); in round 0 it instead runs a
+// circle over all its 2B columns, which also covers the pairs inside each
+// half-block.  Each step needs only wave-level communication: the B dot
+// products are reduced across the 64 lanes by lane swaps (reduce-scatter) and
+// DPP, the pair's rotation is computed by the lane that ends up with its dot
+// product, and read back as a wave-uniform value.  Half-blocks move between
+// waves through LDS only between rounds (4 workgroup barriers per round).
+// Squared column norms live in LDS by column id; a wave touches only the norms
+// of the columns it holds.
+//
+// Rotations are applied in scaled form: column i is held as x_i with a scale
+// d_i (a_i = d_i x_i, scales in LDS by id).  The rotation (c, s = c t) of the
+// pair becomes x_i <- x_i - t (d_j / d_i) x_j, x_j <- x_j + t (d_i / d_j) x_i,
+// d <- c d: two FMAs per row instead of four.  Scales only shrink (c >= 1/sqrt 2)
+// and are folded back into the columns after every sweep.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include "common.h"
+#include "jacobi16.h"
+
+namespace damf {
+
+template <int NP_>
+struct JW {
+  static constexpr int NP = NP_;
+  static constexpr int NW = 8;             // waves
+  static constexpr int B = NP / 16;        // columns per half-block
+  static constexpr int C = 2 * B;          // columns per wave
+  static constexpr int RPL = NP / 64;      // rows per lane
+  static constexpr int Q = B / 4;          // reduced dot products per 16-lane row
+  static constexpr int SLOT = B * NP;      // doubles per half-block in the exchange buffer
+  static constexpr int NRM_OFF = NW * SLOT;
+  static constexpr int SCL_OFF = NRM_OFF + NP;
+  static constexpr int LDS = SCL_OFF + NP;  // exchange buffer + squared norms + scales
+  static_assert(NP % 64 == 0 && NP <= 192 && B % 4 == 0, "NP must be 64, 128 or 192");
+};
+
+template <class S>
+struct JWRegs {
+  double a[S::C][S::RPL];
+};
+
+// column id held by slot c of wave w at a sweep boundary
+template <class S>
+__device__ __forceinline__ int jw_col(int w, int c) {
+  return (c < S::B) ? (w * S::B + c) : ((S::NW + w) * S::B + (c - S::B));
+}
+
+__device__ __forceinline__ double readlane_d(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Lanes l < 32 get x[l] + x[l + 32]; lanes l >= 32 get y[l - 32] + y[l].
+__device__ __forceinline__ double xsum32(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(y), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+// 16-lane rows 0, 1, 2, 3 get x0 + x1, y0 + y1, x2 + x3, y2 + y3 (row sums lane by lane).
+__device__ __forceinline__ double xsum16(double x, double y) {
+  const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(y), false, false);
+  const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(y), false, false);
+  return __hiloint2double(hi[0], lo[0]) + __hiloint2double(hi[1], lo[1]);
+}
+__device__ __forceinline__ double wave_max_d(double x) {
+  x = row_max16(x);
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(x), __double2hiint(x), false, false);
+    x = fmax(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(x), __double2loint(x), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(x), __double2hiint(x), false, false);
+    x = fmax(__hiloint2double(hi[0], lo[0]), __hiloint2double(hi[1], lo[1]));
+  }
+  return x;
+}
+
+// Index of the pair whose wave total row `row` holds in reduced slot q, and
+// the lane that holds pair p's total at slot p % Q.
+template <class S>
+__device__ __forceinline__ int jw_pair(int row, int q) {
+  return q + (row & 1) * S::Q + (row >> 1) * (S::B / 2);
+}
+template <class S>
+__device__ __forceinline__ int jw_lane_of(int p) {
+  return 16 * (((p / (S::B / 2)) << 1) | ((p % (S::B / 2)) / S::Q)) + p % S::Q;
+}
+
+// v[p] (p < B): per-lane partial sums.  On return out[q] (q < Q), in every lane
+// of 16-lane row R, is the wave total of v[jw_pair(R, q)].
+template <class S>
+__device__ __forceinline__ void jw_reduce(const double (&v)[S::B], double (&out)[S::Q]) {
+  constexpr int B = S::B, Q = S::Q;
+  double h[B / 2];
+#pragma unroll
+  for (int p = 0; p < B / 2; ++p) h[p] = xsum32(v[p], v[p + B / 2]);
+#pragma unroll
+  for (int q = 0; q < Q; ++q) out[q] = row_sum16(xsum16(h[q], h[q + Q]));
+}
+
+// Exact squared norms of the wave's 2B columns into nrm[] by column id (the
+// wave holds its sweep-boundary half-blocks w and NW + w).
+template <class S>
+__device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double *nrm, int w) {
+  constexpr int B = S::B, Q = S::Q, RPL = S::RPL;
+  const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
+#pragma unroll
+  for (int half = 0; half < 2; ++half) {
+    double v[B], out[Q];
+#pragma unroll
+    for (int p = 0; p < B; ++p) {
+      double s = 0.0;
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) s = fma(J.a[half * B + p][r], J.a[half * B + p][r], s);
+      v[p] = s;
+    }
+    jw_reduce<S>(v, out);
+    double mine = out[0];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) mine = (sl == q) ? out[q] : mine;
+    if (sl < Q) nrm[jw_col<S>(w, half * B + jw_pair<S>(row, sl))] = mine;
+  }
+}
+
+// Pair maps: pair p of a step rotates slots PM::a(p) and PM::b(p).
+// Cross: top slot p with bottom slot p.  Intra: the pairs of a circle inside
+// each half-block (top half-block pairs first, then the bottom one).
+template <class S>
+struct JWCross {
+  static constexpr int a(int p) { return p; }
+  static constexpr int b(int p) { return S::B + p; }
+};
+template <class S>
+struct JWIntra {
+  static constexpr int H = S::B / 2;
+  static constexpr int a(int p) { return (p < H) ? p : S::B + (p - H); }
+  static constexpr int b(int p) { return (p < H) ? H + p : S::B + H + (p - H); }
+};
+
+// One step: rotate the B disjoint pairs (slot PM::a(p), slot PM::b(p)).
+// ids(p, it, ib) gives the column ids the two slots of pair p hold.
+template <class S, class PM, class IdF>
+__device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, double floor2,
+                                        double tol2, double conv2, IdF ids, int &rot, int &big) {
+  constexpr int B = S::B, Q = S::Q, RPL = S::RPL;
+  const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
+  double v[B], g[Q];
+#pragma unroll
+  for (int p = 0; p < B; ++p) {
+    double s = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) s = fma(J.a[PM::a(p)][r], J.a[PM::b(p)][r], s);
+    v[p] = s;
+  }
+  jw_reduce<S>(v, g);
+  // lane (row, q < Q) computes the rotation of pair jw_pair(row, q)
+  double myg = g[0];
+#pragma unroll
+  for (int q = 1; q < Q; ++q) myg = (sl == q) ? g[q] : myg;
+  const bool plane = sl < Q;
+  int it, ib;
+  ids(plane ? jw_pair<S>(row, sl) : 0, it, ib);
+  const double al = nrm[it], be = nrm[ib];
+  const double di = scl[it], dj = scl[ib];
+  const double gt = myg * (di * dj);  // a_i . a_j
+  const bool live = plane && al > floor2 && be > floor2;
+  const double g2 = gt * gt, ab = al * be;
+  const bool doit = live && g2 > tol2 * ab;
+  big |= (live && g2 >= conv2 * ab) ? 1 : 0;
+  // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 g),
+  // as sign(be - al) 2g / (|be - al| + sqrt((be - al)^2 + 4 g^2))
+  const double dd = be - al, gg = doit ? 2.0 * gt : 0.0;
+  const double q2 = fma(dd, dd, gg * gg);
+  const double den = fabs(dd) + q2 * rsqrt_nr(q2);
+  const double t = doit ? (dd >= 0.0 ? gg : -gg) * rcp_nr(den) : 0.0;
+  const double cs = rsqrt_nr(fma(t, t, 1.0));
+  const double inv = rcp_nr(di * dj);
+  const double t1 = t * (dj * dj) * inv, t2 = t * (di * di) * inv;
+  if (doit) {
+    nrm[it] = fma(-t, gt, al);
+    nrm[ib] = fma(t, gt, be);
+    scl[it] = cs * di;
+    scl[ib] = cs * dj;
+  }
+  rot += doit ? 1 : 0;
+#pragma unroll
+  for (int p = 0; p < B; ++p) {
+    const int L = jw_lane_of<S>(p);
+    const double u1 = readlane_d(t1, L), u2 = readlane_d(t2, L);
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      const double x = J.a[PM::a(p)][r], y = J.a[PM::b(p)][r];
+      J.a[PM::a(p)][r] = fma(-u1, y, x);
+      J.a[PM::b(p)][r] = fma(u2, x, y);
+    }
+  }
+}
+
+// circle move inside each half-block (B slots: B/2 tops, then B/2 bottoms):
+// top p <- top p-1 (p >= 2), top 1 <- bottom 0, bottom p <- bottom p+1,
+// last bottom <- last top
+template <class S>
+__device__ __forceinline__ void jw_intra_move(JWRegs<S> &J) {
+  constexpr int B = S::B, H = B / 2, RPL = S::RPL;
+#pragma unroll
+  for (int o = 0; o < 2 * B; o += B) {
+    double b0[RPL], tl[RPL];
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) {
+      b0[r] = J.a[o + H][r];
+      tl[r] = J.a[o + H - 1][r];
+    }
+#pragma unroll
+    for (int p = H - 1; p >= 2; --p) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) J.a[o + p][r] = J.a[o + p - 1][r];
+    }
+    if (H >= 2) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) J.a[o + 1][r] = b0[r];
+    }
+#pragma unroll
+    for (int p = 0; p < H - 1; ++p) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) J.a[o + H + p][r] = J.a[o + H + p + 1][r];
+    }
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) J.a[o + B - 1][r] = tl[r];
+  }
+}
+
+// turn the bottom half-block by one column: bottom p <- bottom p+1
+template <class S>
+__device__ __forceinline__ void jw_cross_move(JWRegs<S> &J) {
+  constexpr int B = S::B, RPL = S::RPL;
+  double b0[RPL];
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) b0[r] = J.a[B][r];
+#pragma unroll
+  for (int p = 0; p < B - 1; ++p) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) J.a[B + p][r] = J.a[B + p + 1][r];
+  }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) J.a[2 * B - 1][r] = b0[r];
+}
+
+template <class S>
+__device__ __forceinline__ void jw_put(const JWRegs<S> &J, double *xb, int slot, int c0, int lane) {
+#pragma unroll
+  for (int j = 0; j < S::B; ++j) {
+#pragma unroll
+    for (int r = 0; r < S::RPL; ++r) xb[slot * S::SLOT + j * S::NP + r * 64 + lane] = J.a[c0 + j][r];
+  }
+}
+template <class S>
+__device__ __forceinline__ void jw_get(JWRegs<S> &J, const double *xb, int slot, int c0, int lane) {
+#pragma unroll
+  for (int j = 0; j < S::B; ++j) {
+#pragma unroll
+    for (int r = 0; r < S::RPL; ++r) J.a[c0 + j][r] = xb[slot * S::SLOT + j * S::NP + r * 64 + lane];
+  }
+}
+
+// Move the half-blocks to the next round of the circle over waves:
+// new top[w] = old top[w-1] (w >= 2), new top[1] = old bottom[0], top[0] stays;
+// new bottom[w] = old bottom[w+1] (w < 7), new bottom[7] = old top[7].
+template <class S>
+__device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int lane) {
+  constexpr int B = S::B, RPL = S::RPL;
+  jw_put<S>(J, xb, (w == 0) ? 7 : w - 1, B, lane);  // bottoms, by destination wave
+  __syncthreads();
+  if (w < 7) {
+    jw_get<S>(J, xb, w, B, lane);
+  } else {
+#pragma unroll
+    for (int j = 0; j < B; ++j) {
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) J.a[B + j][r] = J.a[j][r];
+    }
+  }
+  __syncthreads();
+  if (w >= 1 && w <= 6) jw_put<S>(J, xb, w, 0, lane);  // tops of waves 1..6, by source wave
+  __syncthreads();
+  if (w == 1)
+    jw_get<S>(J, xb, 7, 0, lane);
+  else if (w >= 2)
+    jw_get<S>(J, xb, w - 1, 0, lane);
+  __syncthreads();
+}
+
+// Sweeps until one applies no rotation or all its rotations were below
+// sqrt(tol) (or max_sweeps); returns the sweep count.  lds_flag points to 2
+// ints of LDS.  A pair is rotated when |a_i . a_j| > tol ||a_i|| ||a_j|| and
+// neither column is numerically zero (norm^2 below 1e-30 of the largest).
+// Every thread of the 512-thread workgroup calls it; on return the columns
+// are back in their sweep-boundary slots (jw_col) and the squared norms are
+// in lds[S::NRM_OFF + id].
+template <class S>
+__device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweeps, double tol) {
+  constexpr int B = S::B, RPL = S::RPL;
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  double *xb = lds;
+  double *nrm = lds + S::NRM_OFF;
+  double *scl = lds + S::SCL_OFF;
+  jw_norms<S>(J, nrm, w);
+  for (int j = threadIdx.x; j < S::NP; j += blockDim.x) scl[j] = 1.0;
+  __syncthreads();
+  const double tol2 = tol * tol, conv2 = tol;  // (sqrt(tol))^2
+  int sweeps = 0;
+  for (; sweeps < max_sweeps; ++sweeps) {
+    int rot = 0, big = 0;
+    double mx = 0.0;
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) mx = fmax(mx, nrm[r * 64 + lane]);
+    const double floor2 = 1e-30 * wave_max_d(mx);
+    for (int round = 0; round < 2 * S::NW - 1; ++round) {
+      const int ht = j16_top_id<2 * S::NW>(w, round), hb = j16_bot_id<2 * S::NW>(w, round);
+      if (round == 0) {
+        // pairs inside each of the two half-blocks: a circle of B - 1 steps in each
+        for (int st = 0; st < B - 1; ++st) {
+          jw_step<S, JWIntra<S>>(J, nrm, scl, floor2, tol2, conv2,
+                                 [&](int p, int &it, int &ib) {
+                                   const int i = (p < B / 2) ? p : p - B / 2;
+                                   const int h = (p < B / 2) ? ht : hb;
+                                   it = h * B + j16_top_id<B>(i, st);
+                                   ib = h * B + j16_bot_id<B>(i, st);
+                                 },
+                                 rot, big);
+          jw_intra_move<S>(J);
+        }
+      }
+      // cross pairs of the two half-blocks: B steps, the bottom turned by one each
+      for (int sh = 0; sh < B; ++sh) {
+        jw_step<S, JWCross<S>>(J, nrm, scl, floor2, tol2, conv2,
+                               [&](int p, int &it, int &ib) {
+                                 int q = p + sh;
+                                 if (q >= B) q -= B;
+                                 it = ht * B + p;
+                                 ib = hb * B + q;
+                               },
+                               rot, big);
+        jw_cross_move<S>(J);
+      }
+      jw_exchange<S>(J, xb, w, lane);
+    }
+    // fold the scales into the columns (each wave its own sweep-boundary
+    // columns), then exact norms; stop when no pair rotated in this sweep, or
+    // when every rotation of this sweep was below sqrt(tol): Jacobi converges
+    // quadratically, so the off-diagonal left after such a sweep is O(tol)
+    // and another sweep would find nothing.
+#pragma unroll
+    for (int c = 0; c < S::C; ++c) {
+      const double dc = scl[jw_col<S>(w, c)];
+#pragma unroll
+      for (int r = 0; r < RPL; ++r) J.a[c][r] *= dc;
+    }
+    __syncthreads();
+    for (int j = threadIdx.x; j < S::NP; j += blockDim.x) scl[j] = 1.0;
+    jw_norms<S>(J, nrm, w);
+    if (threadIdx.x == 0) {
+      lds_flag[0] = 0;
+      lds_flag[1] = 0;
+    }
+    __syncthreads();
+    if (rot > 0) atomicAdd(lds_flag, rot);
+    if (big) atomicOr(lds_flag + 1, 1);
+    __syncthreads();
+    const int total = lds_flag[0], any_big = lds_flag[1];
+    __syncthreads();
+    if (total == 0 || !any_big) {
+      ++sweeps;
+      break;
+    }
+  }
+  return sweeps;
+}
+
+}  // namespace damf
