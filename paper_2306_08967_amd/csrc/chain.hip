@@ -856,7 +856,7 @@ struct PhaseClock {
 };
 
 __global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, const double *Pc) {
-  __shared__ double lds[LDS_DOUBLES];
+  __shared__ __align__(16) double lds[LDS_DOUBLES];
   __shared__ __align__(16) int ilds[1024];
   const int side = blockIdx.x;
   const int d = p.d;
@@ -888,7 +888,7 @@ __global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, 
 }
 
 __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
-  __shared__ double lds[LDS_DOUBLES];
+  __shared__ __align__(16) double lds[LDS_DOUBLES];
   __shared__ __align__(16) int ilds[1024];
   __shared__ uint64_t jt[8];
   const int d = p.d;
@@ -931,7 +931,7 @@ __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
 
 __global__ __launch_bounds__(NT) void chain_back_kernel(ChainParams p, int ch, const double *Pc,
                                                         double *Pn) {
-  __shared__ double lds[LDS_DOUBLES];
+  __shared__ __align__(16) double lds[LDS_DOUBLES];
   __shared__ __align__(16) int ilds[1024];
   const int side = blockIdx.x;
   const int d = p.d;

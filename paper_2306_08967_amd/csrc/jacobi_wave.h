@@ -18,7 +18,7 @@
 // half-block.  Each step needs only wave-level communication: the B dot
 // products are reduced across the 64 lanes by lane swaps (reduce-scatter) and
 // DPP, the pair's rotation is computed by the lane that ends up with its dot
-// product, and read back as a wave-uniform value.  Half-blocks move between
+// product, and read back by every lane from LDS.  Half-blocks move between
 // waves through LDS only between rounds (4 workgroup barriers per round).
 // Squared column norms live in LDS by column id; a wave touches only the norms
 // of the columns it holds.
@@ -48,7 +48,8 @@ struct JW {
   static constexpr int SLOT = B * NP;      // doubles per half-block in the exchange buffer
   static constexpr int NRM_OFF = NW * SLOT;
   static constexpr int SCL_OFF = NRM_OFF + NP;
-  static constexpr int LDS = SCL_OFF + NP;  // exchange buffer + squared norms + scales
+  static constexpr int BC_OFF = SCL_OFF + NP;  // per wave: B rotation factor pairs
+  static constexpr int LDS = BC_OFF + NW * 2 * B;  // exchange, norms, scales, factors
   static_assert(NP % 64 == 0 && NP <= 192 && B % 4 == 0, "NP must be 64, 128 or 192");
 };
 
@@ -61,11 +62,6 @@ struct JWRegs {
 template <class S>
 __device__ __forceinline__ int jw_col(int w, int c) {
   return (c < S::B) ? (w * S::B + c) : ((S::NW + w) * S::B + (c - S::B));
-}
-
-__device__ __forceinline__ double readlane_d(double x, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
-                          __builtin_amdgcn_readlane(__double2loint(x), l));
 }
 
 // Lanes l < 32 get x[l] + x[l + 32]; lanes l >= 32 get y[l - 32] + y[l].
@@ -95,15 +91,10 @@ __device__ __forceinline__ double wave_max_d(double x) {
   return x;
 }
 
-// Index of the pair whose wave total row `row` holds in reduced slot q, and
-// the lane that holds pair p's total at slot p % Q.
+// Index of the pair whose wave total 16-lane row `row` holds in reduced slot q.
 template <class S>
 __device__ __forceinline__ int jw_pair(int row, int q) {
   return q + (row & 1) * S::Q + (row >> 1) * (S::B / 2);
-}
-template <class S>
-__device__ __forceinline__ int jw_lane_of(int p) {
-  return 16 * (((p / (S::B / 2)) << 1) | ((p % (S::B / 2)) / S::Q)) + p % S::Q;
 }
 
 // v[p] (p < B): per-lane partial sums.  On return out[q] (q < Q), in every lane
@@ -158,10 +149,14 @@ struct JWIntra {
 };
 
 // One step: rotate the B disjoint pairs (slot PM::a(p), slot PM::b(p)).
-// ids(p, it, ib) gives the column ids the two slots of pair p hold.
+// ids(p, it, ib) gives the column ids the two slots of pair p hold.  bc: the
+// wave's B (t1, t2) slots in LDS; the lane that computes a pair's rotation
+// writes it there and every lane reads all B back (broadcast reads; LDS
+// operations of one wave complete in order).
 template <class S, class PM, class IdF>
-__device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, double floor2,
-                                        double tol2, double conv2, IdF ids, int &rot, int &big) {
+__device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, double2 *bc,
+                                        double floor2, double tol2, double conv2, IdF ids, int &rot,
+                                        int &big) {
   constexpr int B = S::B, Q = S::Q, RPL = S::RPL;
   const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
   double v[B], g[Q];
@@ -178,8 +173,9 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, 
 #pragma unroll
   for (int q = 1; q < Q; ++q) myg = (sl == q) ? g[q] : myg;
   const bool plane = sl < Q;
+  const int pair = plane ? jw_pair<S>(row, sl) : 0;
   int it, ib;
-  ids(plane ? jw_pair<S>(row, sl) : 0, it, ib);
+  ids(pair, it, ib);
   const double al = nrm[it], be = nrm[ib];
   const double di = scl[it], dj = scl[ib];
   const double gt = myg * (di * dj);  // a_i . a_j
@@ -203,10 +199,12 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, 
     scl[ib] = cs * dj;
   }
   rot += doit ? 1 : 0;
+  if (plane) bc[pair] = make_double2(t1, t2);
+  __builtin_amdgcn_wave_barrier();
 #pragma unroll
   for (int p = 0; p < B; ++p) {
-    const int L = jw_lane_of<S>(p);
-    const double u1 = readlane_d(t1, L), u2 = readlane_d(t2, L);
+    const double2 u = bc[p];
+    const double u1 = u.x, u2 = u.y;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       const double x = J.a[PM::a(p)][r], y = J.a[PM::b(p)][r];
@@ -324,6 +322,7 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
   double *xb = lds;
   double *nrm = lds + S::NRM_OFF;
   double *scl = lds + S::SCL_OFF;
+  double2 *bc = reinterpret_cast<double2 *>(lds + S::BC_OFF) + w * B;
   jw_norms<S>(J, nrm, w);
   for (int j = threadIdx.x; j < S::NP; j += blockDim.x) scl[j] = 1.0;
   __syncthreads();
@@ -340,7 +339,7 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
       if (round == 0) {
         // pairs inside each of the two half-blocks: a circle of B - 1 steps in each
         for (int st = 0; st < B - 1; ++st) {
-          jw_step<S, JWIntra<S>>(J, nrm, scl, floor2, tol2, conv2,
+          jw_step<S, JWIntra<S>>(J, nrm, scl, bc, floor2, tol2, conv2,
                                  [&](int p, int &it, int &ib) {
                                    const int i = (p < B / 2) ? p : p - B / 2;
                                    const int h = (p < B / 2) ? ht : hb;
@@ -353,7 +352,7 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
       }
       // cross pairs of the two half-blocks: B steps, the bottom turned by one each
       for (int sh = 0; sh < B; ++sh) {
-        jw_step<S, JWCross<S>>(J, nrm, scl, floor2, tol2, conv2,
+        jw_step<S, JWCross<S>>(J, nrm, scl, bc, floor2, tol2, conv2,
                                [&](int p, int &it, int &ib) {
                                  int q = p + sh;
                                  if (q >= B) q -= B;
