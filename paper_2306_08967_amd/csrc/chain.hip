@@ -629,10 +629,137 @@ __device__ __noinline__ void mul_PF(int d, const double *Po, const double *F, do
   __syncthreads();
 }
 
+// (value, index) of the larger |entry|, ties to the lower index: a total
+// order, so a butterfly leaves every lane with the same winner.
+__device__ __forceinline__ void argmax_take(double &v, int &i, double ov, int oi) {
+  const bool take = (ov > v) || (ov == v && oi < i);
+  v = take ? ov : v;
+  i = take ? oi : i;
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double &v, int &i) {
+  argmax_take(v, i, dpp_d<CTRL>(v), __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ void argmax_wave(double &v, int &i) {
+  argmax_dpp<0xB1>(v, i);   // quad_perm [1,0,3,2]
+  argmax_dpp<0x4E>(v, i);   // quad_perm [2,3,0,1]
+  argmax_dpp<0x141>(v, i);  // row_half_mirror
+  argmax_dpp<0x140>(v, i);  // row_mirror
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    const auto ii = __builtin_amdgcn_permlane16_swap(i, i, false, false);
+    double va = __hiloint2double(hi[0], lo[0]), vb = __hiloint2double(hi[1], lo[1]);
+    int ia = ii[0], ib = ii[1];
+    argmax_take(va, ia, vb, ib);
+    v = va;
+    i = ia;
+  }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    const auto ii = __builtin_amdgcn_permlane32_swap(i, i, false, false);
+    double va = __hiloint2double(hi[0], lo[0]), vb = __hiloint2double(hi[1], lo[1]);
+    int ia = ii[0], ib = ii[1];
+    argmax_take(va, ia, vb, ib);
+    v = va;
+    i = ia;
+  }
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Partial-pivoting LU of the panel A[j0.., j0 .. j0 + jb) (jb <= 16), by one
+// wave with the panel in VGPRs: lane l holds rows l and l + 64.  Pivot search
+// by a wave argmax (DPP and lane swaps); the two rows to swap are passed
+// through LDS (rb, 2 x 16 doubles) and read back by every lane, then the
+// scaling and rank-1 updates run lane by lane.  Records piv[j]; sets *bad on a
+// zero pivot column.
+__device__ __forceinline__ void lu_panel(double *A, int d, int j0, int jb, int *piv, int *bad,
+                                         double *rb) {
+  constexpr int LUB = 16;
+  const int lane = tid() & 63;
+  double pr[2][LUB];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = lane + 64 * h;
+#pragma unroll
+    for (int t = 0; t < LUB; ++t) pr[h][t] = (i >= j0 && i < d && t < jb) ? A[i * d + j0 + t] : 0.0;
+  }
+#pragma unroll
+  for (int t = 0; t < LUB; ++t) {
+    if (t < jb) {
+      const int j = j0 + t;
+      double v = (lane >= j && lane < d) ? fabs(pr[0][t]) : -1.0;
+      int idx = lane;
+      argmax_take(v, idx, (lane + 64 >= j && lane + 64 < d) ? fabs(pr[1][t]) : -1.0, lane + 64);
+      argmax_wave(v, idx);
+      idx = __builtin_amdgcn_readfirstlane(idx);
+      if (lane == 0) {
+        piv[j] = idx;
+        if (!(v > 0.0)) *bad = 1;
+      }
+      // rows j and idx of the panel, through LDS (rb: 2 x LUB doubles; LDS
+      // operations of one wave complete in order)
+      const int jh = j >> 6, jl = j & 63, ph = idx >> 6, pl = idx & 63;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        if (lane + 64 * h == j) {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) rb[c] = pr[h][c];
+        }
+        if (lane + 64 * h == idx) {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) rb[LUB + c] = pr[h][c];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      double rowj[LUB], rowp[LUB];
+#pragma unroll
+      for (int c = 0; c < LUB; ++c) {
+        rowj[c] = rb[c];
+        rowp[c] = rb[LUB + c];
+      }
+      __builtin_amdgcn_wave_barrier();
+      const bool swap = idx != j;
+      const bool wj0 = swap && lane == jl && jh == 0, wj1 = swap && lane == jl && jh == 1;
+      const bool wp0 = swap && lane == pl && ph == 0, wp1 = swap && lane == pl && ph == 1;
+#pragma unroll
+      for (int c = 0; c < LUB; ++c) {
+        pr[0][c] = wj0 ? rowp[c] : (wp0 ? rowj[c] : pr[0][c]);
+        pr[1][c] = wj1 ? rowp[c] : (wp1 ? rowj[c] : pr[1][c]);
+      }
+      const double pv = rowp[t];
+      const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int i = lane + 64 * h;
+        const bool below = i > j && i < d;
+        const double l = below ? pr[h][t] * inv : 0.0;
+        pr[h][t] = below ? l : pr[h][t];
+#pragma unroll
+        for (int c = 0; c < LUB; ++c)
+          if (c > t) pr[h][c] = fma(-l, rowp[c], pr[h][c]);
+      }
+    }
+  }
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    const int i = lane + 64 * h;
+    if (i >= j0 && i < d) {
+#pragma unroll
+      for (int t = 0; t < LUB; ++t)
+        if (t < jb) A[i * d + j0 + t] = pr[h][t];
+    }
+  }
+}
+
 // LU with partial pivoting of Pn (d x d) in LDS, then X Pn = Dl for `rows`
 // row vectors; adds X to M_b[rows] (and to R when given).  Returns 0, or 1 if
 // a zero pivot was met.
-__device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const double *Dl, const int32_t *rows,
+__device__ __forceinline__ int lu_solve_scatter(int d, const double *Pn, const double *Dl, const int32_t *rows,
                                 int nrows, float *Mb, float *Rr, double *lds, int *ilds,
                                 bool split) {
   double *A = lds;  // d x d
@@ -650,48 +777,7 @@ __device__ __noinline__ int lu_solve_scatter(int d, const double *Pn, const doub
   constexpr int LUB = 16;
   for (int j0 = 0; j0 < d; j0 += LUB) {
     const int jb = min(LUB, d - j0);
-    if (tid() < 64) {
-      for (int j = j0; j < j0 + jb; ++j) {
-        double v = -1.0;
-        int idx = j;
-        for (int i = j + lane; i < d; i += 64) {
-          const double a = fabs(A[i * d + j]);
-          if (a > v) {
-            v = a;
-            idx = i;
-          }
-        }
-#pragma unroll
-        for (int off = 32; off >= 1; off >>= 1) {
-          const double ov = __shfl_xor(v, off, 64);
-          const int oi = __shfl_xor(idx, off, 64);
-          if (ov > v || (ov == v && oi < idx)) {
-            v = ov;
-            idx = oi;
-          }
-        }
-        if (lane == 0) {
-          piv[j] = idx;
-          if (!(v > 0.0)) s_bad = 1;
-        }
-        if (idx != j && lane < jb) {
-          const int c = j0 + lane;
-          const double t = A[j * d + c];
-          A[j * d + c] = A[idx * d + c];
-          A[idx * d + c] = t;
-        }
-        __builtin_amdgcn_wave_barrier();
-        const double pv = A[j * d + j];
-        __builtin_amdgcn_wave_barrier();
-        const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
-        for (int i = j + 1 + lane; i < d; i += 64) {
-          const double l = A[i * d + j] * inv;
-          A[i * d + j] = l;
-          for (int c = j + 1; c < j0 + jb; ++c) A[i * d + c] -= l * A[j * d + c];
-        }
-        __builtin_amdgcn_wave_barrier();
-      }
-    }
+    if (tid() < 64) lu_panel(A, d, j0, jb, piv, &s_bad, lds + DMAX * DMAX);
     __syncthreads();
     // row swaps of this panel on the columns outside it, in pivot order
     for (int c = tid(); c < d; c += NT) {
