@@ -701,36 +701,53 @@ __device__ __forceinline__ void lu_panel(double *A, int d, int j0, int jb, int *
         piv[j] = idx;
         if (!(v > 0.0)) *bad = 1;
       }
-      // rows j and idx of the panel, through LDS (rb: 2 x LUB doubles; LDS
-      // operations of one wave complete in order)
+      // the pivot row (and row j when they differ) through LDS (rb: 2 x LUB
+      // doubles; LDS operations of one wave complete in order).  j, idx and
+      // their halves are wave-uniform, so only the swap's two lanes select.
       const int jh = j >> 6, jl = j & 63, ph = idx >> 6, pl = idx & 63;
-#pragma unroll
-      for (int h = 0; h < 2; ++h) {
-        if (lane + 64 * h == j) {
-#pragma unroll
-          for (int c = 0; c < LUB; ++c) rb[c] = pr[h][c];
-        }
-        if (lane + 64 * h == idx) {
-#pragma unroll
-          for (int c = 0; c < LUB; ++c) rb[LUB + c] = pr[h][c];
-        }
-      }
-      __builtin_amdgcn_wave_barrier();
-      double rowj[LUB], rowp[LUB];
-#pragma unroll
-      for (int c = 0; c < LUB; ++c) {
-        rowj[c] = rb[c];
-        rowp[c] = rb[LUB + c];
-      }
-      __builtin_amdgcn_wave_barrier();
       const bool swap = idx != j;
-      const bool wj0 = swap && lane == jl && jh == 0, wj1 = swap && lane == jl && jh == 1;
-      const bool wp0 = swap && lane == pl && ph == 0, wp1 = swap && lane == pl && ph == 1;
+      if (lane == pl) {
+        if (ph == 0) {
 #pragma unroll
-      for (int c = 0; c < LUB; ++c) {
-        pr[0][c] = wj0 ? rowp[c] : (wp0 ? rowj[c] : pr[0][c]);
-        pr[1][c] = wj1 ? rowp[c] : (wp1 ? rowj[c] : pr[1][c]);
+          for (int c = 0; c < LUB; ++c) rb[LUB + c] = pr[0][c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) rb[LUB + c] = pr[1][c];
+        }
       }
+      if (swap && lane == jl) {
+        if (jh == 0) {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) rb[c] = pr[0][c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) rb[c] = pr[1][c];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
+      double rowp[LUB];
+#pragma unroll
+      for (int c = 0; c < LUB; ++c) rowp[c] = rb[LUB + c];
+      if (swap) {
+        double rowj[LUB];
+#pragma unroll
+        for (int c = 0; c < LUB; ++c) rowj[c] = rb[c];
+        if (jh == 0) {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) pr[0][c] = (lane == jl) ? rowp[c] : pr[0][c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) pr[1][c] = (lane == jl) ? rowp[c] : pr[1][c];
+        }
+        if (ph == 0) {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) pr[0][c] = (lane == pl) ? rowj[c] : pr[0][c];
+        } else {
+#pragma unroll
+          for (int c = 0; c < LUB; ++c) pr[1][c] = (lane == pl) ? rowj[c] : pr[1][c];
+        }
+      }
+      __builtin_amdgcn_wave_barrier();
       const double pv = rowp[t];
       const double inv = (pv != 0.0) ? 1.0 / pv : 0.0;
 #pragma unroll
