@@ -307,36 +307,46 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
   const double *WBt = scr + OFF_WB, *WCt = scr + OFF_WC;
   const double *RB = scr + OFF_RB, *RC = scr + OFF_RC;
   double *KG = scr + OFF_KG, *EG = scr + OFF_EG, *HG = scr + OFF_HG, *TH = scr + OFF_TH;
-  // L_m = [W_B; R_B] into LDS as [t][i] (k x NP)
-  double *Lm = lds;
-  for (int e = tid(); e < k * NP; e += NT) {
-    int t = e / NP, i = e - t * NP;
-    double v = 0.0;
-    if (i < d)
-      v = WBt[t * d + i];
-    else if (i < NB)
-      v = RB[(i - d) * k + t];
-    Lm[e] = v;
-  }
-  __syncthreads();
-  // K = diag(Sigma, 0) + L_m R_m^T, R_m = [W_C; R_C]; wave w holds columns
-  // jw_col(w, c), lane l rows l + 64 r
+  // K = diag(Sigma, 0) + L_m R_m^T with L_m = [W_B; R_B], R_m = [W_C; R_C]
+  // (NP x k each); wave w holds columns jw_col(w, c), lane l rows l + 64 r.
+  // Both factors are staged in LDS as [t][i] in chunks of KC values of t;
+  // a wave reads its columns' R_m entries as broadcasts.
+  constexpr int KC = 32;
+  static_assert(2 * KC * NP <= LDS_DOUBLES, "K build staging does not fit");
+  double *Lm = lds, *Rm = lds + KC * NP;
   JWRegs<S> J;
 #pragma unroll
   for (int c = 0; c < S::C; ++c) {
 #pragma unroll
     for (int r = 0; r < RPL; ++r) J.a[c][r] = 0.0;
   }
-  for (int t = 0; t < k; ++t) {
-    double lm[RPL];
+  for (int t0 = 0; t0 < k; t0 += KC) {
+    const int tn = min(KC, k - t0);
+    __syncthreads();
+    for (int e = tid(); e < tn * NP; e += NT) {
+      const int t = t0 + e / NP, i = e % NP;
+      double lv = 0.0, rv = 0.0;
+      if (i < d) {
+        lv = WBt[t * d + i];
+        rv = WCt[t * d + i];
+      } else {
+        if (i < NB) lv = RB[(i - d) * k + t];
+        if (i < NC) rv = RC[(i - d) * k + t];
+      }
+      Lm[e] = lv;
+      Rm[e] = rv;
+    }
+    __syncthreads();
+    for (int t = 0; t < tn; ++t) {
+      double lm[RPL];
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) lm[r] = Lm[t * NP + r * 64 + lane];
+      for (int r = 0; r < RPL; ++r) lm[r] = Lm[t * NP + r * 64 + lane];
 #pragma unroll
-    for (int c = 0; c < S::C; ++c) {
-      const int j = jw_col<S>(w, c);
-      const double rm = (j < d) ? WCt[t * d + j] : ((j < NC) ? RC[(j - d) * k + t] : 0.0);
+      for (int c = 0; c < S::C; ++c) {
+        const double rm = Rm[t * NP + jw_col<S>(w, c)];
 #pragma unroll
-      for (int r = 0; r < RPL; ++r) J.a[c][r] = fma(lm[r], rm, J.a[c][r]);
+        for (int r = 0; r < RPL; ++r) J.a[c][r] = fma(lm[r], rm, J.a[c][r]);
+      }
     }
   }
 #pragma unroll
@@ -414,39 +424,67 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
     }
   }
   __syncthreads();
-  // ---- H = K^T E Theta^-1 for the top d (tiles of 32 rows of K and E)
+  // ---- H = K^T E Theta^-1 for the top d: rows of K and E staged through LDS
+  // 32 at a time; thread (jb, cb) accumulates rows j = JR jb .. + JR of H and
+  // columns c = 8 cb .. + 8 (register block, operands read as 16-byte pairs).
   {
-    const int c = tid() & 127, g = tid() >> 7;
-    constexpr int JPT = NP / NG;  // j values per thread
-    double acc[JPT];
+    constexpr int JR = NP / 32;
+    constexpr int ET = DMAX + 2, KT = NP + 2;  // padded row strides (even: 16-byte rows)
+    static_assert(32 * (ET + KT) <= LDS_DOUBLES && NT == 512, "H staging does not fit");
+    const int cb = tid() & 15, jb = tid() >> 4;
+    double acc[JR][8];
 #pragma unroll
-    for (int q = 0; q < JPT; ++q) acc[q] = 0.0;
-    double *Et = lds;             // [32][128]
-    double *Kt = lds + 32 * 128;  // [32][NP]
+    for (int q = 0; q < JR; ++q) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[q][u] = 0.0;
+    }
+    double *Et = lds;            // [32][ET]
+    double *Kt = lds + 32 * ET;  // [32][KT]
     for (int i0 = 0; i0 < NB; i0 += 32) {
-      for (int e = tid(); e < 32 * 128; e += NT) {
-        int ii = e >> 7, cc = e & 127;
-        Et[e] = (cc < d && i0 + ii < NB) ? EG[cc * NPMAX + i0 + ii] : 0.0;
+      for (int e = tid(); e < 32 * DMAX; e += NT) {
+        const int ii = e & 31, cc = e >> 5;
+        Et[ii * ET + cc] = (cc < d && i0 + ii < NB) ? EG[cc * NPMAX + i0 + ii] : 0.0;
       }
       for (int e = tid(); e < 32 * NP; e += NT) {
-        int jj = e / 32, ii = e - jj * 32;
-        Kt[ii * NP + jj] = (i0 + ii < NB) ? KG[jj * NPMAX + i0 + ii] : 0.0;
+        const int ii = e & 31, jj = e >> 5;
+        Kt[ii * KT + jj] = (i0 + ii < NB) ? KG[jj * NPMAX + i0 + ii] : 0.0;
       }
       __syncthreads();
       for (int ii = 0; ii < 32; ++ii) {
-        const double ev = Et[ii * 128 + c];
+        double ev[8], kv[JR];
+        const double2 *ep = reinterpret_cast<const double2 *>(Et + ii * ET + 8 * cb);
+        const double2 *kp = reinterpret_cast<const double2 *>(Kt + ii * KT + JR * jb);
 #pragma unroll
-        for (int q = 0; q < JPT; ++q) acc[q] = fma(Kt[ii * NP + g + NG * q], ev, acc[q]);
+        for (int u = 0; u < 4; ++u) {
+          const double2 x = ep[u];
+          ev[2 * u] = x.x;
+          ev[2 * u + 1] = x.y;
+        }
+#pragma unroll
+        for (int q = 0; q < JR / 2; ++q) {
+          const double2 x = kp[q];
+          kv[2 * q] = x.x;
+          kv[2 * q + 1] = x.y;
+        }
+#pragma unroll
+        for (int q = 0; q < JR; ++q) {
+#pragma unroll
+          for (int u = 0; u < 8; ++u) acc[q][u] = fma(kv[q], ev[u], acc[q][u]);
+        }
       }
       __syncthreads();
     }
-    if (c < d) {
-      const double s = TH[c];
-      const double inv = (s > cut) ? 1.0 / s : 0.0;
 #pragma unroll
-      for (int q = 0; q < JPT; ++q) {
-        const int j = g + NG * q;
-        if (j < NPMAX) HG[j * DMAX + c] = (j < NC) ? acc[q] * inv : 0.0;
+    for (int u = 0; u < 8; ++u) {
+      const int c = 8 * cb + u;
+      if (c < d) {
+        const double sc = TH[c];
+        const double inv = (sc > cut) ? 1.0 / sc : 0.0;
+#pragma unroll
+        for (int q = 0; q < JR; ++q) {
+          const int j = JR * jb + q;
+          HG[j * DMAX + c] = (j < NC) ? acc[q][u] * inv : 0.0;
+        }
       }
     }
   }
