@@ -84,7 +84,10 @@ typedef struct {
                             core, Grams, projections, re-orthogonalisation and
                             the eps test stay FP64; Z_b and the PPR residual R
                             stay FP32 (Z_b sums many small pushes).          */
-  int32_t reserved1;
+  int32_t kernel_timing; /* 1: time every Step 2 core-SVD kernel launch with a
+                            pair of HIP events (up to 256 chunks per batch) and
+                            report the sum in damf_batch_info.ms_core_kernel;
+                            0 (default): no per-launch events              */
 } damf_config;
 
 /* Per-batch statistics written by damf_update when `info` is non-NULL. */
@@ -110,6 +113,11 @@ typedef struct {
                                completion, 4 rotations/row corrections,
                                5 P <- P F, 6 LU solve + scatter, 7 Grams   */
   double ms_reorth;       /* re-orthogonalisation run by this batch (0: none)  */
+  double ms_core_kernel;  /* Step 2 core-SVD kernel launches, summed (HIP events
+                             around each launch; needs kernel_timing = 1)     */
+  int64_t core_launches;  /* launches timed into ms_core_kernel                */
+  double core_flops;      /* counted FP64 flops of all core-SVD launches: Jacobi
+                             sweeps x 4N^2(N-1) + 2N^2 d (H) + 2N^2 k (K)      */
 } damf_batch_info;
 
 /* Statistics of the initialisation (damf_init / damf_init_factors). */

@@ -46,7 +46,7 @@ class DamfConfig(C.Structure):
         ("graph_slack", C.c_double),
         ("hip_stream", C.c_void_p),
         ("precision", C.c_int32),
-        ("reserved1", C.c_int32),
+        ("kernel_timing", C.c_int32),
     ]
 
 
@@ -70,6 +70,9 @@ class DamfBatchInfo(C.Structure):
         ("sweeps", C.c_int64),
         ("chain_phase_ms", C.c_double * 8),
         ("ms_reorth", C.c_double),
+        ("ms_core_kernel", C.c_double),
+        ("core_launches", C.c_int64),
+        ("core_flops", C.c_double),
     ]
 
     def as_dict(self):

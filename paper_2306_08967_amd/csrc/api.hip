@@ -61,6 +61,7 @@ damf_status check_config(const damf_config *cfg) {
   if (!(cfg->graph_slack >= 1.0)) return DAMF_E_INVALID_ARG;
   if (cfg->reorth_every < 0) return DAMF_E_INVALID_ARG;
   if (cfg->precision != 0 && cfg->precision != 1) return DAMF_E_INVALID_ARG;
+  if (cfg->kernel_timing != 0 && cfg->kernel_timing != 1) return DAMF_E_INVALID_ARG;
   return DAMF_OK;
 }
 
@@ -119,6 +120,8 @@ damf_status alloc_state(damf_ctx *c) {
   for (auto &e : c->ev) API_HIP(c, hipEventCreate(&e), "event");
   API_HIP(c, hipEventCreate(&c->ev_k[0]), "event");
   API_HIP(c, hipEventCreate(&c->ev_k[1]), "event");
+  if (c->cfg.kernel_timing)
+    for (auto &e : c->ev_core) API_HIP(c, hipEventCreate(&e), "event");
   return DAMF_OK;
 }
 
@@ -147,6 +150,8 @@ void free_ctx(damf_ctx *c) {
   for (auto &e : c->ev)
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->ev_k)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &e : c->ev_core)
     if (e) (void)hipEventDestroy(e);
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
@@ -339,6 +344,11 @@ void step_info(damf_ctx *c, const BatchHeader &h, int64_t k, damf_batch_info *in
   info->ms_prepare = ms_between(c->ev[0], c->ev[1]);
   info->ms_chain_kernel = ch ? ms_between(c->ev[4], c->ev[5]) : 0.0;
   info->chain_flops = ch ? w.cstats_host->flops : 0.0;
+  info->core_flops = ch ? w.cstats_host->core_flops : 0.0;
+  info->ms_core_kernel = 0.0;
+  info->core_launches = ch ? c->core_timed : 0;
+  for (int i = 0; ch && i < c->core_timed; ++i)
+    info->ms_core_kernel += ms_between(c->ev_core[2 * i], c->ev_core[2 * i + 1]);
   info->sweeps = ch ? w.cstats_host->sweeps : 0;
   for (int i = 0; i < 8; ++i)
     info->chain_phase_ms[i] = ch ? (double)w.cstats_host->phase_ticks[i] / c->wall_khz : 0.0;

@@ -88,34 +88,78 @@ constexpr int NG = NT / 128;  // groups of 128 threads (one column each)
 // ---------------------------------------------------------------- Step 1
 
 // MP[i][c] = sum_q Mb[rows[i]][q] * Pm[q][c]  (rows of U or V in the current basis)
-__device__ __noinline__ void gather_project(const float *Mb, const int32_t *rows, int s, const double *Pm,
-                               int d, double *lds, double *MP, bool split) {
-  for (int e = tid(); e < s * d; e += NT) {
-    int i = e / d, q = e - i * d;
-    lds[i * d + q] = (double)basis_ld(Mb, (int64_t)rows[i] * d + q, split);
+// C = A B for one 512-thread workgroup, FP64, M <= 32 MR, N <= 128, any K:
+// K is staged through LDS KC values at a time (A as [k][i], B as [k][c]);
+// thread (rb, cb) accumulates rows MR rb .. + MR and columns 8 cb .. + 8 in
+// registers, reading both operands as 16-byte pairs.  aload(i, k), bload(k,
+// c) fetch the operands; cstore(i, c, v) writes the result.  Uses
+// KC (32 MR + 130) doubles of LDS; starts and ends with the caller's LDS free.
+template <int MR, class AL, class BL, class CS>
+__device__ __forceinline__ void wg_gemm(int M, int N, int K, AL aload, BL bload, CS cstore,
+                                        double *lds) {
+  constexpr int KC = 32, MT = 32 * MR, AS = MT + 2, BS = 128 + 2;
+  static_assert(MR % 2 == 0 && NT == 512 && KC * (AS + BS) <= LDS_DOUBLES, "wg_gemm shape");
+  double *At = lds, *Bt = lds + KC * AS;
+  const int cb = tid() & 15, rb = tid() >> 4;
+  double acc[MR][8];
+#pragma unroll
+  for (int q = 0; q < MR; ++q) {
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc[q][u] = 0.0;
   }
-  __syncthreads();
-  const int c = tid() & 127, g = tid() >> 7;
-  if (c < d) {
-    double acc[KMAX / NG];
+  for (int k0 = 0; k0 < K; k0 += KC) {
+    const int kn = min(KC, K - k0);
+    __syncthreads();
+    for (int e = tid(); e < KC * MT; e += NT) {
+      const int kk = e % KC, i = e / KC;
+      At[kk * AS + i] = (kk < kn && i < M) ? aload(i, k0 + kk) : 0.0;
+    }
+    for (int e = tid(); e < KC * 128; e += NT) {
+      const int c = e & 127, kk = e >> 7;
+      Bt[kk * BS + c] = (kk < kn && c < N) ? bload(k0 + kk, c) : 0.0;
+    }
+    __syncthreads();
+    for (int kk = 0; kk < kn; ++kk) {
+      double av[MR], bv[8];
+      const double2 *ap = reinterpret_cast<const double2 *>(At + kk * AS + MR * rb);
+      const double2 *bp = reinterpret_cast<const double2 *>(Bt + kk * BS + 8 * cb);
 #pragma unroll
-    for (int j = 0; j < KMAX / NG; ++j) acc[j] = 0.0;
-#pragma unroll 8
-    for (int q = 0; q < d; ++q) {
-      const double pv = Pm[q * d + c];
+      for (int q = 0; q < MR / 2; ++q) {
+        const double2 x = ap[q];
+        av[2 * q] = x.x;
+        av[2 * q + 1] = x.y;
+      }
 #pragma unroll
-      for (int j = 0; j < KMAX / NG; ++j) {
-        int i = g + NG * j;
-        if (i < s) acc[j] = fma(lds[i * d + q], pv, acc[j]);
+      for (int u = 0; u < 4; ++u) {
+        const double2 x = bp[u];
+        bv[2 * u] = x.x;
+        bv[2 * u + 1] = x.y;
+      }
+#pragma unroll
+      for (int q = 0; q < MR; ++q) {
+#pragma unroll
+        for (int u = 0; u < 8; ++u) acc[q][u] = fma(av[q], bv[u], acc[q][u]);
       }
     }
+  }
 #pragma unroll
-    for (int j = 0; j < KMAX / NG; ++j) {
-      int i = g + NG * j;
-      if (i < s) MP[i * d + c] = acc[j];
+  for (int q = 0; q < MR; ++q) {
+    const int i = MR * rb + q;
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int c = 8 * cb + u;
+      if (i < M && c < N) cstore(i, c, acc[q][u]);
     }
   }
   __syncthreads();
+}
+
+__device__ __noinline__ void gather_project(const float *Mb, const int32_t *rows, int s, const double *Pm,
+                               int d, double *lds, double *MP, bool split) {
+  wg_gemm<2>(
+      s, d, d, [&](int i, int q) { return (double)basis_ld(Mb, (int64_t)rows[i] * d + q, split); },
+      [&](int q, int c) { return Pm[q * d + c]; }, [&](int i, int c, double v) { MP[i * d + c] = v; },
+      lds);
 }
 
 // Dense D (s1 x s2) into LDS from the chunk entries.
@@ -210,85 +254,125 @@ __device__ __noinline__ void build_gram(const ChunkState &cs, int side, int d, c
   __syncthreads();
 }
 
-// Pivoted Cholesky of the k x k PSD matrix G (LDS, row stride KMAX,
-// overwritten): stops when the largest remaining diagonal <= thr.  On return
-// G[i][j] for j < rho, i >= j holds L in pivoted order and perm[] the pivot
-// order.  Wave 0 picks the pivot, swaps and scales; all threads then update
-// the trailing block (two barriers per step).  Returns rho.
-__device__ __noinline__ int pivoted_cholesky(double *G, int k, double thr, int *perm) {
-  __shared__ int s_rho;
-  const int lane = tid() & 63;
-  if (tid() < KMAX) perm[tid()] = tid();
-  if (tid() == 0) s_rho = k;
-  __syncthreads();
-  for (int j = 0; j < k; ++j) {
-    if (tid() < 64) {
-      double v = (lane >= j && lane < k) ? G[lane * KMAX + lane] : -1.0;
-      int idx = lane;
-#pragma unroll
-      for (int off = 32; off >= 1; off >>= 1) {
-        const double ov = __shfl_xor(v, off, 64);
-        const int oi = __shfl_xor(idx, off, 64);
-        if (ov > v || (ov == v && oi < idx)) {
-          v = ov;
-          idx = oi;
-        }
-      }
-      if (!(v > thr)) {
-        if (lane == 0) s_rho = j;
-      } else {
-        const int p = idx;
-        if (p != j) {
-          // symmetric swap of rows and columns j, p (lane c handles column c)
-          if (lane < k) {
-            const double a = G[j * KMAX + lane], b = G[p * KMAX + lane];
-            G[j * KMAX + lane] = b;
-            G[p * KMAX + lane] = a;
-          }
-          __builtin_amdgcn_wave_barrier();
-          if (lane < k) {
-            const double a = G[lane * KMAX + j], b = G[lane * KMAX + p];
-            G[lane * KMAX + j] = b;
-            G[lane * KMAX + p] = a;
-          }
-          if (lane == 0) {
-            const int t = perm[j];
-            perm[j] = perm[p];
-            perm[p] = t;
-          }
-          __builtin_amdgcn_wave_barrier();
-        }
-        const double ljj = sqrt(G[j * KMAX + j]);
-        __builtin_amdgcn_wave_barrier();
-        if (lane > j && lane < k) G[lane * KMAX + j] /= ljj;
-        if (lane == j) G[j * KMAX + j] = ljj;
-      }
-    }
-    __syncthreads();
-    if (s_rho == j) break;  // uniform: s_rho was set before the barrier
-    // trailing update of the lower triangle, mirrored to the upper one
-    for (int e = tid(); e < KMAX * KMAX; e += NT) {
-      const int i = e >> 6, l = e & 63;
-      if (i > j && l > j && l <= i && i < k) {
-        const double v = G[i * KMAX + l] - G[i * KMAX + j] * G[l * KMAX + j];
-        G[i * KMAX + l] = v;
-        G[l * KMAX + i] = v;
-      }
-    }
-    __syncthreads();
+// (value, index) of the larger value, ties to the lower index: a total
+// order, so a butterfly leaves every lane with the same winner.
+__device__ __forceinline__ void argmax_take(double &v, int &i, double ov, int oi) {
+  const bool take = (ov > v) || (ov == v && oi < i);
+  v = take ? ov : v;
+  i = take ? oi : i;
+}
+template <int CTRL>
+__device__ __forceinline__ void argmax_dpp(double &v, int &i) {
+  argmax_take(v, i, dpp_d<CTRL>(v), __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false));
+}
+__device__ __forceinline__ void argmax_wave(double &v, int &i) {
+  argmax_dpp<0xB1>(v, i);   // quad_perm [1,0,3,2]
+  argmax_dpp<0x4E>(v, i);   // quad_perm [2,3,0,1]
+  argmax_dpp<0x141>(v, i);  // row_half_mirror
+  argmax_dpp<0x140>(v, i);  // row_mirror
+  {
+    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
+    const auto ii = __builtin_amdgcn_permlane16_swap(i, i, false, false);
+    double va = __hiloint2double(hi[0], lo[0]), vb = __hiloint2double(hi[1], lo[1]);
+    int ia = ii[0], ib = ii[1];
+    argmax_take(va, ia, vb, ib);
+    v = va;
+    i = ia;
   }
+  {
+    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
+    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
+    const auto ii = __builtin_amdgcn_permlane32_swap(i, i, false, false);
+    double va = __hiloint2double(hi[0], lo[0]), vb = __hiloint2double(hi[1], lo[1]);
+    int ia = ii[0], ib = ii[1];
+    argmax_take(va, ia, vb, ib);
+    v = va;
+    i = ia;
+  }
+}
+__device__ __forceinline__ double readlane_f64(double x, int l) {
+  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
+                          __builtin_amdgcn_readlane(__double2loint(x), l));
+}
+
+// Pivoted Cholesky of the k x k PSD matrix G (LDS, row stride KMAX), by wave
+// 0 with row i of G in the VGPRs of lane i: each step picks the largest
+// remaining diagonal (wave argmax), stops when it is <= thr, else passes the
+// pivot row through LDS (rb, KMAX doubles) and applies the rank-1 update lane
+// by lane.  Rows are never moved: on return G[i][j] (j < rho) holds L in the
+// original row order (row i's entry for the j-th pivot; 0 for steps after row
+// i was itself the pivot), perm[j] the j-th pivot for j < rho and the other
+// rows in increasing order after it.  Returns rho.
+__device__ __noinline__ int pivoted_cholesky(double *G, int k, double thr, int *perm, double *rb) {
+  __shared__ int s_rho;
+  if (tid() < 64) {
+    const int i = tid();
+    const bool row = i < k;
+    double g[KMAX];
+#pragma unroll
+    for (int l = 0; l < KMAX; ++l) g[l] = (row && l < k) ? G[i * KMAX + l] : 0.0;
+    double dg = row ? G[i * KMAX + i] : 0.0;
+    uint64_t done = 0;  // rows already used as pivots (wave-uniform)
+    bool mine_done = false;
+    int rho = k;
+    for (int j = 0; j < k; ++j) {
+      double v = (row && !mine_done) ? dg : -1.0;
+      int p = i;
+      argmax_wave(v, p);
+      p = __builtin_amdgcn_readfirstlane(p);
+      if (!(v > thr)) {
+        rho = j;
+        break;
+      }
+      const double ljj = sqrt(v), inv = 1.0 / ljj;
+      if (i == p) {
+        double2 *w = reinterpret_cast<double2 *>(rb);
+#pragma unroll
+        for (int l = 0; l < KMAX / 2; ++l) w[l] = make_double2(g[2 * l], g[2 * l + 1]);
+      }
+      __builtin_amdgcn_wave_barrier();
+      // column j of L for every row: 0 for earlier pivots, ljj for p
+      const double li = (!row || mine_done) ? 0.0 : ((i == p) ? ljj : rb[i] * inv);
+      G[i * KMAX + j] = li;  // lane i only touches row i, already in VGPRs
+      if (i == 0) perm[j] = p;
+      done |= 1ull << p;
+      mine_done = mine_done || (i == p);
+      // g[l] -= L[i][j] L[l][j]; entries of pivoted columns l become
+      // meaningless but are never read for a row still in play
+      const double2 *r2 = reinterpret_cast<const double2 *>(rb);
+      const double lis = li * inv;
+#pragma unroll
+      for (int l2 = 0; l2 < KMAX / 2; ++l2) {
+        const double2 x = r2[l2];
+        g[2 * l2] = fma(-lis, x.x, g[2 * l2]);
+        g[2 * l2 + 1] = fma(-lis, x.y, g[2 * l2 + 1]);
+      }
+      dg = fma(-li, li, dg);
+      __builtin_amdgcn_wave_barrier();
+    }
+    // the remaining rows after the pivots, in increasing order
+    if (row && !((done >> i) & 1)) {
+      const uint64_t below = (i == 0) ? 0ull : (~done & ((1ull << i) - 1));
+      perm[rho + __builtin_popcountll(below)] = i;
+    }
+    if (i == 0) s_rho = rho;
+  }
+  __syncthreads();
   const int rho = s_rho;
   __syncthreads();
   return rho;
 }
 
-// R (rho x k): R[i][perm[j]] = L[j][i] (j >= i), i.e. R = L^T Pi^T.
+// L (k x k, pivoted order) and R (rho x k): with Lo = G in original row
+// order, L[a][b] = Lo[perm[a]][b] (b < rho) and R[i][perm[j]] = L[j][i] (j >= i),
+// i.e. R = L^T Pi^T.
 __device__ __noinline__ void store_factor(const double *G, int k, int rho, const int *perm, double *Lg,
                              double *Rg) {
   for (int e = tid(); e < KMAX * KMAX; e += NT) {
     const int i = e >> 6, j = e & 63;
-    if (i < k && j < k) Lg[i * k + j] = G[i * KMAX + j];
-    if (i < rho && j < k) Rg[i * k + perm[j]] = (j >= i) ? G[j * KMAX + i] : 0.0;
+    if (i < k && j < k) Lg[i * k + j] = (j < rho) ? G[perm[i] * KMAX + j] : 0.0;
+    if (i < rho && j < k) Rg[i * k + perm[j]] = (j >= i) ? G[perm[j] * KMAX + i] : 0.0;
   }
 }
 
@@ -636,77 +720,11 @@ __device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, i
   __syncthreads();
 }
 
-// Pn = Po F (d x d): Po staged in LDS (rows read as wave-wide broadcasts),
-// F streamed from L2 (one column per thread, coalesced).
+// Pn = Po F (d x d).
 __device__ __noinline__ void mul_PF(int d, const double *Po, const double *F, double *Pn, double *lds) {
-  for (int e = tid(); e < d * d; e += NT) lds[e] = Po[e];
-  __syncthreads();
-  const int c = tid() & 127;
-  const int g = __builtin_amdgcn_readfirstlane(tid() >> 7);
-  if (c < d) {
-    const int rows_per = (d + NG - 1) / NG;
-    for (int i0 = 0; i0 < rows_per; i0 += 16) {
-      double acc[16];
-#pragma unroll
-      for (int q = 0; q < 16; ++q) acc[q] = 0.0;
-      for (int kk = 0; kk < d; ++kk) {
-        const double f = F[kk * d + c];
-#pragma unroll
-        for (int q = 0; q < 16; ++q) {
-          const int i = g * rows_per + i0 + q;
-          if (i0 + q < rows_per && i < d) acc[q] = fma(lds[i * d + kk], f, acc[q]);
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < 16; ++q) {
-        const int i = g * rows_per + i0 + q;
-        if (i0 + q < rows_per && i < d) Pn[i * d + c] = acc[q];
-      }
-    }
-  }
-  __syncthreads();
-}
-
-// (value, index) of the larger |entry|, ties to the lower index: a total
-// order, so a butterfly leaves every lane with the same winner.
-__device__ __forceinline__ void argmax_take(double &v, int &i, double ov, int oi) {
-  const bool take = (ov > v) || (ov == v && oi < i);
-  v = take ? ov : v;
-  i = take ? oi : i;
-}
-template <int CTRL>
-__device__ __forceinline__ void argmax_dpp(double &v, int &i) {
-  argmax_take(v, i, dpp_d<CTRL>(v), __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false));
-}
-__device__ __forceinline__ void argmax_wave(double &v, int &i) {
-  argmax_dpp<0xB1>(v, i);   // quad_perm [1,0,3,2]
-  argmax_dpp<0x4E>(v, i);   // quad_perm [2,3,0,1]
-  argmax_dpp<0x141>(v, i);  // row_half_mirror
-  argmax_dpp<0x140>(v, i);  // row_mirror
-  {
-    const auto lo = __builtin_amdgcn_permlane16_swap(__double2loint(v), __double2loint(v), false, false);
-    const auto hi = __builtin_amdgcn_permlane16_swap(__double2hiint(v), __double2hiint(v), false, false);
-    const auto ii = __builtin_amdgcn_permlane16_swap(i, i, false, false);
-    double va = __hiloint2double(hi[0], lo[0]), vb = __hiloint2double(hi[1], lo[1]);
-    int ia = ii[0], ib = ii[1];
-    argmax_take(va, ia, vb, ib);
-    v = va;
-    i = ia;
-  }
-  {
-    const auto lo = __builtin_amdgcn_permlane32_swap(__double2loint(v), __double2loint(v), false, false);
-    const auto hi = __builtin_amdgcn_permlane32_swap(__double2hiint(v), __double2hiint(v), false, false);
-    const auto ii = __builtin_amdgcn_permlane32_swap(i, i, false, false);
-    double va = __hiloint2double(hi[0], lo[0]), vb = __hiloint2double(hi[1], lo[1]);
-    int ia = ii[0], ib = ii[1];
-    argmax_take(va, ia, vb, ib);
-    v = va;
-    i = ia;
-  }
-}
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
-                          __builtin_amdgcn_readlane(__double2loint(x), l));
+  wg_gemm<4>(
+      d, d, d, [&](int i, int q) { return Po[i * d + q]; }, [&](int q, int c) { return F[q * d + c]; },
+      [&](int i, int c, double v) { Pn[i * d + c] = v; }, lds);
 }
 
 // Partial-pivoting LU of the panel A[j0.., j0 .. j0 + jb) (jb <= 16), by one
@@ -1018,7 +1036,7 @@ __global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, 
   for (int e = tid(); e < k * d; e += NT) scr[(side ? OFF_WC : OFF_WB) + e] = Wt[e];
   build_gram(cs, side, d, D, Wt, G, &bmax);
   int *perm = ilds;
-  const int rho = pivoted_cholesky(G, k, p.tau * bmax, perm);
+  const int rho = pivoted_cholesky(G, k, p.tau * bmax, perm, lds);
   store_factor(G, k, rho, perm, scr + (side ? OFF_LC : OFF_LB), scr + (side ? OFF_RC : OFF_RB));
   for (int i = tid(); i < k; i += NT) meta[2 + side * KMAX + i] = perm[i];
   if (tid() == 0) {
@@ -1059,6 +1077,8 @@ __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
     // counted FP64 work of this chunk: Jacobi (dot + rotation = 8N flops per
     // pair, N(N-1)/2 pairs per sweep), H = K^T E, F, P F, LU and solves
     const double Nn = (double)N, dd = (double)d, kk = (double)k;
+    atomicAdd(&p.stats->core_flops, sw * 4.0 * Nn * Nn * (Nn - 1.0) + 2.0 * Nn * Nn * dd +
+                                        2.0 * Nn * Nn * kk);
     double flops = sw * 4.0 * Nn * Nn * (Nn - 1.0) + 2.0 * Nn * Nn * dd;
     flops += 2.0 * (2.0 * dd * dd * kk + 2.0 * dd * dd * dd + (2.0 / 3.0) * dd * dd * dd +
                     2.0 * 2.0 * (double)max(cs.s1, cs.s2) * dd * dd);
@@ -1121,9 +1141,18 @@ hipError_t launch_chain(damf_ctx *c, int n_chunks) {
   DAMF_HIP(hipMemsetAsync(c->ws.cstats, 0, sizeof(ChainStats), s));
   // the projections alternate between P and Pnext from chunk to chunk
   double *Pc = c->P, *Pn = c->Pnext;
+  // with kernel timing, a pair of events brackets each core launch
+  const bool timed = c->cfg.kernel_timing != 0;
+  c->core_timed = 0;
   for (int ch = 0; ch < n_chunks; ++ch) {
     chain_front_kernel<<<2, NT, 0, s>>>(p, ch, Pc);
+    const bool tm = timed && ch < damf_ctx::kCoreTimed;
+    if (tm) DAMF_HIP(hipEventRecord(c->ev_core[2 * ch], s));
     chain_core_kernel<<<1, NT, 0, s>>>(p, ch);
+    if (tm) {
+      DAMF_HIP(hipEventRecord(c->ev_core[2 * ch + 1], s));
+      c->core_timed = ch + 1;
+    }
     chain_back_kernel<<<2, NT, 0, s>>>(p, ch, Pc, Pn);
     double *t = Pc;
     Pc = Pn;

@@ -70,6 +70,7 @@ struct ChainStats {
   int32_t numeric_error;
   double flops;  // FP64 flops executed (counted per phase)
   uint64_t phase_ticks[8];  // wall-clock ticks per phase (see chain.hip)
+  double core_flops;        // the core-SVD kernel's share of flops
 };
 
 struct Workspace {
@@ -140,6 +141,9 @@ struct damf_ctx {
   bool ppr_on = true;
   hipEvent_t ev[8] = {};
   hipEvent_t ev_k[2] = {};  // per-kernel timing inside multi-launch stages
+  static constexpr int kCoreTimed = 256;  // core-SVD launches timed per batch
+  hipEvent_t ev_core[2 * kCoreTimed] = {};  // created only with cfg.kernel_timing
+  int core_timed = 0;                       // launches timed by the last chain
   damf_init_info init_info{};
   double push_ms = 0.0, push_bytes = 0.0;  // accumulated by ppr_push
   double wall_khz = 100000.0;               // device wall-clock rate (kHz)
