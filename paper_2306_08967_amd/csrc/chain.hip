@@ -33,6 +33,11 @@ constexpr int NPMAX = 192;   // max padded core size
 constexpr int DMAX = 128;
 constexpr int KMAX = 64;
 constexpr int LDS_DOUBLES = 19200;  // 150 KB
+// Core-SVD Jacobi tolerance: a pair is rotated while |a_i . a_j| exceeds it
+// relative to ||a_i|| ||a_j||, and sweeps stop once every rotation of a sweep
+// was below its square root, leaving the columns orthogonal to about 1e-9 --
+// well under the rounding of the FP32 bases the result is stored into (6e-8).
+constexpr double kJacobiTol = 1e-9;
 
 // global scratch layout (doubles)
 constexpr size_t OFF_KG = 0;                              // K, col-major, stride NPMAX
@@ -447,7 +452,7 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
   __syncthreads();
   int *flag = ilds;
   uint64_t tj0 = wall_clock64();
-  const int sweeps = jw_sweeps<S>(J, lds, flag, 40, 1e-12);
+  const int sweeps = jw_sweeps<S>(J, lds, flag, 40, kJacobiTol);
   if (tid() == 0) ticks[1] += wall_clock64() - tj0;
   *sweeps_out = sweeps;
   // ---- singular values, descending order
