@@ -32,6 +32,34 @@ N_CU = 256
 FP64_CU_PEAK_TFLOPS = FP64_PEAK_TFLOPS / N_CU  # one compute unit (single-workgroup kernel)
 
 
+# Sources of the core-SVD kernel: the PMC byte counts recorded in profiles/ hold
+# for the kernel built from exactly these files.
+CORE_SOURCES = ["paper_2306_08967_amd/csrc/chain.hip", "paper_2306_08967_amd/csrc/jacobi_wave.h",
+                "paper_2306_08967_amd/csrc/jacobi16.h", "paper_2306_08967_amd/csrc/common.h",
+                "paper_2306_08967_amd/csrc/damf_internal.h"]
+CORE_PMC = "profiles/pmc_chain_core_kernel_c2.md"
+
+
+def core_traffic():
+    """HBM bytes per core-kernel launch from the committed PMC summary, or None
+    when the kernel's sources have changed since the counters were taken."""
+    import hashlib
+    import re
+    try:
+        text = open(os.path.join(ROOT, CORE_PMC)).read()
+        h = hashlib.sha256()
+        for f in CORE_SOURCES:
+            with open(os.path.join(ROOT, f), "rb") as fh:
+                h.update(fh.read())
+    except OSError:
+        return None
+    m_t = re.search(r"^traffic_bytes_per_launch: (\d+)", text, re.M)
+    m_h = re.search(r"^source_sha256: ([0-9a-f]+)", text, re.M)
+    if not (m_t and m_h) or m_h.group(1) != h.hexdigest():
+        return None
+    return float(m_t.group(1))
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -58,6 +86,9 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=6000)
     ap.add_argument("--serve-sat", type=int, default=400)
     ap.add_argument("--serve-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (the reference kernel "
+                         "that scales HBM byte counters) and print its size")
     return ap.parse_args()
 
 
@@ -293,8 +324,25 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
+def copy_calibration(mib):
+    """A plain device-to-device copy of known size, for scaling PMC byte counters."""
+    import torch
+    nbytes = mib << 20
+    x = torch.ones(nbytes // 4, dtype=torch.float32, device="cuda")
+    y = torch.empty_like(x)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration": {"bytes_read": nbytes, "bytes_written": nbytes,
+                                           "launches": 3}}))
+
+
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     if args.mode == "serve":
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
@@ -390,7 +438,8 @@ def main():
     dom = "chain_core_kernel" if core_ms >= push_ms else "ppr_push"
     dk = kernels[dom]
     roofline = {"kernel": dom, "bound": dk["bound"], "achieved": dk["achieved"], "peak": dk["peak"],
-                "unit": dk["unit"], "frac": dk["frac"], "traffic": None}
+                "unit": dk["unit"], "frac": dk["frac"],
+                "traffic": core_traffic() if dom == "chain_core_kernel" else None}
 
     accuracy = None
     if args.precision == 1:
