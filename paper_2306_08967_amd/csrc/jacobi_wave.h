@@ -25,9 +25,11 @@
 //
 // Rotations are applied in scaled form: column i is held as x_i with a scale
 // d_i (a_i = d_i x_i, scales in LDS by id).  The rotation (c, s = c t) of the
-// pair becomes x_i <- x_i - t (d_j / d_i) x_j, x_j <- x_j + t (d_i / d_j) x_i,
-// d <- c d: two FMAs per row instead of four.  Scales only shrink (c >= 1/sqrt 2)
-// and are folded back into the columns after every sweep.
+// pair (a_i' = c a_i - s a_j, a_j' = s a_i + c a_j) becomes two in-place shears,
+// x_j <- x_j + t (d_i / d_j) x_i, then x_i <- x_i - c^2 t (d_j / d_i) x_j with the
+// new x_j, and d_j <- c d_j, d_i <- d_i / c: two FMAs per row and no copies.  A
+// scale changes by at most sqrt 2 per rotation (|t| <= 1) and the scales are
+// folded back into the columns after every sweep.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -37,20 +39,25 @@
 
 namespace damf {
 
-template <int NP_>
+template <int NP_, int NW_ = 8>
 struct JW {
   static constexpr int NP = NP_;
-  static constexpr int NW = 8;             // waves
-  static constexpr int B = NP / 16;        // columns per half-block
+  static constexpr int NW = NW_;           // waves
+  static constexpr int B = NP / (2 * NW);  // columns per half-block
   static constexpr int C = 2 * B;          // columns per wave
   static constexpr int RPL = NP / 64;      // rows per lane
-  static constexpr int Q = B / 4;          // reduced dot products per 16-lane row
+  // reduction of B values: the first lane-swap stage leaves H per lane, the
+  // second QF full slots (one pair per 16-lane row each) and, for odd H, one
+  // leftover slot (rows 0 and 2)
+  static constexpr int H = B / 2;
+  static constexpr int QF = H / 2, QL = H % 2, QS = QF + QL;
   static constexpr int SLOT = B * NP;      // doubles per half-block in the exchange buffer
   static constexpr int NRM_OFF = NW * SLOT;
   static constexpr int SCL_OFF = NRM_OFF + NP;
   static constexpr int BC_OFF = SCL_OFF + NP;  // per wave: B rotation factor pairs
   static constexpr int LDS = BC_OFF + NW * 2 * B;  // exchange, norms, scales, factors
-  static_assert(NP % 64 == 0 && NP <= 192 && B % 4 == 0, "NP must be 64, 128 or 192");
+  static_assert(NP % 64 == 0 && NP <= 192 && B % 2 == 0 && B * 2 * NW == NP,
+                "NP must be 64, 128 or 192 and split into 2 NW half-blocks of even width");
 };
 
 template <class S>
@@ -91,29 +98,36 @@ __device__ __forceinline__ double wave_max_d(double x) {
   return x;
 }
 
-// Index of the pair whose wave total 16-lane row `row` holds in reduced slot q.
+// Index of the pair whose wave total 16-lane row `row` holds in reduced slot
+// q, and whether lane sl of that row computes it (slot sl).
 template <class S>
 __device__ __forceinline__ int jw_pair(int row, int q) {
-  return q + (row & 1) * S::Q + (row >> 1) * (S::B / 2);
+  return (q < S::QF) ? q + (row & 1) * S::QF + (row >> 1) * S::H : (S::H - 1) + (row >> 1) * S::H;
+}
+template <class S>
+__device__ __forceinline__ bool jw_plane(int row, int sl) {
+  return sl < S::QF || (S::QL && sl == S::QF && (row & 1) == 0);
 }
 
-// v[p] (p < B): per-lane partial sums.  On return out[q] (q < Q), in every lane
-// of 16-lane row R, is the wave total of v[jw_pair(R, q)].
+// v[p] (p < B): per-lane partial sums.  On return out[q] (q < QS), in every
+// lane of 16-lane row R, is the wave total of v[jw_pair(R, q)].
 template <class S>
-__device__ __forceinline__ void jw_reduce(const double (&v)[S::B], double (&out)[S::Q]) {
-  constexpr int B = S::B, Q = S::Q;
-  double h[B / 2];
+__device__ __forceinline__ void jw_reduce(const double (&v)[S::B], double (&out)[S::QS]) {
+  constexpr int B = S::B, H = S::H, QF = S::QF;
+  double h[H];
 #pragma unroll
-  for (int p = 0; p < B / 2; ++p) h[p] = xsum32(v[p], v[p + B / 2]);
+  for (int p = 0; p < H; ++p) h[p] = xsum32(v[p], v[p + H]);
 #pragma unroll
-  for (int q = 0; q < Q; ++q) out[q] = row_sum16(xsum16(h[q], h[q + Q]));
+  for (int q = 0; q < QF; ++q) out[q] = row_sum16(xsum16(h[q], h[q + QF]));
+  if (S::QL) out[S::QS - 1] = row_sum16(xsum16(h[H - 1], h[H - 1]));
+  (void)B;
 }
 
 // Exact squared norms of the wave's 2B columns into nrm[] by column id (the
 // wave holds its sweep-boundary half-blocks w and NW + w).
 template <class S>
 __device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double *nrm, int w) {
-  constexpr int B = S::B, Q = S::Q, RPL = S::RPL;
+  constexpr int B = S::B, Q = S::QS, RPL = S::RPL;
   const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
@@ -129,17 +143,17 @@ __device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double *nrm, int w)
     double mine = out[0];
 #pragma unroll
     for (int q = 1; q < Q; ++q) mine = (sl == q) ? out[q] : mine;
-    if (sl < Q) nrm[jw_col<S>(w, half * B + jw_pair<S>(row, sl))] = mine;
+    if (jw_plane<S>(row, sl)) nrm[jw_col<S>(w, half * B + jw_pair<S>(row, sl))] = mine;
   }
 }
 
 // Pair maps: pair p of a step rotates slots PM::a(p) and PM::b(p).
-// Cross: top slot p with bottom slot p.  Intra: the pairs of a circle inside
+// Cross: top slot p with bottom slot (p + SH) mod B.  Intra: the pairs of a circle inside
 // each half-block (top half-block pairs first, then the bottom one).
-template <class S>
+template <class S, int SH = 0>
 struct JWCross {
   static constexpr int a(int p) { return p; }
-  static constexpr int b(int p) { return S::B + p; }
+  static constexpr int b(int p) { return S::B + (p + SH) % S::B; }
 };
 template <class S>
 struct JWIntra {
@@ -157,7 +171,7 @@ template <class S, class PM, class IdF>
 __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, double2 *bc,
                                         double floor2, double tol2, double conv2, IdF ids, int &rot,
                                         int &big) {
-  constexpr int B = S::B, Q = S::Q, RPL = S::RPL;
+  constexpr int B = S::B, Q = S::QS, RPL = S::RPL;
   const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
   double v[B], g[Q];
 #pragma unroll
@@ -172,7 +186,7 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, 
   double myg = g[0];
 #pragma unroll
   for (int q = 1; q < Q; ++q) myg = (sl == q) ? g[q] : myg;
-  const bool plane = sl < Q;
+  const bool plane = jw_plane<S>(row, sl);
   const int pair = plane ? jw_pair<S>(row, sl) : 0;
   int it, ib;
   ids(pair, it, ib);
@@ -191,11 +205,13 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, 
   const double t = doit ? (dd >= 0.0 ? gg : -gg) * rcp_nr(den) : 0.0;
   const double cs = rsqrt_nr(fma(t, t, 1.0));
   const double inv = rcp_nr(di * dj);
-  const double t1 = t * (dj * dj) * inv, t2 = t * (di * di) * inv;
+  // two in-place shears: x_j += t (d_i / d_j) x_i, then x_i -= c^2 t (d_j / d_i) x_j
+  // (the new x_j), with d_j <- c d_j and d_i <- d_i / c
+  const double t2 = t * (di * di) * inv, t1 = (cs * cs) * t * (dj * dj) * inv;
   if (doit) {
     nrm[it] = fma(-t, gt, al);
     nrm[ib] = fma(t, gt, be);
-    scl[it] = cs * di;
+    scl[it] = di * rcp_nr(cs);
     scl[ib] = cs * dj;
   }
   rot += doit ? 1 : 0;
@@ -207,9 +223,8 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, 
     const double u1 = u.x, u2 = u.y;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
-      const double x = J.a[PM::a(p)][r], y = J.a[PM::b(p)][r];
-      J.a[PM::a(p)][r] = fma(-u1, y, x);
-      J.a[PM::b(p)][r] = fma(u2, x, y);
+      J.a[PM::b(p)][r] = fma(u2, J.a[PM::a(p)][r], J.a[PM::b(p)][r]);
+      J.a[PM::a(p)][r] = fma(-u1, J.a[PM::b(p)][r], J.a[PM::a(p)][r]);
     }
   }
 }
@@ -220,6 +235,7 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, 
 template <class S>
 __device__ __forceinline__ void jw_intra_move(JWRegs<S> &J) {
   constexpr int B = S::B, H = B / 2, RPL = S::RPL;
+  if (B == 2) return;  // a circle of two columns has one step and no move
 #pragma unroll
   for (int o = 0; o < 2 * B; o += B) {
     double b0[RPL], tl[RPL];
@@ -247,20 +263,26 @@ __device__ __forceinline__ void jw_intra_move(JWRegs<S> &J) {
   }
 }
 
-// turn the bottom half-block by one column: bottom p <- bottom p+1
+// turn the bottom half-block by two columns: bottom p <- bottom p+2 (mod B)
 template <class S>
-__device__ __forceinline__ void jw_cross_move(JWRegs<S> &J) {
+__device__ __forceinline__ void jw_cross_move2(JWRegs<S> &J) {
   constexpr int B = S::B, RPL = S::RPL;
-  double b0[RPL];
+  double b0[RPL], b1[RPL];
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) b0[r] = J.a[B][r];
-#pragma unroll
-  for (int p = 0; p < B - 1; ++p) {
-#pragma unroll
-    for (int r = 0; r < RPL; ++r) J.a[B + p][r] = J.a[B + p + 1][r];
+  for (int r = 0; r < RPL; ++r) {
+    b0[r] = J.a[B][r];
+    b1[r] = J.a[B + 1][r];
   }
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) J.a[2 * B - 1][r] = b0[r];
+  for (int p = 0; p < B - 2; ++p) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) J.a[B + p][r] = J.a[B + p + 2][r];
+  }
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) {
+    J.a[2 * B - 2][r] = b0[r];
+    J.a[2 * B - 1][r] = b1[r];
+  }
 }
 
 template <class S>
@@ -282,13 +304,14 @@ __device__ __forceinline__ void jw_get(JWRegs<S> &J, const double *xb, int slot,
 
 // Move the half-blocks to the next round of the circle over waves:
 // new top[w] = old top[w-1] (w >= 2), new top[1] = old bottom[0], top[0] stays;
-// new bottom[w] = old bottom[w+1] (w < 7), new bottom[7] = old top[7].
+// new bottom[w] = old bottom[w+1] (w < NW-1), new bottom[NW-1] = old top[NW-1].
 template <class S>
 __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int lane) {
   constexpr int B = S::B, RPL = S::RPL;
-  jw_put<S>(J, xb, (w == 0) ? 7 : w - 1, B, lane);  // bottoms, by destination wave
+  constexpr int L = S::NW - 1;
+  jw_put<S>(J, xb, (w == 0) ? L : w - 1, B, lane);  // bottoms, by destination wave
   __syncthreads();
-  if (w < 7) {
+  if (w < L) {
     jw_get<S>(J, xb, w, B, lane);
   } else {
 #pragma unroll
@@ -298,10 +321,10 @@ __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int
     }
   }
   __syncthreads();
-  if (w >= 1 && w <= 6) jw_put<S>(J, xb, w, 0, lane);  // tops of waves 1..6, by source wave
+  if (w >= 1 && w < L) jw_put<S>(J, xb, w, 0, lane);  // tops of waves 1..NW-2, by source wave
   __syncthreads();
   if (w == 1)
-    jw_get<S>(J, xb, 7, 0, lane);
+    jw_get<S>(J, xb, L, 0, lane);
   else if (w >= 2)
     jw_get<S>(J, xb, w - 1, 0, lane);
   __syncthreads();
@@ -311,7 +334,7 @@ __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int
 // sqrt(tol) (or max_sweeps); returns the sweep count.  lds_flag points to 2
 // ints of LDS.  A pair is rotated when |a_i . a_j| > tol ||a_i|| ||a_j|| and
 // neither column is numerically zero (norm^2 below 1e-30 of the largest).
-// Every thread of the 512-thread workgroup calls it; on return the columns
+// Every thread of the 64 NW-thread workgroup calls it; on return the columns
 // are back in their sweep-boundary slots (jw_col) and the squared norms are
 // in lds[S::NRM_OFF + id].
 template <class S>
@@ -350,17 +373,26 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
           jw_intra_move<S>(J);
         }
       }
-      // cross pairs of the two half-blocks: B steps, the bottom turned by one each
-      for (int sh = 0; sh < B; ++sh) {
-        jw_step<S, JWCross<S>>(J, nrm, scl, bc, floor2, tol2, conv2,
-                               [&](int p, int &it, int &ib) {
-                                 int q = p + sh;
-                                 if (q >= B) q -= B;
-                                 it = ht * B + p;
-                                 ib = hb * B + q;
-                               },
-                               rot, big);
-        jw_cross_move<S>(J);
+      // cross pairs of the two half-blocks: B steps, two per iteration (the
+      // second with the bottom offset by one slot), then the bottom turned by two
+      for (int sh = 0; sh < B; sh += 2) {
+        jw_step<S, JWCross<S, 0>>(J, nrm, scl, bc, floor2, tol2, conv2,
+                                  [&](int p, int &it, int &ib) {
+                                    int q = p + sh;
+                                    if (q >= B) q -= B;
+                                    it = ht * B + p;
+                                    ib = hb * B + q;
+                                  },
+                                  rot, big);
+        jw_step<S, JWCross<S, 1>>(J, nrm, scl, bc, floor2, tol2, conv2,
+                                  [&](int p, int &it, int &ib) {
+                                    int q = p + sh + 1;
+                                    if (q >= B) q -= B;
+                                    it = ht * B + p;
+                                    ib = hb * B + q;
+                                  },
+                                  rot, big);
+        jw_cross_move2<S>(J);
       }
       jw_exchange<S>(J, xb, w, lane);
     }
