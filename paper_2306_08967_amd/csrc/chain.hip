@@ -459,10 +459,10 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
   double *sv = lds;                        // NP values
   int *sid = ilds + 8;                     // NP column ids -> sorted order
   int *rank_of = ilds + 8 + 256;           // column id -> rank
-  const double *nrm = lds + S::NRM_OFF;
+
   __syncthreads();
   for (int j = tid(); j < NP; j += NT) {
-    sv[j] = sqrt(nrm[j]);
+    sv[j] = sqrt(jw_norm2<S>(lds, j));
     sid[j] = j;
   }
   __syncthreads();

@@ -20,8 +20,8 @@
 // DPP, the pair's rotation is computed by the lane that ends up with its dot
 // product, and read back by every lane from LDS.  Half-blocks move between
 // waves through LDS only between rounds (4 workgroup barriers per round).
-// Squared column norms live in LDS by column id; a wave touches only the norms
-// of the columns it holds.
+// Squared column norms (with the column scales below, as pairs) live in LDS by
+// column id; a wave touches only those of the columns it holds.
 //
 // Rotations are applied in scaled form: column i is held as x_i with a scale
 // d_i (a_i = d_i x_i, scales in LDS by id).  The rotation (c, s = c t) of the
@@ -33,6 +33,8 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+
+#include <utility>
 
 #include "common.h"
 #include "jacobi16.h"
@@ -51,14 +53,20 @@ struct JW {
   // leftover slot (rows 0 and 2)
   static constexpr int H = B / 2;
   static constexpr int QF = H / 2, QL = H % 2, QS = QF + QL;
+  static constexpr int XU = (B % 4 == 0) ? 4 : 2;  // cross steps per loop iteration
   static constexpr int SLOT = B * NP;      // doubles per half-block in the exchange buffer
-  static constexpr int NRM_OFF = NW * SLOT;
-  static constexpr int SCL_OFF = NRM_OFF + NP;
-  static constexpr int BC_OFF = SCL_OFF + NP;  // per wave: B rotation factor pairs
+  static constexpr int NS_OFF = NW * SLOT;      // per column id: (norm^2, scale) pairs
+  static constexpr int BC_OFF = NS_OFF + 2 * NP;  // per wave: B rotation factor pairs
   static constexpr int LDS = BC_OFF + NW * 2 * B;  // exchange, norms, scales, factors
   static_assert(NP % 64 == 0 && NP <= 192 && B % 2 == 0 && B * 2 * NW == NP,
                 "NP must be 64, 128 or 192 and split into 2 NW half-blocks of even width");
 };
+
+// squared norm of column id after jw_sweeps
+template <class S>
+__device__ __forceinline__ double jw_norm2(const double *lds, int id) {
+  return lds[S::NS_OFF + 2 * id];
+}
 
 template <class S>
 struct JWRegs {
@@ -123,10 +131,10 @@ __device__ __forceinline__ void jw_reduce(const double (&v)[S::B], double (&out)
   (void)B;
 }
 
-// Exact squared norms of the wave's 2B columns into nrm[] by column id (the
+// Exact squared norms of the wave's 2B columns into ns[].x by column id (the
 // wave holds its sweep-boundary half-blocks w and NW + w).
 template <class S>
-__device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double *nrm, int w) {
+__device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double2 *ns, int w) {
   constexpr int B = S::B, Q = S::QS, RPL = S::RPL;
   const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
 #pragma unroll
@@ -143,7 +151,7 @@ __device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double *nrm, int w)
     double mine = out[0];
 #pragma unroll
     for (int q = 1; q < Q; ++q) mine = (sl == q) ? out[q] : mine;
-    if (jw_plane<S>(row, sl)) nrm[jw_col<S>(w, half * B + jw_pair<S>(row, sl))] = mine;
+    if (jw_plane<S>(row, sl)) ns[jw_col<S>(w, half * B + jw_pair<S>(row, sl))].x = mine;
   }
 }
 
@@ -168,7 +176,7 @@ struct JWIntra {
 // writes it there and every lane reads all B back (broadcast reads; LDS
 // operations of one wave complete in order).
 template <class S, class PM, class IdF>
-__device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, double2 *bc,
+__device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
                                         double floor2, double tol2, double conv2, IdF ids, int &rot,
                                         int &big) {
   constexpr int B = S::B, Q = S::QS, RPL = S::RPL;
@@ -190,8 +198,9 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, 
   const int pair = plane ? jw_pair<S>(row, sl) : 0;
   int it, ib;
   ids(pair, it, ib);
-  const double al = nrm[it], be = nrm[ib];
-  const double di = scl[it], dj = scl[ib];
+  const double2 nsi = ns[it], nsj = ns[ib];
+  const double al = nsi.x, be = nsj.x;
+  const double di = nsi.y, dj = nsj.y;
   const double gt = myg * (di * dj);  // a_i . a_j
   const bool live = plane && al > floor2 && be > floor2;
   const double g2 = gt * gt, ab = al * be;
@@ -209,10 +218,8 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double *nrm, double *scl, 
   // (the new x_j), with d_j <- c d_j and d_i <- d_i / c
   const double t2 = t * (di * di) * inv, t1 = (cs * cs) * t * (dj * dj) * inv;
   if (doit) {
-    nrm[it] = fma(-t, gt, al);
-    nrm[ib] = fma(t, gt, be);
-    scl[it] = di * rcp_nr(cs);
-    scl[ib] = cs * dj;
+    ns[it] = make_double2(fma(-t, gt, al), di * rcp_nr(cs));
+    ns[ib] = make_double2(fma(t, gt, be), cs * dj);
   }
   rot += doit ? 1 : 0;
   if (plane) bc[pair] = make_double2(t1, t2);
@@ -263,25 +270,26 @@ __device__ __forceinline__ void jw_intra_move(JWRegs<S> &J) {
   }
 }
 
-// turn the bottom half-block by two columns: bottom p <- bottom p+2 (mod B)
-template <class S>
-__device__ __forceinline__ void jw_cross_move2(JWRegs<S> &J) {
+// turn the bottom half-block by K columns: bottom p <- bottom p+K (mod B)
+template <class S, int K>
+__device__ __forceinline__ void jw_cross_move(JWRegs<S> &J) {
   constexpr int B = S::B, RPL = S::RPL;
-  double b0[RPL], b1[RPL];
+  if (K % B == 0) return;
+  double keep[K][RPL];
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    b0[r] = J.a[B][r];
-    b1[r] = J.a[B + 1][r];
+  for (int q = 0; q < K; ++q) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) keep[q][r] = J.a[B + q][r];
   }
 #pragma unroll
-  for (int p = 0; p < B - 2; ++p) {
+  for (int p = 0; p < B - K; ++p) {
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) J.a[B + p][r] = J.a[B + p + 2][r];
+    for (int r = 0; r < RPL; ++r) J.a[B + p][r] = J.a[B + p + K][r];
   }
 #pragma unroll
-  for (int r = 0; r < RPL; ++r) {
-    J.a[2 * B - 2][r] = b0[r];
-    J.a[2 * B - 1][r] = b1[r];
+  for (int q = 0; q < K; ++q) {
+#pragma unroll
+    for (int r = 0; r < RPL; ++r) J.a[2 * B - K + q][r] = keep[q][r];
   }
 }
 
@@ -330,24 +338,40 @@ __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int
   __syncthreads();
 }
 
+// Steps sh .. sh + U - 1 of a cross round, the bottom offset by 0 .. U - 1 slots.
+template <class S, int U, int... SH>
+__device__ __forceinline__ void jw_cross_steps(JWRegs<S> &J, double2 *ns, double2 *bc, double floor2,
+                                               double tol2, double conv2, int ht, int hb, int sh,
+                                               int &rot, int &big, std::integer_sequence<int, SH...>) {
+  constexpr int B = S::B;
+  (jw_step<S, JWCross<S, SH>>(J, ns, bc, floor2, tol2, conv2,
+                              [&](int p, int &it, int &ib) {
+                                int q = p + sh + SH;
+                                if (q >= B) q -= B;
+                                it = ht * B + p;
+                                ib = hb * B + q;
+                              },
+                              rot, big),
+   ...);
+}
+
 // Sweeps until one applies no rotation or all its rotations were below
 // sqrt(tol) (or max_sweeps); returns the sweep count.  lds_flag points to 2
 // ints of LDS.  A pair is rotated when |a_i . a_j| > tol ||a_i|| ||a_j|| and
 // neither column is numerically zero (norm^2 below 1e-30 of the largest).
 // Every thread of the 64 NW-thread workgroup calls it; on return the columns
 // are back in their sweep-boundary slots (jw_col) and the squared norms are
-// in lds[S::NRM_OFF + id].
+// in lds[S::NS_OFF + 2 id] (jw_norm2).
 template <class S>
 __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweeps, double tol) {
-  constexpr int B = S::B, RPL = S::RPL;
+  constexpr int B = S::B, RPL = S::RPL, XU = S::XU;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double *xb = lds;
-  double *nrm = lds + S::NRM_OFF;
-  double *scl = lds + S::SCL_OFF;
+  double2 *ns = reinterpret_cast<double2 *>(lds + S::NS_OFF);
   double2 *bc = reinterpret_cast<double2 *>(lds + S::BC_OFF) + w * B;
-  jw_norms<S>(J, nrm, w);
-  for (int j = threadIdx.x; j < S::NP; j += blockDim.x) scl[j] = 1.0;
+  for (int j = threadIdx.x; j < S::NP; j += blockDim.x) ns[j].y = 1.0;
+  jw_norms<S>(J, ns, w);
   __syncthreads();
   const double tol2 = tol * tol, conv2 = tol;  // (sqrt(tol))^2
   int sweeps = 0;
@@ -355,14 +379,14 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
     int rot = 0, big = 0;
     double mx = 0.0;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) mx = fmax(mx, nrm[r * 64 + lane]);
+    for (int r = 0; r < RPL; ++r) mx = fmax(mx, ns[r * 64 + lane].x);
     const double floor2 = 1e-30 * wave_max_d(mx);
     for (int round = 0; round < 2 * S::NW - 1; ++round) {
       const int ht = j16_top_id<2 * S::NW>(w, round), hb = j16_bot_id<2 * S::NW>(w, round);
       if (round == 0) {
         // pairs inside each of the two half-blocks: a circle of B - 1 steps in each
         for (int st = 0; st < B - 1; ++st) {
-          jw_step<S, JWIntra<S>>(J, nrm, scl, bc, floor2, tol2, conv2,
+          jw_step<S, JWIntra<S>>(J, ns, bc, floor2, tol2, conv2,
                                  [&](int p, int &it, int &ib) {
                                    const int i = (p < B / 2) ? p : p - B / 2;
                                    const int h = (p < B / 2) ? ht : hb;
@@ -373,26 +397,12 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
           jw_intra_move<S>(J);
         }
       }
-      // cross pairs of the two half-blocks: B steps, two per iteration (the
-      // second with the bottom offset by one slot), then the bottom turned by two
-      for (int sh = 0; sh < B; sh += 2) {
-        jw_step<S, JWCross<S, 0>>(J, nrm, scl, bc, floor2, tol2, conv2,
-                                  [&](int p, int &it, int &ib) {
-                                    int q = p + sh;
-                                    if (q >= B) q -= B;
-                                    it = ht * B + p;
-                                    ib = hb * B + q;
-                                  },
-                                  rot, big);
-        jw_step<S, JWCross<S, 1>>(J, nrm, scl, bc, floor2, tol2, conv2,
-                                  [&](int p, int &it, int &ib) {
-                                    int q = p + sh + 1;
-                                    if (q >= B) q -= B;
-                                    it = ht * B + p;
-                                    ib = hb * B + q;
-                                  },
-                                  rot, big);
-        jw_cross_move2<S>(J);
+      // cross pairs of the two half-blocks: B steps, XU per iteration (step u
+      // with the bottom offset by u slots), then the bottom turned by XU
+      for (int sh = 0; sh < B; sh += XU) {
+        jw_cross_steps<S, XU>(J, ns, bc, floor2, tol2, conv2, ht, hb, sh, rot, big,
+                              std::make_integer_sequence<int, XU>{});
+        jw_cross_move<S, XU>(J);
       }
       jw_exchange<S>(J, xb, w, lane);
     }
@@ -403,13 +413,13 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
     // and another sweep would find nothing.
 #pragma unroll
     for (int c = 0; c < S::C; ++c) {
-      const double dc = scl[jw_col<S>(w, c)];
+      const double dc = ns[jw_col<S>(w, c)].y;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) J.a[c][r] *= dc;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < S::NP; j += blockDim.x) scl[j] = 1.0;
-    jw_norms<S>(J, nrm, w);
+    for (int j = threadIdx.x; j < S::NP; j += blockDim.x) ns[j].y = 1.0;
+    jw_norms<S>(J, ns, w);
     if (threadIdx.x == 0) {
       lds_flag[0] = 0;
       lds_flag[1] = 0;
