@@ -99,6 +99,10 @@ constexpr int NG = NT / 128;  // groups of 128 threads (one column each)
 // registers, reading both operands as 16-byte pairs.  aload(i, k), bload(k,
 // c) fetch the operands; cstore(i, c, v) writes the result.  Uses
 // KC (32 MR + 130) doubles of LDS; starts and ends with the caller's LDS free.
+template <int MR>
+constexpr int wg_gemm_lds() {
+  return 32 * (32 * MR + 2 + 128 + 2);
+}
 template <int MR, class AL, class BL, class CS>
 __device__ __forceinline__ void wg_gemm(int M, int N, int K, AL aload, BL bload, CS cstore,
                                         double *lds) {
@@ -180,81 +184,51 @@ __device__ __noinline__ void build_D(const ChunkState &cs, double *D) {
   __syncthreads();
 }
 
-// W^T (k x d) for one side.  side 0 (B): mode 1: W_B^T = UP; mode 0: W_B^T = D^T UP.
-// side 1 (C): mode 1: W_C^T = D VP; mode 0: W_C^T = VP.
+// W^T (k x d) for one side into Wg (global): side 0 (B): mode 1: W_B^T = UP;
+// mode 0: W_B^T = D^T UP.  side 1 (C): mode 1: W_C^T = D VP; mode 0: W_C^T =
+// VP.  D (LDS, s1 x s2) stays readable; stage is wg_gemm's LDS.
 __device__ __noinline__ void build_Wt(const ChunkState &cs, int side, int d, const double *D,
-                         const double *MP, double *Wt_lds) {
-  const int k = cs.k;
-  for (int e = tid(); e < k * d; e += NT) {
-    int t = e / d, c = e - t * d;
-    double v = 0.0;
-    if (side == 0) {
-      if (cs.mode) {
-        v = MP[t * d + c];
-      } else {
-        for (int i = 0; i < cs.s1; ++i) {
-          double dv = D[i * cs.s2 + t];
-          if (dv != 0.0) v = fma(dv, MP[i * d + c], v);
-        }
-      }
-    } else {
-      if (cs.mode) {
-        for (int j = 0; j < cs.s2; ++j) {
-          double dv = D[t * cs.s2 + j];
-          if (dv != 0.0) v = fma(dv, MP[j * d + c], v);
-        }
-      } else {
-        v = MP[t * d + c];
-      }
-    }
-    Wt_lds[t * d + c] = v;
+                                      const double *MP, double *Wg, double *stage) {
+  const int k = cs.k, s2 = cs.s2;
+  const bool copy = side ? (cs.mode == 0) : (cs.mode != 0);
+  if (copy) {
+    for (int e = tid(); e < k * d; e += NT) Wg[e] = MP[e];
+    __syncthreads();
+  } else if (side == 0) {
+    wg_gemm<2>(
+        k, d, cs.s1, [&](int t, int i) { return D[i * s2 + t]; },
+        [&](int i, int c) { return MP[i * d + c]; }, [&](int t, int c, double v) { Wg[t * d + c] = v; },
+        stage);
+  } else {
+    wg_gemm<2>(
+        k, d, s2, [&](int t, int j) { return D[t * s2 + j]; },
+        [&](int j, int c) { return MP[j * d + c]; }, [&](int t, int c, double v) { Wg[t * d + c] = v; },
+        stage);
   }
-  __syncthreads();
 }
 
 // G = B^T B - W^T W (side B) or C^T C - W^T W (side C), k x k in LDS (row
-// stride KMAX); also returns max(1, max diag of B^T B) through *bmax.
-// Thread t owns row a = t / 8 and columns b = 8 (t % 8) .. + 7.
+// stride KMAX), as one product [B^T | W] [B | -W]^T (B^T B = D^T D, C^T C =
+// D D^T, or I); also returns max(1, max diag of B^T B) through *bmax.
 __device__ __noinline__ void build_gram(const ChunkState &cs, int side, int d, const double *D,
-                           const double *Wt, double *G, double *bmax_out) {
-  const int k = cs.k;
+                                        const double *Wg, double *G, double *bmax_out, double *stage) {
+  const int k = cs.k, s2 = cs.s2;
   __shared__ double s_bmax;
+  const bool ident = (side == 0) ? (cs.mode != 0) : (cs.mode == 0);
+  const int sB = ident ? 0 : ((side == 0) ? cs.s1 : s2);
+  // column a of B (side B: D[:, a]) or row a of C^T (side C: D[a, :])
+  auto bel = [&](int a, int x) { return (side == 0) ? D[x * s2 + a] : D[a * s2 + x]; };
   if (tid() == 0) s_bmax = 1.0;
   __syncthreads();
-  // side B: B^T B = I (mode 1) or D^T D (mode 0); side C: C^T C = D D^T (mode 1) or I
-  const bool ident = (side == 0) ? (cs.mode != 0) : (cs.mode == 0);
-  for (int t = tid(); t < KMAX * 8; t += NT) {
-    const int a = t >> 3, b0 = (t & 7) * 8;
-    if (a >= k || b0 >= k) continue;
-    double w[8];
-#pragma unroll
-    for (int q = 0; q < 8; ++q) w[q] = 0.0;
-    for (int c = 0; c < d; ++c) {
-      const double wa = Wt[a * d + c];
-#pragma unroll
-      for (int q = 0; q < 8; ++q)
-        if (b0 + q < k) w[q] = fma(wa, Wt[(b0 + q) * d + c], w[q]);
-    }
-#pragma unroll
-    for (int q = 0; q < 8; ++q) {
-      const int b = b0 + q;
-      if (b >= k) break;
-      double btb;
-      if (ident) {
-        btb = (a == b) ? 1.0 : 0.0;
-      } else if (side == 0) {
-        btb = 0.0;
-        for (int i = 0; i < cs.s1; ++i) btb = fma(D[i * cs.s2 + a], D[i * cs.s2 + b], btb);
-      } else {
-        btb = 0.0;
-        for (int j = 0; j < cs.s2; ++j) btb = fma(D[a * cs.s2 + j], D[b * cs.s2 + j], btb);
-      }
-      G[a * KMAX + b] = btb - w[q];
-      if (a == b && btb > 1.0)
-        atomicMax((unsigned long long *)&s_bmax, __double_as_longlong(btb));
-    }
+  for (int a = tid(); a < k && sB > 0; a += NT) {
+    double v = 0.0;
+    for (int x = 0; x < sB; ++x) v = fma(bel(a, x), bel(a, x), v);
+    if (v > 1.0) atomicMax((unsigned long long *)&s_bmax, __double_as_longlong(v));
   }
-  __syncthreads();
+  wg_gemm<2>(
+      k, k, sB + d, [&](int a, int x) { return (x < sB) ? bel(a, x) : Wg[a * d + x - sB]; },
+      [&](int x, int b) { return (x < sB) ? bel(b, x) : -Wg[b * d + x - sB]; },
+      [&](int a, int b, double v) { G[a * KMAX + b] = (ident && a == b) ? 1.0 + v : v; }, stage);
   *bmax_out = s_bmax;
   __syncthreads();
 }
@@ -1034,12 +1008,13 @@ __global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, 
   clk.tick(p.stats, 0);
   double bmax = 1.0;
   double *D = lds;                              // s1 x s2 (<= 4096)
-  double *Wt = lds + KMAX * KMAX;               // k x d (<= 8192)
+  double *stage = lds + KMAX * KMAX;            // GEMM staging (< 8192)
+  static_assert(wg_gemm_lds<2>() <= KMAX * DMAX, "Step 1 GEMM staging must end before G");
   double *G = lds + KMAX * KMAX + KMAX * DMAX;  // k x k, row stride KMAX
+  double *Wg = scr + (side ? OFF_WC : OFF_WB);  // W^T, k x d
   build_D(cs, D);
-  build_Wt(cs, side, d, D, scr + (side ? OFF_VP : OFF_UP), Wt);
-  for (int e = tid(); e < k * d; e += NT) scr[(side ? OFF_WC : OFF_WB) + e] = Wt[e];
-  build_gram(cs, side, d, D, Wt, G, &bmax);
+  build_Wt(cs, side, d, D, scr + (side ? OFF_VP : OFF_UP), Wg, stage);
+  build_gram(cs, side, d, D, Wg, G, &bmax, stage);
   int *perm = ilds;
   const int rho = pivoted_cholesky(G, k, p.tau * bmax, perm, lds);
   store_factor(G, k, rho, perm, scr + (side ? OFF_LC : OFF_LB), scr + (side ? OFF_RC : OFF_RB));
