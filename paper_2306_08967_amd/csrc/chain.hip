@@ -643,60 +643,49 @@ __device__ __noinline__ void solve_Y(int side, int d, int k, int rho, const int 
   __syncthreads();
 }
 
-// F = E_top - W Y (d x d) and the row corrections.
+// F = E_top - W Y (d x d) and the row corrections, as workgroup GEMMs.
 __device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, int d, double *scr,
                                   double *lds) {
-  const int k = cs.k;
+  const int k = cs.k, s2 = cs.s2;
   const double *Y = scr + (side ? OFF_YC : OFF_YB);
   const double *Wt = scr + (side ? OFF_WC : OFF_WB);
   const double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
   double *F = scr + (side ? OFF_FV : OFF_FU);
   double *Dl = scr + (side ? OFF_DV : OFF_DU);
-  double *Ys = lds;               // k x d
-  double *Ws = lds + KMAX * DMAX;  // k x d
-  for (int e = tid(); e < k * d; e += NT) {
-    Ys[e] = Y[e];
-    Ws[e] = Wt[e];
-  }
-  __syncthreads();
-  {
-    const int c = tid() & 127;
-    if (c < d) {
-      for (int i = tid() >> 7; i < d; i += NG) {
-        double v = side ? HG[i * DMAX + c] : EG[c * NPMAX + i];
-        for (int t = 0; t < k; ++t) v -= Ws[t * d + i] * Ys[t * d + c];
-        F[i * d + c] = v;
-      }
-    }
-  }
-  __syncthreads();
+  wg_gemm<4>(
+      d, d, k, [&](int i, int t) { return Wt[t * d + i]; }, [&](int t, int c) { return Y[t * d + c]; },
+      [&](int i, int c, double v) {
+        F[i * d + c] = (side ? HG[i * DMAX + c] : EG[c * NPMAX + i]) - v;
+      },
+      lds);
   // row corrections: side B: mode 1 -> Y (s1 rows); mode 0 -> D Y (s1 x d)
   //                  side C: mode 1 -> D^T Y (s2 rows); mode 0 -> Y
-  double *D = lds + KMAX * DMAX;  // s1 x s2, over the W copy
-  for (int e = tid(); e < cs.s1 * cs.s2; e += NT) D[e] = 0.0;
+  const bool direct = side ? (cs.mode == 0) : (cs.mode != 0);
+  if (direct) {
+    for (int e = tid(); e < k * d; e += NT) Dl[e] = Y[e];
+    __syncthreads();
+    return;
+  }
+  double *D = lds;  // s1 x s2
+  double *stage = lds + KMAX * KMAX;
+  static_assert(KMAX * KMAX + wg_gemm_lds<2>() <= LDS_DOUBLES, "Step 3 staging does not fit");
+  for (int e = tid(); e < cs.s1 * s2; e += NT) D[e] = 0.0;
   __syncthreads();
   for (int e = tid(); e < cs.ne; e += NT) {
     NetEntry en = cs.ent[e];
     int i = (int)lower_bound(cs.S1, (int64_t)cs.s1, en.row);
-    int j = (int)lower_bound(cs.S2, (int64_t)cs.s2, en.col);
-    D[i * cs.s2 + j] = (double)en.delta;
+    int j = (int)lower_bound(cs.S2, (int64_t)s2, en.col);
+    D[i * s2 + j] = (double)en.delta;
   }
   __syncthreads();
-  const int rows = side ? cs.s2 : cs.s1;
-  const bool direct = side ? (cs.mode == 0) : (cs.mode != 0);
-  for (int e = tid(); e < rows * d; e += NT) {
-    int i = e / d, c = e - i * d;
-    double v = 0.0;
-    if (direct) {
-      v = Ys[i * d + c];
-    } else if (side == 0) {
-      for (int t = 0; t < k; ++t) v = fma(D[i * cs.s2 + t], Ys[t * d + c], v);
-    } else {
-      for (int t = 0; t < k; ++t) v = fma(D[t * cs.s2 + i], Ys[t * d + c], v);
-    }
-    Dl[i * d + c] = v;
-  }
-  __syncthreads();
+  if (side == 0)
+    wg_gemm<2>(
+        cs.s1, d, k, [&](int i, int t) { return D[i * s2 + t]; }, [&](int t, int c) { return Y[t * d + c]; },
+        [&](int i, int c, double v) { Dl[i * d + c] = v; }, stage);
+  else
+    wg_gemm<2>(
+        s2, d, k, [&](int i, int t) { return D[t * s2 + i]; }, [&](int t, int c) { return Y[t * d + c]; },
+        [&](int i, int c, double v) { Dl[i * d + c] = v; }, stage);
 }
 
 // Pn = Po F (d x d).
