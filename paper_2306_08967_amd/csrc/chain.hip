@@ -842,7 +842,10 @@ __device__ __forceinline__ int lu_solve_scatter(int d, const double *Pn, const d
       }
     }
     __syncthreads();
-    // A22 -= A21 U12: thread owns column c and rows j0 + jb + g, + NG, ...
+    // A22 -= A21 U12: thread owns column c and rows j0 + jb + g, + NG, ...,
+    // four rows at a time; with even d and a full panel a row of A21 is read
+    // as 16-byte pairs
+    const bool pairs = (d % 2 == 0) && jb == LUB;
     {
       const int c = tid() & 127;
       const int g = tid() >> 7;
@@ -850,12 +853,35 @@ __device__ __forceinline__ int lu_solve_scatter(int d, const double *Pn, const d
         double u[LUB];
 #pragma unroll
         for (int t = 0; t < LUB; ++t) u[t] = (t < jb) ? A[(j0 + t) * d + c] : 0.0;
-        for (int i = j0 + jb + g; i < d; i += NG) {
-          double v = A[i * d + c];
+        for (int i = j0 + jb + g; i < d; i += 4 * NG) {
+          double v[4];
 #pragma unroll
-          for (int t = 0; t < LUB; ++t)
-            if (t < jb) v -= A[i * d + j0 + t] * u[t];
-          A[i * d + c] = v;
+          for (int q = 0; q < 4; ++q) {
+            const int ii = i + q * NG;
+            v[q] = (ii < d) ? A[ii * d + c] : 0.0;
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int ii = i + q * NG;
+            if (ii < d && pairs) {
+              const double2 *ar = reinterpret_cast<const double2 *>(A + ii * d + j0);
+#pragma unroll
+              for (int t2 = 0; t2 < LUB / 2; ++t2) {
+                const double2 x = ar[t2];
+                v[q] = fma(-x.x, u[2 * t2], v[q]);
+                v[q] = fma(-x.y, u[2 * t2 + 1], v[q]);
+              }
+            } else if (ii < d) {
+#pragma unroll
+              for (int t = 0; t < LUB; ++t)
+                if (t < jb) v[q] = fma(-A[ii * d + j0 + t], u[t], v[q]);
+            }
+          }
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            const int ii = i + q * NG;
+            if (ii < d) A[ii * d + c] = v[q];
+          }
         }
       }
     }
@@ -884,6 +910,7 @@ __device__ __forceinline__ int lu_solve_scatter(int d, const double *Pn, const d
     y1[q] = (i < nrows && lane + 64 < d) ? Dl[i * d + lane + 64] : 0.0;
   }
   // Y U = Dl, forward over columns
+#pragma unroll 2
   for (int c = 0; c < d; ++c) {
     const double inv = 1.0 / A[c * d + c];
     const double u0 = (lane > c && lane < d) ? A[c * d + lane] : 0.0;
@@ -905,6 +932,7 @@ __device__ __forceinline__ int lu_solve_scatter(int d, const double *Pn, const d
     }
   }
   // W L = Y (L unit lower), backward over columns
+#pragma unroll 2
   for (int c = d - 1; c >= 0; --c) {
     const double l0 = (lane < c && lane < d) ? A[c * d + lane] : 0.0;
     const double l1 = (lane + 64 < c) ? A[c * d + lane + 64] : 0.0;

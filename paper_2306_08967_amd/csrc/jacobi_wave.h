@@ -212,13 +212,14 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
   const double q2 = fma(dd, dd, gg * gg);
   const double den = fabs(dd) + q2 * rsqrt_nr(q2);
   const double t = doit ? (dd >= 0.0 ? gg : -gg) * rcp_nr(den) : 0.0;
-  const double cs = rsqrt_nr(fma(t, t, 1.0));
+  const double q1 = fma(t, t, 1.0);
+  const double cs = rsqrt_nr(q1);
   const double inv = rcp_nr(di * dj);
   // two in-place shears: x_j += t (d_i / d_j) x_i, then x_i -= c^2 t (d_j / d_i) x_j
   // (the new x_j), with d_j <- c d_j and d_i <- d_i / c
   const double t2 = t * (di * di) * inv, t1 = (cs * cs) * t * (dj * dj) * inv;
   if (doit) {
-    ns[it] = make_double2(fma(-t, gt, al), di * rcp_nr(cs));
+    ns[it] = make_double2(fma(-t, gt, al), di * (q1 * cs));  // d_i / c = d_i (1 + t^2) c
     ns[ib] = make_double2(fma(t, gt, be), cs * dj);
   }
   rot += doit ? 1 : 0;
