@@ -34,8 +34,8 @@ FP64_CU_PEAK_TFLOPS = FP64_PEAK_TFLOPS / N_CU  # one compute unit (single-workgr
 
 # Sources of the core-SVD kernel: the PMC byte counts recorded in profiles/ hold
 # for the kernel built from exactly these files.
-CORE_SOURCES = ["paper_2306_08967_amd/csrc/chain.hip", "paper_2306_08967_amd/csrc/jacobi_wave.h",
-                "paper_2306_08967_amd/csrc/jacobi16.h", "paper_2306_08967_amd/csrc/common.h",
+CORE_SOURCES = ["paper_2306_08967_amd/csrc/chain.hip", "paper_2306_08967_amd/csrc/jacobi_wave.h", "paper_2306_08967_amd/csrc/wave_ops.h",
+                "paper_2306_08967_amd/csrc/common.h",
                 "paper_2306_08967_amd/csrc/damf_internal.h"]
 CORE_PMC = "profiles/pmc_chain_core_kernel_c2.md"
 

@@ -37,7 +37,7 @@
 #include <utility>
 
 #include "common.h"
-#include "jacobi16.h"
+#include "wave_ops.h"
 
 namespace damf {
 
