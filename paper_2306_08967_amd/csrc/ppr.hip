@@ -156,9 +156,9 @@ __device__ __forceinline__ void spread64(const int32_t *row, int cnt, const int3
       }
     }
   }
-  for (int q = 0; q < cnt; ++q) {
-    const int32_t u = __shfl(myu, q, 64);
-    const float sc = __shfl(mysc, q, 64);
+  for (int q = 0; q < cnt; ++q) {  // q is wave-uniform: lane reads, no LDS
+    const int32_t u = __builtin_amdgcn_readlane(myu, q);
+    const float sc = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(mysc), q));
     if (c0) atomicAdd(&R[(int64_t)u * d + lane], sc * r0);
     if (c1) atomicAdd(&R[(int64_t)u * d + lane + 64], sc * r1);
   }
@@ -183,8 +183,8 @@ __device__ __forceinline__ void flush_candidates(const int32_t *s_list, int s_cn
 // residual goes to hbuf and its row to segments of kSegEdges neighbours that
 // spread_heavy_kernel spreads with one wave each.  Counters: [1] frontier,
 // [2] next candidates, [3] edges, [4] heavy nodes, [5] heavy segments.
-constexpr int kHeavy = 512;
-constexpr int kSegEdges = 256;
+constexpr int kHeavy = 64;
+constexpr int kSegEdges = 64;
 __global__ __launch_bounds__(256) void push_kernel(Csr gin, const int32_t *outdeg,
                                                    const int32_t *frontier, float *R,
                                                    float *Z, int d, float alpha, int32_t round,
