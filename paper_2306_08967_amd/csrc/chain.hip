@@ -270,11 +270,6 @@ __device__ __forceinline__ void argmax_wave(double &v, int &i) {
     i = ia;
   }
 }
-__device__ __forceinline__ double readlane_f64(double x, int l) {
-  return __hiloint2double(__builtin_amdgcn_readlane(__double2hiint(x), l),
-                          __builtin_amdgcn_readlane(__double2loint(x), l));
-}
-
 // Pivoted Cholesky of the k x k PSD matrix G (LDS, row stride KMAX), by wave
 // 0 with row i of G in the VGPRs of lane i: each step picks the largest
 // remaining diagonal (wave argmax), stops when it is <= thr, else passes the
