@@ -56,7 +56,7 @@ enum { DAMF_DEVICE_PTRS = 1 };
 
 /* Configuration.  Fill with damf_config_default() and override fields. */
 typedef struct {
-  int64_t n;             /* number of nodes                                   */
+  int64_t n;             /* number of nodes, 1..2^30                          */
   int32_t d;             /* t-SVD rank = embedding width (Sec. 4.1); 1..128   */
   int32_t directed;      /* 0: an op on (u,v) edits A[u,v] and A[v,u]         */
   int32_t oversample;    /* randomized t-SVD oversampling p (default 10)      */
@@ -141,8 +141,9 @@ void damf_config_default(damf_config *cfg);
  * Q = qr(A^T Q), Q = qr(A Q), then B^T = A^T Q = Q2 R2 and svd(R2^T)), sets
  * the projections to the identity and propagates PPR until max |R| <= eps.
  * src/dst: m edges (duplicates collapse; self-loops are entries).
- * Errors: DAMF_E_INVALID_ARG (n < 1, d out of range, m < 0, null arrays with
- * m > 0), DAMF_E_OUT_OF_RANGE (id outside [0,n)), DAMF_E_OOM. */
+ * Errors: DAMF_E_INVALID_ARG (n outside 1..2^30, d out of range, m < 0, null arrays with
+ * m > 0), DAMF_E_OUT_OF_RANGE (id outside [0,n)), DAMF_E_OOM, DAMF_E_NUMERIC
+ * (the factorisation or the PPR residual came out NaN or infinite). */
 damf_status damf_init(const damf_config *cfg, int64_t m, const int32_t *src,
                       const int32_t *dst, int32_t flags, damf_ctx **out);
 

@@ -47,7 +47,9 @@ hipError_t dalloc(T **p, size_t count) {
 
 damf_status check_config(const damf_config *cfg) {
   if (!cfg) return DAMF_E_INVALID_ARG;
-  if (cfg->n < 1 || cfg->n > (int64_t)INT32_MAX) return DAMF_E_INVALID_ARG;
+  // node ids are int32; row-parallel launches (TSQR, the rotation GEMMs) take
+  // up to 4 work-items per node, and a dispatch holds fewer than 2^32
+  if (cfg->n < 1 || cfg->n > kMaxNodes) return DAMF_E_INVALID_ARG;
   if (cfg->d < 1 || cfg->d > kMaxD) return DAMF_E_INVALID_ARG;
   if (cfg->max_core_rank < 1 || cfg->max_side < 1 || cfg->max_side > kMaxSide)
     return DAMF_E_INVALID_ARG;
@@ -328,7 +330,7 @@ damf_status step_finish(damf_ctx *c, const BatchHeader &h) {
     API_HIP(c, csr_compact(c, c->in, c->cfg.graph_slack, 0), "CSR^T compaction");
   if (h.n_chunks > 0 && w.cstats_host->numeric_error) {
     c->poisoned = true;
-    return fail(c, DAMF_E_NUMERIC, "singular projection in the lazy update");
+    return fail(c, DAMF_E_NUMERIC, "singular projection or non-finite core in the lazy update");
   }
   return DAMF_OK;
 }
@@ -527,6 +529,10 @@ damf_status damf_init_factors(const damf_config *cfg, int64_t m, const int32_t *
       free_ctx(c);
       return DAMF_E_DEVICE;
     }
+    if (c->nonfinite) {
+      free_ctx(c);
+      return DAMF_E_NUMERIC;
+    }
   }
   if (hipStreamSynchronize(c->stream) != hipSuccess) {
     free_ctx(c);
@@ -560,6 +566,10 @@ damf_status damf_init(const damf_config *cfg, int64_t m, const int32_t *src, con
   if (e != hipSuccess) {
     free_ctx(c);
     return (e == hipErrorOutOfMemory) ? DAMF_E_OOM : DAMF_E_DEVICE;
+  }
+  if (c->nonfinite) {  // the factorisation produced NaN or Inf
+    free_ctx(c);
+    return DAMF_E_NUMERIC;
   }
   *out = c;
   return DAMF_OK;

@@ -21,6 +21,8 @@
 // (Step 4 input, Algorithm 2).
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
+
 #include "common.h"
 #include "damf_internal.h"
 #include "jacobi_wave.h"
@@ -353,7 +355,7 @@ __device__ __noinline__ void store_factor(const double *G, int k, int rho, const
 // ---------------------------------------------------------------- Step 2
 
 template <int RPL>
-__device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double *sigma, double *scr,
+__device__ __noinline__ int core_svd(const ChunkState &cs, int d, const double *sigma, double *scr,
                          double *lds, int *ilds, int *sweeps_out, uint64_t *ticks) {
   constexpr int NP = 64 * RPL;
   using S = JW<NP>;
@@ -430,8 +432,12 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
   int *rank_of = ilds + 8 + 256;           // column id -> rank
 
   __syncthreads();
+  // a NaN or infinite value gets the key -0.5: it sorts after every finite
+  // value and before the -1 padding, so the sort stays a total order and
+  // every real column keeps a rank below NP
   for (int j = tid(); j < NP; j += NT) {
-    sv[j] = sqrt(jw_norm2<S>(lds, j));
+    const double v = sqrt(jw_norm2<S>(lds, j));
+    sv[j] = (v <= DBL_MAX) ? v : -0.5;
     sid[j] = j;
   }
   __syncthreads();
@@ -461,6 +467,7 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
       __syncthreads();
     }
   }
+  const int nonfinite = sv[NP - 1] < 0.0;  // some column norm was NaN or infinite
   if (tid() < NP) rank_of[sid[tid()]] = tid();
   if (tid() < NPMAX) TH[tid()] = (tid() < NP) ? sv[tid()] : 0.0;
   __syncthreads();
@@ -547,6 +554,7 @@ __device__ __noinline__ void core_svd(const ChunkState &cs, int d, const double 
     }
   }
   __syncthreads();
+  return nonfinite;
 }
 
 // Orthonormal completion of columns c < d whose singular value is <= cut:
@@ -1051,13 +1059,14 @@ __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
   __syncthreads();
   PhaseClock clk;
   const int N = d + max(cs.rhoB, cs.rhoC);
-  int sw = 0;
+  int sw = 0, nonfinite;
   if (N <= 64)
-    core_svd<1>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
+    nonfinite = core_svd<1>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
   else if (N <= 128)
-    core_svd<2>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
+    nonfinite = core_svd<2>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
   else
-    core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
+    nonfinite = core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw, jt);
+  if (nonfinite && tid() == 0) atomicOr(&p.stats->numeric_error, 1);
   clk.tick(p.stats, 2);
   if (scr[OFF_TH + d - 1] <= 1e-10 * scr[OFF_TH]) {
     complete_basis(d, d + cs.rhoB, d + cs.rhoC, scr);

@@ -19,6 +19,10 @@ __device__ __forceinline__ float wave_max(float v) {
   return v;
 }
 
+// |x| for max reductions that must not skip a NaN (fmaxf drops NaN operands):
+// NaN becomes +inf, so a non-finite residual shows up as an infinite maximum.
+__device__ __forceinline__ float nan_to_inf(float a) { return (a == a) ? a : INFINITY; }
+
 __device__ __forceinline__ int wave_sum_i(int v) {
 #pragma unroll
   for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
@@ -40,6 +44,16 @@ __device__ __forceinline__ int64_t lower_bound(const T *a, int64_t n, T x) {
 }
 
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+// Workgroups for a grid-stride loop over `count` items taken `per_block` per
+// workgroup pass.  A dispatch holds at most 2^32 - 1 work-items in x, so a
+// grid over n x d elements (5e9 at n = 4e7, d = 128) or with one workgroup
+// per node must stride rather than grow with the problem.
+constexpr int64_t kMaxStrideBlocks = 1 << 16;
+inline unsigned stride_grid(int64_t count, int64_t per_block) {
+  const int64_t b = (count + per_block - 1) / per_block;
+  return (unsigned)(b < 1 ? 1 : (b > kMaxStrideBlocks ? kMaxStrideBlocks : b));
+}
 
 // ---- precision form: a basis element as a pair of BF16 numbers in one
 // 32-bit word, hi = bf16(x) in the upper half and lo = bf16(x - hi) in the

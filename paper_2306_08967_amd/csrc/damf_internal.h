@@ -12,6 +12,7 @@
 
 namespace damf {
 
+constexpr int64_t kMaxNodes = int64_t(1) << 30;  // nodes per context
 constexpr int kMaxBatch = 8192;     // ops per damf_update call (sorted in LDS)
 constexpr int kMaxCore = 192;       // d + chunk rank <= kMaxCore (Jacobi in VGPRs)
 constexpr int kMaxD = 128;          // embedding width
@@ -130,6 +131,7 @@ struct damf_ctx {
   bool own_stream = false;
   int device = 0;
   bool poisoned = false;
+  bool nonfinite = false;  // a residual maximum came out NaN or infinite
   std::string err;
   damf::Csr out, in;
   float *Ub = nullptr, *Vb = nullptr, *Zb = nullptr, *R = nullptr;

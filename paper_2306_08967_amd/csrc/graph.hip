@@ -122,39 +122,42 @@ struct CapOf {
 
 __global__ void validate_edges_kernel(const int32_t *src, const int32_t *dst, int64_t m,
                                       int64_t n, int32_t *bad) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  int32_t u = src[e], v = dst[e];
-  if (u < 0 || v < 0 || (int64_t)u >= n || (int64_t)v >= n) atomicAdd(bad, 1);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = src[e], v = dst[e];
+    if (u < 0 || v < 0 || (int64_t)u >= n || (int64_t)v >= n) atomicAdd(bad, 1);
+  }
 }
 
 hipError_t launch_validate_edges(const int32_t *src, const int32_t *dst, int64_t m,
                                  int64_t n, int32_t *bad, hipStream_t s) {
   DAMF_HIP(hipMemsetAsync(bad, 0, sizeof(int32_t), s));
-  if (m > 0) validate_edges_kernel<<<ceil_div(m, 256), 256, 0, s>>>(src, dst, m, n, bad);
+  if (m > 0) validate_edges_kernel<<<stride_grid(m, 256), 256, 0, s>>>(src, dst, m, n, bad);
   return hipGetLastError();
 }
 
 __global__ void count_rows_kernel(const int32_t *rows, const int32_t *cols, int64_t m,
                                   int32_t undirected, int32_t *cnt) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  int32_t u = rows[e], v = cols[e];
-  atomicAdd(&cnt[u], 1);
-  if (undirected && u != v) atomicAdd(&cnt[v], 1);
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = rows[e], v = cols[e];
+    atomicAdd(&cnt[u], 1);
+    if (undirected && u != v) atomicAdd(&cnt[v], 1);
+  }
 }
 
 __global__ void scatter_rows_kernel(const int32_t *rows, const int32_t *cols, int64_t m,
                                     int32_t undirected, const int64_t *off, int32_t *cursor,
                                     int32_t *tmp) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= m) return;
-  int32_t u = rows[e], v = cols[e];
-  int32_t p = atomicAdd(&cursor[u], 1);
-  tmp[off[u] + p] = v;
-  if (undirected && u != v) {
-    p = atomicAdd(&cursor[v], 1);
-    tmp[off[v] + p] = u;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < m;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t u = rows[e], v = cols[e];
+    int32_t p = atomicAdd(&cursor[u], 1);
+    tmp[off[u] + p] = v;
+    if (undirected && u != v) {
+      p = atomicAdd(&cursor[v], 1);
+      tmp[off[v] + p] = u;
+    }
   }
 }
 
@@ -218,15 +221,16 @@ __global__ __launch_bounds__(256) void sort_rows_small_kernel(int64_t n, const i
                                                               int32_t *len, int32_t *tmp,
                                                               int32_t *big, int32_t *nbig) {
   __shared__ int32_t buf[kSmallRow];
-  int64_t r = blockIdx.x;
-  if (r >= n) return;
-  int32_t L = len[r];
-  if (L <= 1) return;
-  if (L > kSmallRow) {
-    if (threadIdx.x == 0) big[atomicAdd(nbig, 1)] = (int32_t)r;
-    return;
+  // rows are workgroup-uniform, so the early continues keep barriers aligned
+  for (int64_t r = blockIdx.x; r < n; r += gridDim.x) {
+    const int32_t L = len[r];
+    if (L <= 1) continue;
+    if (L > kSmallRow) {
+      if (threadIdx.x == 0) big[atomicAdd(nbig, 1)] = (int32_t)r;
+      continue;
+    }
+    sort_unique_segment<256, kSmallRow>(tmp + off[r], L, buf, &len[r]);
   }
-  sort_unique_segment<256, kSmallRow>(tmp + off[r], L, buf, &len[r]);
 }
 
 __global__ __launch_bounds__(1024) void sort_rows_large_kernel(const int32_t *big,
@@ -274,27 +278,32 @@ __global__ __launch_bounds__(1024) void sort_rows_large_kernel(const int32_t *bi
 __global__ void copy_rows_kernel(int64_t n, const int64_t *src_off, const int32_t *tmp,
                                  const int64_t *start, const int32_t *len, int32_t *col) {
   // one wave per row
-  int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (r >= n) return;
-  int lane = threadIdx.x & 63;
-  int32_t L = len[r];
-  const int32_t *s = tmp + src_off[r];
-  int32_t *d = col + start[r];
-  for (int32_t j = lane; j < L; j += 64) d[j] = s[j];
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); r < n;
+       r += (int64_t)gridDim.x * (blockDim.x / 64)) {
+    const int32_t L = len[r];
+    const int32_t *s = tmp + src_off[r];
+    int32_t *d = col + start[r];
+    for (int32_t j = lane; j < L; j += 64) d[j] = s[j];
+  }
 }
 
 __global__ void sum_len_kernel(int64_t n, const int32_t *len, int64_t *total) {
-  const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int v = (r < n) ? len[r] : 0;
-  v = wave_sum_i(v);
+  int64_t v = 0;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x)
+    v += len[r];
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
   if ((threadIdx.x & 63) == 0 && v) atomicAdd((unsigned long long *)total, (unsigned long long)v);
 }
 
 __global__ void set_caps_kernel(int64_t n, const int32_t *len, int32_t *cap) {
-  int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (r >= n) return;
-  int32_t l = len[r];
-  cap[r] = l + (l >> 2) + 4;
+  for (int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; r < n;
+       r += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t l = len[r];
+    cap[r] = l + (l >> 2) + 4;
+  }
 }
 
 // Pool entries for `used` reserved entries and `edges` edges: at least
@@ -327,16 +336,16 @@ hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows, const int32_t *
   DAMF_HIP(hipMemsetAsync(g.cap, 0, n * sizeof(int32_t), s));
   DAMF_HIP(hipMemsetAsync(nbig, 0, sizeof(int32_t), s));
   if (m > 0) {
-    count_rows_kernel<<<ceil_div(m, 256), 256, 0, s>>>(d_rows, d_cols, m, und, g.len);
+    count_rows_kernel<<<stride_grid(m, 256), 256, 0, s>>>(d_rows, d_cols, m, und, g.len);
     DAMF_HIP(hipGetLastError());
   }
   DAMF_HIP(exclusive_scan(LenOf{g.len}, n, off, tmp_sums, total, s));
   if (m > 0) {
-    scatter_rows_kernel<<<ceil_div(m, 256), 256, 0, s>>>(d_rows, d_cols, m, und, off, g.cap,
+    scatter_rows_kernel<<<stride_grid(m, 256), 256, 0, s>>>(d_rows, d_cols, m, und, off, g.cap,
                                                          tmpcol);
     DAMF_HIP(hipGetLastError());
   }
-  sort_rows_small_kernel<<<(unsigned)n, 256, 0, s>>>(n, off, g.len, tmpcol, big, nbig);
+  sort_rows_small_kernel<<<stride_grid(n, 1), 256, 0, s>>>(n, off, g.len, tmpcol, big, nbig);
   DAMF_HIP(hipGetLastError());
   int32_t h_nbig = 0;
   DAMF_HIP(hipMemcpyAsync(&h_nbig, nbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -345,9 +354,9 @@ hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows, const int32_t *
     sort_rows_large_kernel<<<h_nbig, 1024, 0, s>>>(big, off, g.len, tmpcol);
     DAMF_HIP(hipGetLastError());
   }
-  set_caps_kernel<<<ceil_div(n, 256), 256, 0, s>>>(n, g.len, g.cap);
+  set_caps_kernel<<<stride_grid(n, 256), 256, 0, s>>>(n, g.len, g.cap);
   DAMF_HIP(hipMemsetAsync(total + 1, 0, sizeof(int64_t), s));
-  sum_len_kernel<<<ceil_div(n, 256), 256, 0, s>>>(n, g.len, total + 1);
+  sum_len_kernel<<<stride_grid(n, 256), 256, 0, s>>>(n, g.len, total + 1);
   DAMF_HIP(hipMemcpyAsync(&g.nnz_built, total + 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
   DAMF_HIP(exclusive_scan(CapOf{g.len}, n, g.start, tmp_sums, total, s));
   int64_t pool_used = 0;
@@ -355,7 +364,7 @@ hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows, const int32_t *
   DAMF_HIP(hipStreamSynchronize(s));
   g.pool_cap = pool_capacity(pool_used, m2, slack);
   DAMF_HIP(hipMalloc(&g.col, g.pool_cap * sizeof(int32_t)));
-  copy_rows_kernel<<<ceil_div(n, 4), 256, 0, s>>>(n, off, tmpcol, g.start, g.len, g.col);
+  copy_rows_kernel<<<stride_grid(n, 4), 256, 0, s>>>(n, off, tmpcol, g.start, g.len, g.col);
   DAMF_HIP(hipGetLastError());
   DAMF_HIP(hipMemcpyAsync(g.top, &pool_used, sizeof(int64_t), hipMemcpyHostToDevice, s));
   DAMF_HIP(hipStreamSynchronize(s));
@@ -383,13 +392,14 @@ hipError_t csr_free(Csr &g) {
 
 __global__ void gather_rows_kernel(int64_t n, const int64_t *start, const int32_t *len,
                                    const int32_t *col, const int64_t *indptr, int32_t *out) {
-  int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
-  if (r >= n) return;
-  int lane = threadIdx.x & 63;
-  int32_t L = len[r];
-  const int32_t *s = col + start[r];
-  int32_t *d = out + indptr[r];
-  for (int32_t j = lane; j < L; j += 64) d[j] = s[j];
+  const int lane = threadIdx.x & 63;
+  for (int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6); r < n;
+       r += (int64_t)gridDim.x * (blockDim.x / 64)) {
+    const int32_t L = len[r];
+    const int32_t *s = col + start[r];
+    int32_t *d = out + indptr[r];
+    for (int32_t j = lane; j < L; j += 64) d[j] = s[j];
+  }
 }
 
 hipError_t csr_export(damf_ctx *c, const Csr &g, int64_t *h_indptr, int32_t *h_indices,
@@ -410,7 +420,7 @@ hipError_t csr_export(damf_ctx *c, const Csr &g, int64_t *h_indptr, int32_t *h_i
   if (h_indices && m > 0) {
     int32_t *idx = nullptr;
     DAMF_HIP(hipMalloc(&idx, m * sizeof(int32_t)));
-    gather_rows_kernel<<<ceil_div(n, 4), 256, 0, s>>>(n, g.start, g.len, g.col, indptr, idx);
+    gather_rows_kernel<<<stride_grid(n, 4), 256, 0, s>>>(n, g.start, g.len, g.col, indptr, idx);
     DAMF_HIP(hipGetLastError());
     DAMF_HIP(hipMemcpyAsync(h_indices, idx, m * sizeof(int32_t), hipMemcpyDeviceToHost, s));
     DAMF_HIP(hipStreamSynchronize(s));
@@ -1095,7 +1105,7 @@ hipError_t csr_compact(damf_ctx *c, Csr &g, double slack, int64_t min_free) {
   DAMF_HIP(hipMalloc(&tmp_sums, (ceil_div(n, 1024) + 1) * sizeof(int64_t)));
   DAMF_HIP(hipMalloc(&total, 2 * sizeof(int64_t)));
   DAMF_HIP(hipMemsetAsync(total + 1, 0, sizeof(int64_t), s));
-  sum_len_kernel<<<ceil_div(n, 256), 256, 0, s>>>(n, g.len, total + 1);
+  sum_len_kernel<<<stride_grid(n, 256), 256, 0, s>>>(n, g.len, total + 1);
   DAMF_HIP(exclusive_scan(CapOf{g.len}, n, nstart, tmp_sums, total, s));
   int64_t h[2] = {0, 0};
   DAMF_HIP(hipMemcpyAsync(h, total, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -1103,8 +1113,8 @@ hipError_t csr_compact(damf_ctx *c, Csr &g, double slack, int64_t min_free) {
   const int64_t pool_used = h[0], nnz = h[1];
   const int64_t cap = std::max(pool_capacity(pool_used, nnz, slack), pool_used + min_free);
   DAMF_HIP(hipMalloc(&ncol, cap * sizeof(int32_t)));
-  copy_rows_kernel<<<ceil_div(n, 4), 256, 0, s>>>(n, g.start, g.col, nstart, g.len, ncol);
-  set_caps_kernel<<<ceil_div(n, 256), 256, 0, s>>>(n, g.len, g.cap);
+  copy_rows_kernel<<<stride_grid(n, 4), 256, 0, s>>>(n, g.start, g.col, nstart, g.len, ncol);
+  set_caps_kernel<<<stride_grid(n, 256), 256, 0, s>>>(n, g.len, g.cap);
   DAMF_HIP(hipGetLastError());
   DAMF_HIP(hipMemcpyAsync(g.start, nstart, n * sizeof(int64_t), hipMemcpyDeviceToDevice, s));
   DAMF_HIP(hipMemcpyAsync(g.top, &h[0], sizeof(int64_t), hipMemcpyHostToDevice, s));

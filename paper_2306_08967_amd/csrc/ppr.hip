@@ -281,15 +281,16 @@ __global__ __launch_bounds__(256) void spread_heavy_kernel(Csr gin, const int32_
 
 // FP32 copy of a basis stored as BF16 pairs.
 __global__ void decode_kernel(const float *M, float *out, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) out[i] = split_decode(__float_as_uint(M[i]));
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    out[i] = split_decode(__float_as_uint(M[i]));
 }
 
 __global__ void abs_max_kernel(const float *R, int64_t count, unsigned *maxbits) {
   float m = 0.f;
   for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
        i += (int64_t)gridDim.x * blockDim.x)
-    m = fmaxf(m, fabsf(R[i]));
+    m = fmaxf(m, nan_to_inf(fabsf(R[i])));
   m = wave_max(m);
   if ((threadIdx.x & 63) == 0 && m > 0.f) atomicMax(maxbits, __float_as_uint(m));
 }
@@ -302,7 +303,7 @@ hipError_t ppr_init(damf_ctx *c) {
   const int d = c->d;
   const size_t bytes = (size_t)n * d * sizeof(float);
   if (c->split) {
-    decode_kernel<<<ceil_div((int64_t)n * d, 256), 256, 0, s>>>(c->Ub, c->R, (int64_t)n * d);
+    decode_kernel<<<stride_grid((int64_t)n * d, 256), 256, 0, s>>>(c->Ub, c->R, (int64_t)n * d);
     DAMF_HIP(hipGetLastError());
   } else {
     DAMF_HIP(hipMemcpyAsync(c->R, c->Ub, bytes, hipMemcpyDeviceToDevice, s));
@@ -324,6 +325,10 @@ hipError_t ppr_init(damf_ctx *c) {
   for (int round = 0; round < 100000; ++round) {
     float mx;
     std::memcpy(&mx, &h, sizeof(float));
+    if (!std::isfinite(mx)) {  // NaN or Inf in the factors: stop, do not iterate on it
+      c->nonfinite = true;
+      break;
+    }
     if (!((double)mx > c->cfg.eps)) break;
     DAMF_HIP(hipMemsetAsync(maxbits, 0, sizeof(unsigned), s));
     DAMF_HIP(hipEventRecord(c->ev_k[0], s));

@@ -13,6 +13,7 @@
 // rotation GEMM on MFMA (FP32 in, FP32 accumulate).
 #include <hip/hip_runtime.h>
 
+#include <cfloat>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -36,12 +37,13 @@ __device__ __forceinline__ uint64_t splitmix64_out(uint64_t state) {
 }
 
 __global__ void sketch_kernel(float *Om, int64_t n, int l, int ld, uint64_t seed) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= n * l) return;
-  const int64_t i = e / l;
-  const int j = (int)(e - i * l);
-  const uint64_t ctr = (seed << 40) ^ ((uint64_t)i * (uint64_t)l + (uint64_t)j);
-  Om[i * ld + j] = (splitmix64_out(ctr) >> 63) ? -1.f : 1.f;
+  for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < n * l;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t i = e / l;
+    const int j = (int)(e - i * l);
+    const uint64_t ctr = (seed << 40) ^ ((uint64_t)i * (uint64_t)l + (uint64_t)j);
+    Om[i * ld + j] = (splitmix64_out(ctr) >> 63) ? -1.f : 1.f;
+  }
 }
 
 // ---------------------------------------------------------------- TSQR
@@ -231,6 +233,54 @@ __global__ __launch_bounds__(TNT) void tsqr_formq_kernel(float *A, int64_t m, in
 }
 
 // ---------------------------------------------------------------- small SVD
+
+// Orthonormal completion, by one wave, of the columns c of M (l x d,
+// row-major, l <= 192) whose singular value sv[c] is <= cut: unit vectors
+// e_q, q = 0, 1, ..., are orthogonalised (two Gram-Schmidt passes) against
+// the kept columns and the completed ones before c, and the first with at
+// least a quarter of its norm left is taken.
+__device__ void complete_columns(double *M, int l, int d, const double *sv, double cut) {
+  const int lane = threadIdx.x & 63;
+  for (int c = 0; c < d; ++c) {
+    if (sv[c] > cut) continue;
+    for (int q = 0; q < l; ++q) {
+      double v[3];
+#pragma unroll
+      for (int r = 0; r < 3; ++r) v[r] = (r * 64 + lane == q) ? 1.0 : 0.0;
+      for (int pass = 0; pass < 2; ++pass) {
+        for (int o = 0; o < d; ++o) {
+          if (o == c || (sv[o] <= cut && o > c)) continue;
+          double dot = 0.0;
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const int i = r * 64 + lane;
+            if (i < l) dot = fma(M[i * d + o], v[r], dot);
+          }
+          dot = wave_sum(dot);
+#pragma unroll
+          for (int r = 0; r < 3; ++r) {
+            const int i = r * 64 + lane;
+            if (i < l) v[r] = fma(-dot, M[i * d + o], v[r]);
+          }
+        }
+      }
+      double nn = 0.0;
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+        if (r * 64 + lane < l) nn = fma(v[r], v[r], nn);
+      nn = wave_sum(nn);
+      if (nn > 0.25) {
+        const double inv = 1.0 / sqrt(nn);
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          const int i = r * 64 + lane;
+          if (i < l) M[i * d + c] = v[r] * inv;
+        }
+        break;
+      }
+    }
+  }
+}
 // FP64 one-sided Jacobi SVD of M (l x l, row-major FP32 upper-triangular R
 // given; the kernel factors M = R^T).  Outputs the top d left vectors E
 // (l x d), singular values and right vectors H = M^T E Theta^-1 (l x d),
@@ -258,8 +308,12 @@ __global__ __launch_bounds__(1024) void small_svd_kernel(const float *Rtop, int 
   }
   jacobi_sweeps<RPL, NW>(J, lds, &flag, 40, 1e-12);
   const double *nrm = lds + 4 * NW * SH::SLOT;
+  // a NaN or infinite norm gets the key -0.5: after every finite value and
+  // before the -1 padding, so the sort is a total order and every real
+  // column ranks below NP (theta < 0 then reports the failure)
   for (int j = threadIdx.x; j < 256; j += 1024) {
-    sv[j] = (j < NP) ? sqrt(nrm[j]) : -1.0;
+    const double v = (j < NP) ? sqrt(nrm[j]) : -1.0;
+    sv[j] = (j >= NP || v <= DBL_MAX) ? v : -0.5;
     sid[j] = j;
   }
   __syncthreads();
@@ -307,6 +361,13 @@ __global__ __launch_bounds__(1024) void small_svd_kernel(const float *Rtop, int 
     double acc = 0.0;
     for (int i = 0; i < l; ++i) acc = fma((double)Rtop[j * l + i], E[i * d + c], acc);
     H[j * d + c] = (sv[c] > cut) ? acc / sv[c] : 0.0;
+  }
+  __syncthreads();
+  // rank(A) < d leaves columns with theta <= cut: complete E and H to
+  // orthonormal columns so that U = Q E and V = Q2 H stay orthonormal
+  if (threadIdx.x < 64 && sv[d - 1] <= cut) {
+    complete_columns(E, l, d, sv, cut);
+    complete_columns(H, l, d, sv, cut);
   }
 }
 
@@ -366,8 +427,9 @@ __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t 
 }
 
 __global__ void encode_kernel(float *M, int64_t count) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < count) M[i] = __uint_as_float(split_encode(M[i]));
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+       i += (int64_t)gridDim.x * blockDim.x)
+    M[i] = __uint_as_float(split_encode(M[i]));
 }
 
 __global__ void to_float_kernel(const double *x, float *y, int64_t count) {
@@ -462,7 +524,7 @@ hipError_t rsvd_init(damf_ctx *c) {
   DAMF_HIP(hipMalloc(&th, (size_t)kMaxCore * sizeof(double)));
   DAMF_HIP(hipMalloc(&Ef, (size_t)l * d * sizeof(float)));
   DAMF_HIP(hipMalloc(&Hf, (size_t)l * d * sizeof(float)));
-  sketch_kernel<<<ceil_div(n * l, 256), 256, 0, s>>>(T, n, l, ld, c->cfg.seed);
+  sketch_kernel<<<stride_grid(n * l, 256), 256, 0, s>>>(T, n, l, ld, c->cfg.seed);
   DAMF_HIP(hipGetLastError());
   SpmmPlan pout, pin;
   DAMF_HIP(spmm_plan_build(c, c->out, ld, &pout));
@@ -487,8 +549,8 @@ hipError_t rsvd_init(damf_ctx *c) {
   DAMF_HIP(gemm_tall(Y, n, l, ld, Ef, d, c->Ub, d, s));  // U = Q Ut_d
   DAMF_HIP(gemm_tall(T, n, l, ld, Hf, d, c->Vb, d, s));  // V = Q2 Vt_d
   if (c->split) {  // precision form: store the bases as BF16 pairs
-    encode_kernel<<<ceil_div((int64_t)n * d, 256), 256, 0, s>>>(c->Ub, (int64_t)n * d);
-    encode_kernel<<<ceil_div((int64_t)n * d, 256), 256, 0, s>>>(c->Vb, (int64_t)n * d);
+    encode_kernel<<<stride_grid((int64_t)n * d, 256), 256, 0, s>>>(c->Ub, (int64_t)n * d);
+    encode_kernel<<<stride_grid((int64_t)n * d, 256), 256, 0, s>>>(c->Vb, (int64_t)n * d);
     DAMF_HIP(hipGetLastError());
   }
   // projections = I, Sigma
@@ -498,7 +560,11 @@ hipError_t rsvd_init(damf_ctx *c) {
   DAMF_HIP(hipMemcpyAsync(c->P, P.data(), P.size() * sizeof(double), hipMemcpyHostToDevice, s));
   DAMF_HIP(hipMemsetAsync(c->sigma, 0, kMaxCore * sizeof(double), s));
   DAMF_HIP(hipMemcpyAsync(c->sigma, th, d * sizeof(double), hipMemcpyDeviceToDevice, s));
+  std::vector<double> th_host(d);
+  DAMF_HIP(hipMemcpyAsync(th_host.data(), th, d * sizeof(double), hipMemcpyDeviceToHost, s));
   DAMF_HIP(hipStreamSynchronize(s));
+  for (double t : th_host)  // NaN or Inf anywhere upstream ends as theta < 0 or non-finite
+    if (!(t >= 0.0 && t <= DBL_MAX)) c->nonfinite = true;
   (void)hipFree(Y);
   (void)hipFree(T);
   (void)hipFree(Rt);

@@ -73,7 +73,7 @@ __device__ __forceinline__ float finish_row(int64_t u, int32_t L, const float (&
       Y[i] = r;
       if (mode == 1) {
         Z[i] += alpha * X[i];
-        m = fmaxf(m, fabsf(r));
+        m = fmaxf(m, nan_to_inf(fabsf(r)));
       }
     }
   }
@@ -158,13 +158,13 @@ __global__ __launch_bounds__(256) void spmm_long_finish_kernel(
 
 // Plan: long rows (append order), their first segment, and the segment list.
 __global__ void count_long_kernel(Csr g, int64_t n, int64_t *counts) {
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t rows = 0, segs = 0;
-  if (u < n) {
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x) {
     const int32_t L = g.len[u];
     if (L > kSegLen) {
-      rows = 1;
-      segs = (L + kSegLen - 1) / kSegLen;
+      rows += 1;
+      segs += (L + kSegLen - 1) / kSegLen;
     }
   }
   for (int off = 32; off > 0; off >>= 1) {
@@ -179,18 +179,19 @@ __global__ void count_long_kernel(Csr g, int64_t n, int64_t *counts) {
 
 __global__ void fill_long_kernel(Csr g, int64_t n, int64_t *cursor, int32_t *long_row,
                                  int64_t *long_seg0, int32_t *seg_row, int32_t *seg_idx) {
-  const int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (u >= n) return;
-  const int32_t L = g.len[u];
-  if (L <= kSegLen) return;
-  const int32_t ns = (L + kSegLen - 1) / kSegLen;
-  const int64_t h = (int64_t)atomicAdd((unsigned long long *)&cursor[0], 1ull);
-  const int64_t s0 = (int64_t)atomicAdd((unsigned long long *)&cursor[1], (unsigned long long)ns);
-  long_row[h] = (int32_t)u;
-  long_seg0[h] = s0;
-  for (int32_t j = 0; j < ns; ++j) {
-    seg_row[s0 + j] = (int32_t)u;
-    seg_idx[s0 + j] = j;
+  for (int64_t u = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; u < n;
+       u += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t L = g.len[u];
+    if (L <= kSegLen) continue;
+    const int32_t ns = (L + kSegLen - 1) / kSegLen;
+    const int64_t h = (int64_t)atomicAdd((unsigned long long *)&cursor[0], 1ull);
+    const int64_t s0 = (int64_t)atomicAdd((unsigned long long *)&cursor[1], (unsigned long long)ns);
+    long_row[h] = (int32_t)u;
+    long_seg0[h] = s0;
+    for (int32_t j = 0; j < ns; ++j) {
+      seg_row[s0 + j] = (int32_t)u;
+      seg_idx[s0 + j] = j;
+    }
   }
 }
 
@@ -204,7 +205,7 @@ hipError_t spmm_plan_build(damf_ctx *c, const Csr &g, int kmax, SpmmPlan *p) {
   int64_t *counts = nullptr;
   DAMF_HIP(hipMalloc(&counts, 4 * sizeof(int64_t)));
   DAMF_HIP(hipMemsetAsync(counts, 0, 4 * sizeof(int64_t), s));
-  count_long_kernel<<<ceil_div(n, 256), 256, 0, s>>>(g, n, counts);
+  count_long_kernel<<<stride_grid(n, 256), 256, 0, s>>>(g, n, counts);
   DAMF_HIP(hipGetLastError());
   int64_t h[2] = {0, 0};
   DAMF_HIP(hipMemcpyAsync(h, counts, 2 * sizeof(int64_t), hipMemcpyDeviceToHost, s));
@@ -218,7 +219,7 @@ hipError_t spmm_plan_build(damf_ctx *c, const Csr &g, int kmax, SpmmPlan *p) {
     DAMF_HIP(hipMalloc(&p->seg_idx, p->nseg * sizeof(int32_t)));
     DAMF_HIP(hipMalloc(&p->part, (size_t)p->nseg * kmax * sizeof(float)));
     DAMF_HIP(hipMemsetAsync(counts + 2, 0, 2 * sizeof(int64_t), s));
-    fill_long_kernel<<<ceil_div(n, 256), 256, 0, s>>>(g, n, counts + 2, p->long_row, p->long_seg0,
+    fill_long_kernel<<<stride_grid(n, 256), 256, 0, s>>>(g, n, counts + 2, p->long_row, p->long_seg0,
                                                       p->seg_row, p->seg_idx);
     DAMF_HIP(hipGetLastError());
   }
