@@ -81,6 +81,10 @@ def parse():
                     help="1: the precision form (bases as BF16 pairs, BF16 MFMA rotations)")
     ap.add_argument("--mode", choices=("update", "serve"), default="update",
                     help="update: batches through damf_update (default); serve: the server")
+    ap.add_argument("--workload", choices=("c2", "billion"), default="c2",
+                    help="c2 (default): Chung-Lu 2.1, n=1e6, m=1e7, batches of 1000 ops; billion: "
+                         "Chung-Lu 2.0, n=4e7, m=1e9, precision form, batches of 100 inserts, "
+                         "eps=1e-6 (generated on the GPU)")
     ap.add_argument("--serve-n", type=int, default=10_000_000)
     ap.add_argument("--serve-m", type=int, default=200_000_000)
     ap.add_argument("--serve-requests", type=int, default=6000)
@@ -324,6 +328,130 @@ def serve_main(args):
     print(json.dumps(line), flush=True)
 
 
+def chung_lu_edges_gpu(n, m, beta, seed):
+    """Directed Chung-Lu edge set drawn on the GPU (torch): weights (i + i0)^(-1/(beta-1))
+    with i0 set so the largest expected degree is sqrt(m), independently permuted out- and
+    in-labels, self-loops and duplicates dropped and redrawn until m distinct edges remain,
+    then shuffled.  Returns (src, dst) int32 device tensors and the sampler's pieces."""
+    import torch
+    g = torch.Generator(device="cuda")
+    g.manual_seed(seed)
+    gamma = 1.0 / (beta - 1.0)
+    idx = torch.arange(n, dtype=torch.float64, device="cuda")
+    lo, hi, target = 1e-3, float(n), m ** 0.5
+    for _ in range(100):
+        mid = (lo * hi) ** 0.5
+        w = (idx + mid) ** (-gamma)
+        if m * float(w[0]) / float(w.sum()) > target:
+            lo = mid
+        else:
+            hi = mid
+    w = (idx + hi) ** (-gamma)
+    cdf = torch.cumsum(w / w.sum(), 0)
+    cdf[-1] = 1.0
+    del w, idx
+    perm_out = torch.randperm(n, generator=g, device="cuda")
+    perm_in = torch.randperm(n, generator=g, device="cuda")
+
+    def draw(cnt):
+        a = torch.searchsorted(cdf, torch.rand(cnt, generator=g, device="cuda", dtype=torch.float64),
+                               right=True).clamp_(max=n - 1)
+        b = torch.searchsorted(cdf, torch.rand(cnt, generator=g, device="cuda", dtype=torch.float64),
+                               right=True).clamp_(max=n - 1)
+        return perm_out[a], perm_in[b]
+
+    keys = torch.empty(0, dtype=torch.int64, device="cuda")
+    while keys.numel() < m:
+        need = m - keys.numel()
+        parts = []
+        left = int(need * 1.05) + 4096
+        while left > 0:
+            c = min(left, 200_000_000)
+            s, t = draw(c)
+            ok = s != t
+            parts.append(s[ok] * n + t[ok])
+            left -= c
+            del s, t, ok
+        keys = torch.unique(torch.cat([keys] + parts))
+        del parts
+    keys = keys[torch.randperm(keys.numel(), generator=g, device="cuda")[:m]]
+    src = (keys // n).to(torch.int32)
+    dst = (keys % n).to(torch.int32)
+    del keys
+    return src, dst, draw
+
+
+def billion_main(args):
+    """Billion-edge form: one GPU holds the graph, the BF16-pair bases and the PPR state."""
+    import torch
+
+    from paper_2306_08967_amd import Context, default_config
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n, m, d, K, W, bs = 40_000_000, 1_000_000_000, 128, args.steps, args.warmup, 100
+    t0 = time.perf_counter()
+    src, dst, draw = chung_lu_edges_gpu(n, m, 2.0, args.seed)
+    batches = []
+    for _ in range(W + K):
+        s, t = draw(bs)
+        batches.append((s.to(torch.int32).contiguous(), t.to(torch.int32).contiguous(),
+                        torch.ones(bs, dtype=torch.int8, device="cuda")))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()  # hand the generator's scratch back before the library allocates
+    log(f"billion workload: n={n} m={m} on the GPU in {time.perf_counter() - t0:.1f}s; "
+        f"{W + K} batches of {bs} inserts")
+    cfg = default_config(n, d, directed=True, alpha=0.15, eps=1e-6, oversample=10,
+                         power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64,
+                         precision=1, kernel_timing=1)
+    t0 = time.perf_counter()
+    ctx = Context.init(cfg, src, dst)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    del src, dst
+    ii = ctx.init_info()
+    log(f"init {init_s:.1f}s: graph {ii['ms_graph']:.0f} ms, rsvd {ii['ms_rsvd']:.0f} ms, "
+        f"ppr {ii['ms_ppr']:.0f} ms ({ii['ppr_rounds']} rounds); device memory in use "
+        f"{torch.cuda.memory_allocated() / 2**30:.1f} GiB (torch) / "
+        f"{(torch.cuda.mem_get_info()[1] - torch.cuda.mem_get_info()[0]) / 2**30:.1f} GiB (device)")
+    for b in range(W):
+        wi = ctx.update(*batches[b])
+        log(f"warmup {b + 1}/{W}: chunks {wi['chunks']} push rounds {wi['push_rounds']} "
+            f"pushes {wi['pushes']}")
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t_start = time.perf_counter()
+    for b in range(W, W + K):
+        t = time.perf_counter()
+        infos.append(ctx.update(*batches[b]))
+        lat.append(time.perf_counter() - t)
+        if (b - W) % 20 == 19:
+            log(f"step {b - W + 1}/{K}: last {lat[-1] * 1e3:.2f} ms")
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t_start
+    value = K * bs / T
+
+    def mean(key):
+        return float(np.mean([i[key] for i in infos]))
+
+    out = {
+        "metric": "edge-updates/s", "value": value, "unit": "edge-updates/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": T / K * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x2", "data": "synthetic",
+        "config": {"workload": "chung-lu-2.0 n=4e7 m=1e9 d=128 batch=100 inserts, alpha=0.15 "
+                               "eps=1e-6, precision form", "n": n, "m": m, "d": d, "batch": bs},
+        "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
+                       "mean": float(np.mean(lat)) * 1e3},
+        "init_s": init_s, "init_ms": ii,
+        "stage_ms_mean": {k: mean(k) for k in ("ms_prepare", "ms_chain", "ms_enhance",
+                                               "ms_core_kernel", "ms_push_kernel")},
+        "per_batch_mean": {k: mean(k) for k in ("chunks", "sweeps", "push_rounds", "pushes",
+                                                "push_edges")},
+        "residual_max": ctx.residual_max(),
+        "cpu_baseline": None,
+    }
+    print(json.dumps(out))
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -342,6 +470,12 @@ def main():
     args = parse()
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
+        return
+    if args.workload == "billion":
+        if args.gpus != 1:
+            print("bench.py runs on one GPU only", file=sys.stderr)
+            sys.exit(2)
+        billion_main(args)
         return
     if args.mode == "serve":
         if args.gpus != 1:
