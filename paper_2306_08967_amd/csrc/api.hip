@@ -122,6 +122,9 @@ damf_status alloc_state(damf_ctx *c) {
   for (auto &e : c->ev) API_HIP(c, hipEventCreate(&e), "event");
   API_HIP(c, hipEventCreate(&c->ev_k[0]), "event");
   API_HIP(c, hipEventCreate(&c->ev_k[1]), "event");
+  API_HIP(c, hipStreamCreateWithFlags(&c->scatter_stream, hipStreamNonBlocking), "stream");
+  for (auto &e : c->ev_back) API_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  for (auto &e : c->ev_scatter) API_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
   if (c->cfg.kernel_timing)
     for (auto &e : c->ev_core) API_HIP(c, hipEventCreate(&e), "event");
   return DAMF_OK;
@@ -130,6 +133,7 @@ damf_status alloc_state(damf_ctx *c) {
 void free_ctx(damf_ctx *c) {
   if (!c) return;
   if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->scatter_stream) (void)hipStreamSynchronize(c->scatter_stream);
   csr_free(c->out);
   csr_free(c->in);
   void *ptrs[] = {c->Ub, c->Vb, c->Zb, c->R, c->P, c->Pnext, c->sigma,
@@ -155,6 +159,14 @@ void free_ctx(damf_ctx *c) {
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->ev_core)
     if (e) (void)hipEventDestroy(e);
+  for (auto &e : c->ev_back)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &e : c->ev_scatter)
+    if (e) (void)hipEventDestroy(e);
+  if (c->scatter_stream) {
+    (void)hipStreamSynchronize(c->scatter_stream);
+    (void)hipStreamDestroy(c->scatter_stream);
+  }
   if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
   delete c;
 }
@@ -305,7 +317,7 @@ damf_status step_chain(damf_ctx *c, const BatchHeader &h) {
   if (h.n_chunks <= 0) return DAMF_OK;
   hipStream_t s = c->stream;
   API_HIP(c, hipEventRecord(c->ev[4], s), "event");
-  API_HIP(c, launch_chain(c, h.n_chunks), "chain");
+  API_HIP(c, launch_chain(c, h.n_chunks, h.meets_prev), "chain");
   API_HIP(c, hipEventRecord(c->ev[5], s), "event");
   return DAMF_OK;
 }

@@ -59,9 +59,16 @@ constexpr size_t OFF_DU = OFF_FV + DMAX * DMAX;           // dU rows [i][c]
 constexpr size_t OFF_DV = OFF_DU + KMAX * DMAX;
 constexpr size_t OFF_YB = OFF_DV + KMAX * DMAX;           // Y = T E_bot [t][c]
 constexpr size_t OFF_YC = OFF_YB + KMAX * DMAX;
-constexpr size_t OFF_TH = OFF_YC + KMAX * DMAX;           // theta (NPMAX)
+constexpr size_t OFF_DU2 = OFF_YC + KMAX * DMAX;          // dU, dV of odd chunks
+constexpr size_t OFF_DV2 = OFF_DU2 + KMAX * DMAX;
+constexpr size_t OFF_TH = OFF_DV2 + KMAX * DMAX;          // theta (NPMAX)
 constexpr size_t OFF_META = OFF_TH + NPMAX + 64;         // ints: rho_B, rho_C, perm_B, perm_C
 constexpr size_t SCRATCH_DOUBLES = OFF_META + (2 + 2 * KMAX) / 2 + 8;
+// Row corrections of chunk ch (side 0: dU on S1, side 1: dV on S2), by chunk
+// parity: the solve-and-scatter of chunk ch runs while chunk ch + 1 computes.
+__host__ __device__ constexpr size_t off_dl(int side, int ch) {
+  return (ch & 1) ? (side ? OFF_DV2 : OFF_DU2) : (side ? OFF_DV : OFF_DU);
+}
 
 struct ChainParams {
   int d;
@@ -648,13 +655,13 @@ __device__ __noinline__ void solve_Y(int side, int d, int k, int rho, const int 
 
 // F = E_top - W Y (d x d) and the row corrections, as workgroup GEMMs.
 __device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, int d, double *scr,
-                                  double *lds) {
+                                  double *lds, int ch) {
   const int k = cs.k, s2 = cs.s2;
   const double *Y = scr + (side ? OFF_YC : OFF_YB);
   const double *Wt = scr + (side ? OFF_WC : OFF_WB);
   const double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
   double *F = scr + (side ? OFF_FV : OFF_FU);
-  double *Dl = scr + (side ? OFF_DV : OFF_DU);
+  double *Dl = scr + off_dl(side, ch);
   wg_gemm<4>(
       d, d, k, [&](int i, int t) { return Wt[t * d + i]; }, [&](int t, int c) { return Y[t * d + c]; },
       [&](int i, int c, double v) {
@@ -1094,7 +1101,6 @@ __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
 __global__ __launch_bounds__(NT) void chain_back_kernel(ChainParams p, int ch, const double *Pc,
                                                         double *Pn) {
   __shared__ __align__(16) double lds[LDS_DOUBLES];
-  __shared__ __align__(16) int ilds[1024];
   const int side = blockIdx.x;
   const int d = p.d;
   double *scr = p.scr;
@@ -1103,11 +1109,25 @@ __global__ __launch_bounds__(NT) void chain_back_kernel(ChainParams p, int ch, c
   PhaseClock clk;
   solve_Y(side, d, cs.k, side ? cs.rhoC : cs.rhoB, meta + 2 + side * KMAX,
           scr + (side ? OFF_LC : OFF_LB), scr, lds);
-  build_F_and_delta(cs, side, d, scr, lds);
+  build_F_and_delta(cs, side, d, scr, lds, ch);
   clk.tick(p.stats, 4);
   mul_PF(d, Pc + side * d * d, scr + (side ? OFF_FV : OFF_FU), Pn + side * d * d, lds);
   clk.tick(p.stats, 5);
-  const int bad = lu_solve_scatter(d, Pn + side * d * d, scr + (side ? OFF_DV : OFF_DU),
+}
+
+// Step 3's row update of chunk ch, M_b[rows] += dM P_new^-1 (and the same
+// signal change into R), on its own stream beside the next chunk's Steps
+// 1-2.  Reads only P_new of this chunk, its row corrections (parity buffer)
+// and its row lists, none of which the next chunk overwrites; a next chunk
+// that reads any of its rows waits for it (launch_chain).
+__global__ __launch_bounds__(NT) void chain_scatter_kernel(ChainParams p, int ch, const double *Pn) {
+  __shared__ __align__(16) double lds[LDS_DOUBLES];
+  __shared__ __align__(16) int ilds[1024];
+  const int side = blockIdx.x;
+  const int d = p.d;
+  ChunkState cs = chunk_state(p, ch, nullptr);
+  PhaseClock clk;
+  const int bad = lu_solve_scatter(d, Pn + side * d * d, p.scr + off_dl(side, ch),
                                    side ? cs.S2 : cs.S1, side ? cs.s2 : cs.s1,
                                    side ? p.Vb : p.Ub, side ? nullptr : p.R, lds, ilds, p.split);
   if (bad && tid() == 0) atomicOr(&p.stats->numeric_error, 1);
@@ -1118,7 +1138,7 @@ __global__ __launch_bounds__(NT) void chain_back_kernel(ChainParams p, int ch, c
 
 size_t chain_scratch_doubles() { return SCRATCH_DOUBLES; }
 
-hipError_t launch_chain(damf_ctx *c, int n_chunks) {
+hipError_t launch_chain(damf_ctx *c, int n_chunks, const uint64_t *meets) {
   if (n_chunks <= 0) return hipSuccess;
   hipStream_t s = c->stream;
   ChainParams p;
@@ -1140,13 +1160,23 @@ hipError_t launch_chain(damf_ctx *c, int n_chunks) {
   p.stats = c->ws.cstats;
   p.split = c->split;
   DAMF_HIP(hipMemsetAsync(c->ws.cstats, 0, sizeof(ChainStats), s));
-  // the projections alternate between P and Pnext from chunk to chunk
-  double *Pc = c->P, *Pn = c->Pnext;
+  // The projections alternate between P and Pnext from chunk to chunk.  The
+  // solve-and-scatter of chunk ch runs on stream t after chunk ch's back and
+  // beside chunk ch + 1; stream s waits for it before the front of chunk
+  // ch + 1 when that chunk's S1 or S2 meets chunk ch's (the front reads those
+  // rows of U_b, V_b), and always before the front of chunk ch + 2 (whose
+  // back reuses chunk ch's P buffer and row-correction parity).  The result
+  // is the same as with every step in one stream.
+  hipStream_t t = c->scatter_stream;
+  double *Pbuf[2] = {c->P, c->Pnext};
   // with kernel timing, a pair of events brackets each core launch
   const bool timed = c->cfg.kernel_timing != 0;
   c->core_timed = 0;
   for (int ch = 0; ch < n_chunks; ++ch) {
-    chain_front_kernel<<<2, NT, 0, s>>>(p, ch, Pc);
+    if (ch >= 2) DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(ch - 2) & 3], 0));
+    if (ch >= 1 && ((meets[ch >> 6] >> (ch & 63)) & 1))
+      DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(ch - 1) & 3], 0));
+    chain_front_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[ch & 1]);
     const bool tm = timed && ch < damf_ctx::kCoreTimed;
     if (tm) DAMF_HIP(hipEventRecord(c->ev_core[2 * ch], s));
     chain_core_kernel<<<1, NT, 0, s>>>(p, ch);
@@ -1154,12 +1184,15 @@ hipError_t launch_chain(damf_ctx *c, int n_chunks) {
       DAMF_HIP(hipEventRecord(c->ev_core[2 * ch + 1], s));
       c->core_timed = ch + 1;
     }
-    chain_back_kernel<<<2, NT, 0, s>>>(p, ch, Pc, Pn);
-    double *t = Pc;
-    Pc = Pn;
-    Pn = t;
+    chain_back_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[ch & 1], Pbuf[(ch + 1) & 1]);
+    DAMF_HIP(hipEventRecord(c->ev_back[ch & 3], s));
+    DAMF_HIP(hipStreamWaitEvent(t, c->ev_back[ch & 3], 0));
+    chain_scatter_kernel<<<2, NT, 0, t>>>(p, ch, Pbuf[(ch + 1) & 1]);
+    DAMF_HIP(hipEventRecord(c->ev_scatter[ch & 3], t));
   }
+  DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(n_chunks - 1) & 3], 0));
   DAMF_HIP(hipGetLastError());
+  double *Pc = Pbuf[n_chunks & 1];
   if (Pc != c->P)
     DAMF_HIP(hipMemcpyAsync(c->P, Pc, 2 * (size_t)c->d * c->d * sizeof(double),
                             hipMemcpyDeviceToDevice, s));

@@ -61,6 +61,8 @@ struct BatchHeader {
   int32_t max_s;          // largest |S1| or |S2|
   int32_t pool_overflow;  // CSR rows that found no pool space (set by edits)
   int32_t s1_total;       // entries of all chunks' S1 lists
+  // bit j: chunk j's S1 meets chunk j-1's S1, or its S2 meets chunk j-1's S2
+  uint64_t meets_prev[kMaxBatch / 64];
 };
 
 // Per-chunk results written by the chain kernel (for batch info).
@@ -146,6 +148,10 @@ struct damf_ctx {
   static constexpr int kCoreTimed = 256;  // core-SVD launches timed per batch
   hipEvent_t ev_core[2 * kCoreTimed] = {};  // created only with cfg.kernel_timing
   int core_timed = 0;                       // launches timed by the last chain
+  // Step 3's solve-and-scatter runs on scatter_stream, beside the next
+  // chunk's core; ev_front / ev_scatter order the two streams (rings of 4)
+  hipStream_t scatter_stream = nullptr;
+  hipEvent_t ev_back[4] = {}, ev_scatter[4] = {};
   damf_init_info init_info{};
   double push_ms = 0.0, push_bytes = 0.0;  // accumulated by ppr_push
   double wall_khz = 100000.0;               // device wall-clock rate (kHz)
@@ -195,7 +201,7 @@ hipError_t launch_csr_edit(damf_ctx *c, Csr &g, const NetEntry *net,
                            int nrows, bool transposed);
 
 // ---- chain.hip
-hipError_t launch_chain(damf_ctx *c, int n_chunks);
+hipError_t launch_chain(damf_ctx *c, int n_chunks, const uint64_t *meets);
 
 // ---- ppr.hip
 hipError_t ppr_init(damf_ctx *c);

@@ -606,6 +606,18 @@ __device__ void bitonic_u32(uint32_t *a, int P) {
 // units are chunked on their own (a chunk never spans two requests), and the
 // graph edits use the net change of the whole batch.  With one segment this
 // is the plain batch.
+__device__ void set_header(BatchHeader *h, int bad, int ne, int nchunks, int rows_out,
+                           int rows_in, int maxs, int s1tot) {
+  h->bad_ops = bad;
+  h->n_net = ne;
+  h->n_chunks = nchunks;
+  h->n_rows_out = rows_out;
+  h->n_rows_in = rows_in;
+  h->max_s = maxs;
+  h->pool_overflow = 0;
+  h->s1_total = s1tot;
+}
+
 __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams p) {
   __shared__ __align__(16) unsigned char lds[kPrepLdsBytes];
   __shared__ int wbuf[16];
@@ -659,11 +671,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
   }
   __syncthreads();
   if (s_bad > 0) {
-    if (threadIdx.x == 0) {
-      BatchHeader h{};
-      h.bad_ops = s_bad;
-      *p.hdr = h;
-    }
+    if (threadIdx.x == 0) set_header(p.hdr, s_bad, 0, 0, 0, 0, 0, 0);
     return;
   }
   // sort (key, idx) pairs; equal keys keep batch order through idx
@@ -902,17 +910,29 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
     }
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    BatchHeader h{};
-    h.bad_ops = 0;
-    h.n_net = ne;
-    h.n_chunks = s_nchunks;
-    h.n_rows_out = n_rows_out;
-    h.n_rows_in = n_rows_in;
-    h.max_s = s_maxs;
-    h.s1_total = s_s1tot;
-    *p.hdr = h;
+  // ---- phase 5: chunks whose S1 meets the previous chunk's S1, or whose S2
+  // meets its S2 (both lists sorted): Step 1 of such a chunk reads rows that
+  // the previous chunk's Step 3 writes, so the host orders the two
+  __shared__ unsigned long long s_meets[kMaxBatch / 64];
+  for (int i = threadIdx.x; i < kMaxBatch / 64; i += kPrepThreads) s_meets[i] = 0ull;
+  __syncthreads();
+  auto meet = [](const int32_t *a, int na, const int32_t *b, int nb) {
+    for (int i = 0; i < nb; ++i) {
+      const int64_t q = lower_bound(a, (int64_t)na, b[i]);
+      if (q < na && a[q] == b[i]) return true;
+    }
+    return false;
+  };
+  for (int j = 1 + threadIdx.x; j < s_nchunks; j += kPrepThreads) {
+    const ChunkDesc a = p.chunks[j - 1], b = p.chunks[j];
+    if (meet(p.chunk_s1 + a.s1_off, a.s1, p.chunk_s1 + b.s1_off, b.s1) ||
+        meet(p.chunk_s2 + a.s2_off, a.s2, p.chunk_s2 + b.s2_off, b.s2))
+      atomicOr(&s_meets[j >> 6], 1ull << (j & 63));
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i < kMaxBatch / 64; i += kPrepThreads) p.hdr->meets_prev[i] = s_meets[i];
+  if (threadIdx.x == 0)
+    set_header(p.hdr, 0, ne, s_nchunks, n_rows_out, n_rows_in, s_maxs, s_s1tot);
 }
 
 hipError_t launch_batch_prepare(damf_ctx *c, int k, int nseg) {
