@@ -90,6 +90,39 @@ def test_small_update_parity(damf):
     ctx.close()
 
 
+@pytest.mark.parametrize("shared", [True, False])
+def test_chunk_order_across_streams(damf, shared):
+    """Step 3's solve-and-scatter of a chunk runs on a second stream beside the
+    next chunk.  shared: every chunk of a batch has the same source row, so each
+    front must wait for the previous scatter; else consecutive chunks touch
+    disjoint rows and overlap.  Both must match the oracle chunk for chunk."""
+    _say(f"case chunk_order shared={shared}")
+    rng = np.random.default_rng(9)
+    n, d, k = 200, 8, 40
+    s0, t0 = rng.integers(0, n, 1500), rng.integers(0, n, 1500)
+    orc = DAMFOracle(n, d, True, alpha=1.0, r=4, r_max=4, tau=1e-6).init_exact(s0, t0)
+    ctx = _ctx_from_oracle(damf, orc, (s0, t0))
+    for b in range(6):
+        if shared:
+            s = np.full(k, b, dtype=np.int64)
+            t = rng.choice(n, k, replace=False)
+        else:
+            nodes = rng.permutation(n)[: 2 * k]
+            s, t = nodes[:k], nodes[k:]
+        op = np.ones(k, dtype=np.int8)
+        orc.update(s, t, op)
+        info = ctx.update(s, t, op)
+        sg = ctx.singular_values()
+        X, Y = ctx.query("X"), ctx.query("Y")
+        err_s = np.max(np.abs(sg - orc.s)) / orc.s[0]
+        err_p = product_rel_err(X, Y, orc.X(), orc.Y())
+        _say(f"  batch {b}: chunks {info['chunks']} sigma err {err_s:.2e} product err {err_p:.2e}")
+        assert info["chunks"] >= 8
+        assert err_s <= 1e-5 and err_p <= 1e-5
+    _assert_csr(ctx, orc)
+    ctx.close()
+
+
 def test_c1_parity(damf):
     """C1: undirected G(2000, 20000), d = 32, exact init on 90%, 200 batches of 10 inserts."""
     _say("case c1_parity")
