@@ -10,7 +10,7 @@ say).  ``ppr_series`` evaluates the series by its partial sums until the tail
 is below 1e-15 relative; it is the definition the tests compare against.
 
 The paper delegates the dynamic maintenance to InstantGNN, which is not
-reproduced here.  ``PushState`` is the residual-push scheme that this build
+reproduced here.  ``PushState`` is the residual-push scheme that the library
 uses, derived from the definition alone: with Pi = alpha (I - (1-alpha) P)^-1
 (P = D^-1 A) it keeps the invariant  PPR(X) = Z + Pi R.  Pushing node v
 moves alpha R[v] into Z[v] and (1 - alpha) A[u, v] / deg(u) R[v] into R[u] for
