@@ -553,7 +553,7 @@ def main():
         "chain_steps_1_3": {
             "bound": "alu", "unit": "TFLOP/s", "achieved": chain_tf,
             "peak": FP64_CU_PEAK_TFLOPS, "frac": chain_tf / FP64_CU_PEAK_TFLOPS,
-            "scope": "all Steps 1-3 launches of a batch (front, core, back per chunk) as one span",
+            "scope": "all Steps 1-3 launches of a batch (front, core, back, scatter per chunk) as one span",
             "ms_per_batch": chain_ms / max(n_chain, 1), "batches": n_chain,
             "flops_per_batch": chain_flops / max(n_chain, 1),
         },
