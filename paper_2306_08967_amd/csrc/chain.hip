@@ -1,11 +1,11 @@
 // chain.hip -- Steps 1-3 of the update (Sec. 4.5; Theorem 2; Algorithm 1,
-// UpdateEmbeddingE) for every chunk of a batch, in one workgroup.
+// UpdateEmbeddingE) for every chunk of a batch.
 //
 // Chunks depend on each other through Sigma and the projections, so they run
-// one after another inside a single 512-thread workgroup that keeps the
-// small dense state in LDS / L2 and the core matrix in VGPRs.  For a chunk
-// with rows S1, columns S2 and dA = I[:,S1] D I[:,S2]^T the kernel computes,
-// in the U-form (U = U_b P_U, V = V_b P_V):
+// one after another; each step of a chunk is a kernel of one or two 512-thread
+// workgroups that keep the small dense state in LDS / L2 and the core matrix
+// in VGPRs.  For a chunk with rows S1, columns S2 and dA = I[:,S1] D I[:,S2]^T
+// the kernels compute, in the U-form (U = U_b P_U, V = V_b P_V):
 //
 //   Step 1  W_B = U^T B, W_C = V^T C  (gather of the touched rows, Lemma 2)
 //           residual Grams G = B^T B - W^T W (Proposition 1 for k columns),
@@ -982,12 +982,13 @@ __device__ __forceinline__ int lu_solve_scatter(int d, const double *Pn, const d
   return 0;
 }
 
-// A chunk runs as three kernels in stream order.  front (one workgroup per
-// side): Step 1 -- gather/project the touched rows, the residual Gram and its
-// pivoted Cholesky factor.  core (one workgroup): Step 2 -- the core SVD and
-// Sigma <- Theta.  back (one workgroup per side): Step 3 -- Y, F and the row
-// corrections, P <- P F, and the LU solve and scatter into the base rows.
-// The two sides of front and back are independent and run on two CUs.
+// A chunk runs as four kernels.  front (one workgroup per side): Step 1 --
+// gather/project the touched rows, the residual Gram and its pivoted Cholesky
+// factor.  core (one workgroup): Step 2 -- the core SVD and Sigma <- Theta.
+// back (one workgroup per side): Step 3 -- Y, F and the row corrections,
+// P <- P F.  scatter (one workgroup per side, second stream): the LU solve and
+// scatter into the base rows.  The two sides of front, back and scatter are
+// independent and run on two CUs each.
 
 __device__ __forceinline__ ChunkState chunk_state(const ChainParams &p, int ch, const int *meta) {
   const ChunkDesc desc = p.chunks[ch];

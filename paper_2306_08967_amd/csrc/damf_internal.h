@@ -65,7 +65,7 @@ struct BatchHeader {
   uint64_t meets_prev[kMaxBatch / 64];
 };
 
-// Per-chunk results written by the chain kernel (for batch info).
+// Per-chunk results written by the chain kernels (for batch info).
 struct ChainStats {
   int32_t max_core;
   int32_t dropped;
@@ -110,7 +110,7 @@ struct Workspace {
   BatchHeader *hdr_host = nullptr;  // pinned
   ChainStats *cstats = nullptr;
   ChainStats *cstats_host = nullptr;
-  // chain kernel scratch (float64, L2 resident)
+  // chain kernels' scratch (float64, L2 resident)
   double *scratch = nullptr;
   size_t scratch_doubles = 0;
   // PPR push
@@ -138,7 +138,7 @@ struct damf_ctx {
   damf::Csr out, in;
   float *Ub = nullptr, *Vb = nullptr, *Zb = nullptr, *R = nullptr;
   double *P = nullptr;     // [P_U | P_V] (2 d x d, row-major)
-  double *Pnext = nullptr; // double buffer for the chain kernel
+  double *Pnext = nullptr; // double buffer for the chain kernels
   double *sigma = nullptr; // d
   damf::Workspace ws;
   int64_t round_counter = 0;
