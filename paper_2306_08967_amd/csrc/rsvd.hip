@@ -13,6 +13,7 @@
 // rotation GEMM on MFMA (FP32 in, FP32 accumulate).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cfloat>
 #include <cmath>
 #include <cstring>
@@ -380,27 +381,29 @@ constexpr int GK = 16;
 
 typedef float v4f __attribute__((ext_vector_type(4)));
 
-// C (n x d) = A (n x l) B (l x d), d <= 128.  C may be A itself (lda == ldc):
+// C (n x d) = A (n x l) B (l x d), d <= 16 TL.  C may be A itself (lda == ldc):
 // each workgroup owns whole rows and has read all of them before it writes.
+template <int TL>
 __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t n, int l, int lda,
                                                         const float *__restrict__ B, int d,
                                                         float *C, int ldc) {
+  constexpr int BW = 16 * TL;
   __shared__ float As[GM][GK + 1];
-  __shared__ float Bs[GK][128 + 4];
+  __shared__ float Bs[GK][BW + 4];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
   const int64_t row0 = (int64_t)blockIdx.x * GM;
-  v4f acc[8];
+  v4f acc[TL];
 #pragma unroll
-  for (int t = 0; t < 8; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+  for (int t = 0; t < TL; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
   for (int k0 = 0; k0 < l; k0 += GK) {
     for (int e = threadIdx.x; e < GM * GK; e += 256) {
       const int i = e / GK, k = e - i * GK;
       const int64_t r = row0 + i;
       As[i][k] = (r < n && k0 + k < l) ? A[r * lda + k0 + k] : 0.f;
     }
-    for (int e = threadIdx.x; e < GK * 128; e += 256) {
-      const int k = e >> 7, j = e & 127;
+    for (int e = threadIdx.x; e < GK * BW; e += 256) {
+      const int k = e / BW, j = e - k * BW;
       Bs[k][j] = (k0 + k < l && j < d) ? B[(k0 + k) * d + j] : 0.f;
     }
     __syncthreads();
@@ -408,7 +411,7 @@ __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t 
     for (int kk = 0; kk < GK; kk += 4) {
       const float a = As[w * 16 + (lane & 15)][kk + (lane >> 4)];
 #pragma unroll
-      for (int t = 0; t < 8; ++t) {
+      for (int t = 0; t < TL; ++t) {
         const float b = Bs[kk + (lane >> 4)][t * 16 + (lane & 15)];
         acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
       }
@@ -416,7 +419,7 @@ __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t 
     __syncthreads();
   }
 #pragma unroll
-  for (int t = 0; t < 8; ++t) {
+  for (int t = 0; t < TL; ++t) {
     const int j = t * 16 + (lane & 15);
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
@@ -424,6 +427,145 @@ __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t 
       if (r < n && j < d) C[r * ldc + j] = acc[t][q];
     }
   }
+}
+
+// ---------------------------------------------------------------- CholeskyQR2
+// Tall-skinny QR of Y (m x l, l <= 192) as two CholeskyQR passes: the Gram
+// G = Y^T Y in FP64 (one read of Y), G = R^T R by Cholesky in FP64, then
+// Y <- Y R^-1 on FP32 MFMA in place (one read and write); the second pass
+// restores the orthogonality the first loses to FP32 rounding, and the R
+// factor is R2 R1.  A first Gram whose pivots fall below 1e-10 of its largest
+// diagonal (Y numerically rank deficient, or cond(Y) above ~1e5) sends the
+// QR to the Householder TSQR above instead.
+
+constexpr int LM = kMaxCore;     // widest sketch, d + p <= 192
+constexpr int kCqrParts = 256;   // workgroups of a Gram pass
+constexpr double kCqrPivot = 1e-10;
+
+// Partial Grams: workgroup b sums its share of the rows into part[b] (LM x
+// LM).  Thread (ti, tj) of a 16 x 32 grid owns rows 12 ti .. + 12 and
+// columns 6 tj .. + 6.
+__global__ __launch_bounds__(512) void cqr_gram_kernel(const float *Y, int64_t m, int l, int ld,
+                                                       double *part) {
+  __shared__ float tile[64][LM + 4];
+  const int ti = threadIdx.x >> 5, tj = threadIdx.x & 31;
+  const bool active = 12 * ti < l && 6 * tj < l;
+  double acc[12][6];
+#pragma unroll
+  for (int i = 0; i < 12; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) acc[i][j] = 0.0;
+  const int64_t per = (m + gridDim.x - 1) / gridDim.x;
+  const int64_t r0 = (int64_t)blockIdx.x * per;
+  const int64_t r1 = min<int64_t>(m, r0 + per);
+  for (int64_t base = r0; base < r1; base += 64) {
+    for (int e = threadIdx.x; e < 64 * LM; e += 512) {
+      const int rr = e / LM, c = e - rr * LM;
+      const int64_t r = base + rr;
+      tile[rr][c] = (r < r1 && c < l) ? Y[r * ld + c] : 0.f;
+    }
+    __syncthreads();
+    if (active) {
+      for (int rr = 0; rr < 64; ++rr) {
+        double a[12], b[6];
+#pragma unroll
+        for (int i = 0; i < 12; ++i) a[i] = (double)tile[rr][12 * ti + i];
+#pragma unroll
+        for (int j = 0; j < 6; ++j) b[j] = (double)tile[rr][6 * tj + j];
+#pragma unroll
+        for (int i = 0; i < 12; ++i)
+#pragma unroll
+          for (int j = 0; j < 6; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      }
+    }
+    __syncthreads();
+  }
+  double *out = part + (size_t)blockIdx.x * LM * LM;
+#pragma unroll
+  for (int i = 0; i < 12; ++i)
+#pragma unroll
+    for (int j = 0; j < 6; ++j) out[(12 * ti + i) * LM + 6 * tj + j] = acc[i][j];
+}
+
+// G[i][j] = sum over the parts (i, j < l), row stride LM.
+__global__ void cqr_reduce_kernel(const double *part, int nparts, int l, double *G) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= l * l) return;
+  const int i = e / l, j = e - i * l;
+  double s = 0.0;
+  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * LM * LM + i * LM + j];
+  G[i * LM + j] = s;
+}
+
+// One workgroup: G = R^T R (right-looking, upper R in G's upper triangle,
+// FP64), then Rinv = R^-1 (upper) written as FP32 l x l row-major for the
+// MFMA product, R kept in FP64 (stride LM).  *bad = 1 on a pivot below
+// kCqrPivot times the largest diagonal entry (or not finite).
+__global__ __launch_bounds__(1024) void cqr_chol_kernel(double *G, int l, double *R, float *Rinv,
+                                                        int *bad) {
+  __shared__ double dmax;
+  __shared__ int s_bad;
+  if (threadIdx.x == 0) {
+    double mx = 0.0;
+    for (int i = 0; i < l; ++i) mx = fmax(mx, G[i * LM + i]);
+    dmax = mx;
+    s_bad = 0;
+  }
+  __syncthreads();
+  for (int j = 0; j < l; ++j) {
+    const double piv = G[j * LM + j];
+    if (!(piv > kCqrPivot * dmax)) {
+      if (threadIdx.x == 0) s_bad = 1;
+      break;  // uniform: every thread read the same pivot
+    }
+    const double rjj = sqrt(piv), inv = 1.0 / rjj;
+    __syncthreads();
+    for (int c = j + threadIdx.x; c < l; c += 1024) G[j * LM + c] = (c == j) ? rjj : G[j * LM + c] * inv;
+    __syncthreads();
+    // trailing update of the upper triangle: G[i][c] -= R[j][i] R[j][c], j < i <= c
+    const int t = l - j - 1;
+    for (int e = threadIdx.x; e < t * t; e += 1024) {
+      const int i = j + 1 + e / t, c = j + 1 + e % t;
+      if (c >= i) G[i * LM + c] = fma(-G[j * LM + i], G[j * LM + c], G[i * LM + c]);
+    }
+    __syncthreads();
+  }
+  __syncthreads();
+  if (s_bad) {
+    if (threadIdx.x == 0) *bad = 1;
+    return;
+  }
+  // R (upper, zeros below) and its inverse, one column per thread
+  for (int e = threadIdx.x; e < l * l; e += 1024) {
+    const int i = e / l, c = e - i * l;
+    R[i * LM + c] = (c >= i) ? G[i * LM + c] : 0.0;
+  }
+  __syncthreads();
+  // X = R^-1 by columns, one thread per column c, in G's space (row c of G
+  // holds column c of X): X[c][c] = 1 / R[c][c],
+  // X[i][c] = -(sum_{k=i+1..c} R[i][k] X[k][c]) / R[i][i] for i < c
+  for (int c = threadIdx.x; c < l; c += 1024) {
+    double *x = G + c * LM;
+    for (int i = 0; i < l; ++i) x[i] = 0.0;
+    x[c] = 1.0 / R[c * LM + c];
+    for (int i = c - 1; i >= 0; --i) {
+      double sacc = 0.0;
+      for (int k = i + 1; k <= c; ++k) sacc = fma(R[i * LM + k], x[k], sacc);
+      x[i] = -sacc / R[i * LM + i];
+    }
+    for (int i = 0; i < l; ++i) Rinv[i * l + c] = (float)x[i];
+  }
+  if (threadIdx.x == 0) *bad = 0;
+}
+
+// Rtop (FP32, l x l row-major) = R2 R1 (both upper, FP64, stride LM).
+__global__ void cqr_rprod_kernel(const double *R2, const double *R1, int l, float *Rtop) {
+  const int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= l * l) return;
+  const int i = e / l, c = e - i * l;
+  double s = 0.0;
+  for (int k = i; k <= c; ++k) s = fma(R2[i * LM + k], R1[k * LM + c], s);
+  Rtop[e] = (c >= i) ? (float)s : 0.f;
 }
 
 __global__ void encode_kernel(float *M, int64_t count) {
@@ -500,9 +642,62 @@ hipError_t tsqr(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) 
 
 hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B, int d, float *C,
                      int ldc, hipStream_t s) {
-  gemm_tall_kernel<<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+  if (d <= 128)
+    gemm_tall_kernel<8><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+  else if (d <= 192)
+    gemm_tall_kernel<12><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+  else
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
+
+namespace {
+
+// CholeskyQR2 of Y in place (Rtop = R2 R1); the Householder TSQR when the
+// first Gram is not clearly positive definite.
+hipError_t tall_qr(float *Y, int64_t m, int l, int ld, float *Rtop, hipStream_t s) {
+  if (l > LM) return hipErrorInvalidValue;
+  const int nparts = (int)std::min<int64_t>(kCqrParts, (m + 63) / 64);
+  double *part = nullptr, *G = nullptr, *R1 = nullptr, *R2 = nullptr;
+  float *Rinv = nullptr;
+  int *bad = nullptr;
+  int hbad = 0;
+  hipError_t err = hipSuccess;
+  auto pass = [&](double *R) -> hipError_t {
+    cqr_gram_kernel<<<nparts, 512, 0, s>>>(Y, m, l, ld, part);
+    cqr_reduce_kernel<<<ceil_div((int64_t)l * l, 256), 256, 0, s>>>(part, nparts, l, G);
+    cqr_chol_kernel<<<1, 1024, 0, s>>>(G, l, R, Rinv, bad);
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || hbad) return e;
+    return gemm_tall(Y, m, l, ld, Rinv, l, Y, ld, s);
+  };
+  if ((err = hipMalloc(&part, (size_t)nparts * LM * LM * sizeof(double))) == hipSuccess &&
+      (err = hipMalloc(&G, (size_t)LM * LM * sizeof(double))) == hipSuccess &&
+      (err = hipMalloc(&R1, (size_t)LM * LM * sizeof(double))) == hipSuccess &&
+      (err = hipMalloc(&R2, (size_t)LM * LM * sizeof(double))) == hipSuccess &&
+      (err = hipMalloc(&Rinv, (size_t)l * l * sizeof(float))) == hipSuccess &&
+      (err = hipMalloc(&bad, sizeof(int))) == hipSuccess) {
+    err = pass(R1);
+    if (err == hipSuccess && hbad) {
+      err = tsqr(Y, m, l, ld, Rtop, s);  // Y untouched by the failed pass
+    } else if (err == hipSuccess) {
+      err = pass(R2);
+      if (err == hipSuccess && hbad) err = hipErrorInvalidValue;  // Q1 not finite
+      if (err == hipSuccess) {
+        cqr_rprod_kernel<<<ceil_div((int64_t)l * l, 256), 256, 0, s>>>(R2, R1, l, Rtop);
+        err = hipGetLastError();
+      }
+    }
+  }
+  (void)hipStreamSynchronize(s);
+  for (void *q : {(void *)part, (void *)G, (void *)R1, (void *)R2, (void *)Rinv, (void *)bad})
+    if (q) (void)hipFree(q);
+  return err;
+}
+
+}  // namespace
 
 hipError_t tsqr_public(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) {
   return tsqr(A, m, l, ld, Rtop, s);
@@ -530,18 +725,18 @@ hipError_t rsvd_init(damf_ctx *c) {
   DAMF_HIP(spmm_plan_build(c, c->out, ld, &pout));
   DAMF_HIP(spmm_plan_build(c, c->in, ld, &pin));
   DAMF_HIP(csr_spmm(c->out, pout, T, Y, n, l, ld, s));  // Y = A Omega
-  DAMF_HIP(tsqr(Y, n, l, ld, Rt, s));
+  DAMF_HIP(tall_qr(Y, n, l, ld, Rt, s));
   for (int it = 0; it < c->cfg.power_iters; ++it) {
     DAMF_HIP(csr_spmm(c->in, pin, Y, T, n, l, ld, s));  // A^T Q
-    DAMF_HIP(tsqr(T, n, l, ld, Rt, s));
+    DAMF_HIP(tall_qr(T, n, l, ld, Rt, s));
     DAMF_HIP(csr_spmm(c->out, pout, T, Y, n, l, ld, s));  // A Q
-    DAMF_HIP(tsqr(Y, n, l, ld, Rt, s));
+    DAMF_HIP(tall_qr(Y, n, l, ld, Rt, s));
   }
   DAMF_HIP(csr_spmm(c->in, pin, Y, T, n, l, ld, s));  // B^T = A^T Q
   DAMF_HIP(hipStreamSynchronize(s));
   spmm_plan_free(pout);
   spmm_plan_free(pin);
-  DAMF_HIP(tsqr(T, n, l, ld, Rt, s));        // T = Q2, Rt = R2
+  DAMF_HIP(tall_qr(T, n, l, ld, Rt, s));     // T = Q2, Rt = R2
   small_svd_kernel<<<1, 1024, 0, s>>>(Rt, l, d, E, th, H);
   DAMF_HIP(hipGetLastError());
   to_float_kernel<<<ceil_div((int64_t)l * d, 256), 256, 0, s>>>(E, Ef, (int64_t)l * d);
