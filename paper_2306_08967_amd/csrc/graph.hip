@@ -848,9 +848,22 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
       s1v = s2v = -1;
       cur_units = 0;
     };
+    // the units arrive 64 at a time, one per lane, and are read lane by lane
+    // (a global load per unit would put its latency on every step)
+    uint64_t win_uk = 0ull;
+    int win_sg = 0;
+    int acc_seg = -1, acc_cnt = 0;  // lane 0: the current segment's entry count
     for (int t = 0; t < n_units; ++t) {
-      uint64_t uk = p.units[t];
-      const int sg = p.unit_seg[t];
+      if ((t & 63) == 0) {
+        const int q = t + lane;
+        win_uk = (q < n_units) ? p.units[q] : 0ull;
+        win_sg = (q < n_units) ? p.unit_seg[q] : 0;
+      }
+      const int at = t & 63;
+      const uint32_t ulo = __builtin_amdgcn_readlane((uint32_t)win_uk, at);
+      const uint32_t uhi = __builtin_amdgcn_readlane((uint32_t)(win_uk >> 32), at);
+      const uint64_t uk = ((uint64_t)uhi << 32) | ulo;
+      const int sg = __builtin_amdgcn_readlane(win_sg, at);
       int32_t u = (int32_t)(uk >> 33), v = (int32_t)((uk >> 1) & 0x7fffffffu);
       int ins = (int)(uk & 1u);
       bool pair = !p.directed && u != v;
@@ -897,12 +910,20 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
           en.col = u;
           p.chunk_ent[e_start + e_cnt + 1] = en;
         }
-        p.seg_stats[2 * sg] += pair ? 2 : 1;
+        // entries per segment, flushed when the segment changes (units come
+        // in segment order)
+        if (sg != acc_seg) {
+          if (acc_seg >= 0) p.seg_stats[2 * acc_seg] += acc_cnt;
+          acc_seg = sg;
+          acc_cnt = 0;
+        }
+        acc_cnt += pair ? 2 : 1;
       }
       e_cnt += pair ? 2 : 1;
       ++cur_units;
     }
     if (cur_units > 0) close();
+    if (lane == 0 && acc_seg >= 0) p.seg_stats[2 * acc_seg] += acc_cnt;
     if (lane == 0) {
       s_nchunks = nchunks;
       s_maxs = maxs;
