@@ -141,9 +141,19 @@ def cpu_baseline(w, batches, d, r):
     }
 
 
+def hashed_subset(keys, m, seed):
+    """The first m of the distinct int64 keys in the order of a seeded multiplicative hash:
+    an odd multiplier is a bijection mod 2^64, so the order has no ties and is the same in
+    every process (a stand-in for a random subset in random order)."""
+    import torch
+    h = keys * -7046029254386353131 + (seed * 6364136223846793005) % (1 << 62)
+    return keys[torch.argsort(h, stable=True)[:m]]
+
+
 def rmat_edges_gpu(n, m, seed, a=0.57, b=0.19, c=0.19):
     """R-MAT edge set drawn on the GPU (torch): scale ceil(log2 n), ids >= n, self-loops and
-    duplicates dropped and redrawn until m distinct edges remain, then shuffled."""
+    duplicates dropped and redrawn until m distinct edges remain, then m of them kept in hashed
+    order (the same edge set in every process)."""
     import math
 
     import torch
@@ -167,7 +177,7 @@ def rmat_edges_gpu(n, m, seed, a=0.57, b=0.19, c=0.19):
         del s, t, ok
         keys = torch.unique(torch.cat([keys, k]))
         del k
-    keys = keys[torch.randperm(keys.numel(), generator=g, device="cuda")[:m]]
+    keys = hashed_subset(keys, m, seed)
     return (keys >> 32).to(torch.int32), (keys & 0xFFFFFFFF).to(torch.int32)
 
 
@@ -332,24 +342,34 @@ def chung_lu_edges_gpu(n, m, beta, seed):
     """Directed Chung-Lu edge set drawn on the GPU (torch): weights (i + i0)^(-1/(beta-1))
     with i0 set so the largest expected degree is sqrt(m), independently permuted out- and
     in-labels, self-loops and duplicates dropped and redrawn until m distinct edges remain,
-    then shuffled.  Returns (src, dst) int32 device tensors and the sampler's pieces."""
+    then m of them kept in hashed order (the same edge set in every process).  Returns (src,
+    dst) int32 device tensors and the sampler's pieces."""
     import torch
     g = torch.Generator(device="cuda")
     g.manual_seed(seed)
+    from scipy.special import digamma, zeta
     gamma = 1.0 / (beta - 1.0)
-    idx = torch.arange(n, dtype=torch.float64, device="cuda")
+
+    def wsum(x):  # sum_{i<n} (i + x)^-gamma in closed form (Hurwitz zeta; digamma at gamma = 1)
+        if gamma == 1.0:
+            return float(digamma(x + n) - digamma(x))
+        if gamma > 1.0:
+            return float(zeta(gamma, x) - zeta(gamma, x + n))
+        return float(np.sum((np.arange(n, dtype=np.float64) + x) ** (-gamma)))
+
     lo, hi, target = 1e-3, float(n), m ** 0.5
     for _ in range(100):
         mid = (lo * hi) ** 0.5
-        w = (idx + mid) ** (-gamma)
-        if m * float(w[0]) / float(w.sum()) > target:
+        if m * mid ** (-gamma) / wsum(mid) > target:
             lo = mid
         else:
             hi = mid
-    w = (idx + hi) ** (-gamma)
-    cdf = torch.cumsum(w / w.sum(), 0)
-    cdf[-1] = 1.0
-    del w, idx
+    # the CDF on the host in FP64 (the same bits in every process), then to the GPU
+    w = (np.arange(n, dtype=np.float64) + hi) ** (-gamma)
+    cdf_h = np.cumsum(w / w.sum())
+    cdf_h[-1] = 1.0
+    cdf = torch.from_numpy(cdf_h).cuda()
+    del w, cdf_h
     perm_out = torch.randperm(n, generator=g, device="cuda")
     perm_in = torch.randperm(n, generator=g, device="cuda")
 
@@ -374,7 +394,7 @@ def chung_lu_edges_gpu(n, m, beta, seed):
             del s, t, ok
         keys = torch.unique(torch.cat([keys] + parts))
         del parts
-    keys = keys[torch.randperm(keys.numel(), generator=g, device="cuda")[:m]]
+    keys = hashed_subset(keys, m, seed)
     src = (keys // n).to(torch.int32)
     dst = (keys % n).to(torch.int32)
     del keys
