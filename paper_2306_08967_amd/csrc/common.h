@@ -23,12 +23,6 @@ __device__ __forceinline__ float wave_max(float v) {
 // NaN becomes +inf, so a non-finite residual shows up as an infinite maximum.
 __device__ __forceinline__ float nan_to_inf(float a) { return (a == a) ? a : INFINITY; }
 
-__device__ __forceinline__ int wave_sum_i(int v) {
-#pragma unroll
-  for (int off = 32; off >= 1; off >>= 1) v += __shfl_xor(v, off, 64);
-  return v;
-}
-
 // Lower bound in a sorted int32 array (global or LDS).
 template <typename T>
 __device__ __forceinline__ int64_t lower_bound(const T *a, int64_t n, T x) {

@@ -233,8 +233,6 @@ hipError_t ppr_pull_round(const Csr &g, const SpmmPlan &p, const float *Rold, fl
 hipError_t rsvd_init(damf_ctx *c);
 hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B,
                      int d, float *C, int ldc, hipStream_t s);
-hipError_t tsqr_public(float *A, int64_t m, int l, int ld, float *Rtop,
-                       hipStream_t s);
 
 // ---- reorth.hip
 hipError_t flush_projections(damf_ctx *c);

@@ -699,10 +699,6 @@ hipError_t tall_qr(float *Y, int64_t m, int l, int ld, float *Rtop, hipStream_t 
 
 }  // namespace
 
-hipError_t tsqr_public(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) {
-  return tsqr(A, m, l, ld, Rtop, s);
-}
-
 hipError_t rsvd_init(damf_ctx *c) {
   hipStream_t s = c->stream;
   const int64_t n = c->n;
