@@ -139,7 +139,8 @@ void damf_config_default(damf_config *cfg);
  * builds the graph, takes the randomized rank-d t-SVD of A (sketch
  * Omega[i,j] = +/-1 from SplitMix64, Q = qr(A Omega), q rounds of
  * Q = qr(A^T Q), Q = qr(A Q), then B^T = A^T Q = Q2 R2 and svd(R2^T)), sets
- * the projections to the identity and propagates PPR until max |R| <= eps.
+ * the projections to the identity and propagates PPR until max |R| <= eps / 2
+ * (headroom for the first updates' pushes).
  * src/dst: m edges (duplicates collapse; self-loops are entries).
  * Errors: DAMF_E_INVALID_ARG (n outside 1..2^30, d out of range, m < 0, null arrays with
  * m > 0), DAMF_E_OUT_OF_RANGE (id outside [0,n)), DAMF_E_OOM, DAMF_E_NUMERIC

@@ -329,7 +329,10 @@ hipError_t ppr_init(damf_ctx *c) {
       c->nonfinite = true;
       break;
     }
-    if (!((double)mx > c->cfg.eps)) break;
+    // to eps / 2: a synchronous round lowers every residual together, so
+    // stopping at eps would leave many nodes just under it, and the first
+    // update's push would cascade through them
+    if (!((double)mx > 0.5 * c->cfg.eps)) break;
     DAMF_HIP(hipMemsetAsync(maxbits, 0, sizeof(unsigned), s));
     DAMF_HIP(hipEventRecord(c->ev_k[0], s));
     DAMF_HIP(ppr_pull_round(c->out, plan, Rcur, Rnxt, c->Zb, n, d, alpha, maxbits, s));

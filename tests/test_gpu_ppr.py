@@ -61,6 +61,7 @@ def test_ppr_initial_propagation(damf):
     _say("case ppr_init")
     orc, ctx = _make(damf, 400, 3000, 8, 0.15, 1e-6, seed=21)
     _check_z(ctx, orc, 1e-6)
+    assert ctx.residual_max() <= 0.5e-6  # the start propagates to eps / 2
     ctx.close()
 
 
