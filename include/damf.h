@@ -243,6 +243,21 @@ damf_status damf_residual_max(damf_ctx *ctx, double *out);
 /* Wait for all work of the context. */
 damf_status damf_sync(damf_ctx *ctx);
 
+/* Checkpoint (not part of the paper's method; it lets a long-running
+ * context stop and resume).  damf_save writes the whole state to `path`: the
+ * graph as the canonical out-CSR, P_U, P_V, Sigma, U_b, V_b (as stored, FP32
+ * or BF16 pairs) and, with PPR, Z_b and R, plus the re-orthogonalisation and
+ * push counters; host byte order, streamed through a 64 MiB pinned buffer.
+ * damf_load creates a context from such a file: cfg supplies the run-time
+ * options (stream, eps, chunk ranks, ...) and must agree with the file on n,
+ * d, directed, precision and alpha (else DAMF_E_INVALID_ARG).  The loaded
+ * context rebuilds its CSR pools compactly; every later result equals the
+ * saved context's bit for bit, except where float atomics of Step 4 order
+ * differently.  Errors: DAMF_E_INVALID_ARG (path, mismatch, short or corrupt
+ * file), DAMF_E_STATE (save of a poisoned context), DAMF_E_OOM, DAMF_E_DEVICE. */
+damf_status damf_save(damf_ctx *ctx, const char *path);
+damf_status damf_load(const char *path, const damf_config *cfg, damf_ctx **out);
+
 void damf_destroy(damf_ctx *ctx);
 
 const char *damf_last_error(const damf_ctx *ctx);

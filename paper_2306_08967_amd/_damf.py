@@ -201,6 +201,8 @@ def lib():
     L.damf_residual_max.argtypes = [p, C.POINTER(C.c_double)]
     L.damf_get_init_info.argtypes = [p, C.POINTER(DamfInitInfo)]
     L.damf_sync.argtypes = [p]
+    L.damf_save.argtypes = [p, C.c_char_p]
+    L.damf_load.argtypes = [C.c_char_p, C.POINTER(DamfConfig), C.POINTER(C.c_void_p)]
     L.damf_destroy.argtypes = [p]
     L.damf_destroy.restype = None
     L.damf_last_error.argtypes = [p]
@@ -210,7 +212,7 @@ def lib():
     for name in ("damf_init", "damf_init_factors", "damf_update", "damf_enhance", "damf_flush",
                  "damf_reorthogonalize", "damf_query",
                  "damf_singular_values", "damf_export_csr", "damf_export_state",
-                 "damf_residual_max", "damf_sync", "damf_get_init_info"):
+                 "damf_residual_max", "damf_sync", "damf_get_init_info", "damf_save", "damf_load"):
         getattr(L, name).restype = C.c_int
     del i32p
     _lib = L
@@ -381,6 +383,20 @@ class Context:
 
     def sync(self):
         self._check(lib().damf_sync(self._h))
+
+    def save(self, path):
+        """Write the whole state to `path` (damf_save)."""
+        self._check(lib().damf_save(self._h, os.fsencode(path)))
+
+    @classmethod
+    def load(cls, path, cfg):
+        """A context from a damf_save file; cfg must match its n, d, directed,
+        precision and alpha."""
+        h = C.c_void_p()
+        st = lib().damf_load(os.fsencode(path), C.byref(cfg), C.byref(h))
+        if st != DAMF_OK:
+            raise DamfError(st, lib().damf_status_string(st).decode())
+        return Context(h, cfg)
 
     def close(self):
         if self._h:

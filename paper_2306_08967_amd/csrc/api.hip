@@ -751,6 +751,154 @@ damf_status damf_sync(damf_ctx *c) {
   return DAMF_OK;
 }
 
+// ---- checkpoint: the whole state of a context in one file
+//
+// Layout (host byte order): CkptHeader; out-CSR indptr (n + 1 int64) and
+// indices (m int32), canonical; P (2 d d FP64); Sigma (kMaxCore FP64);
+// U_b, V_b (n d 32-bit words each, as stored: FP32 or BF16 pairs); with PPR,
+// Z_b and R (n d FP32 each).  Matrices stream through a pinned buffer.
+
+namespace {
+
+struct CkptHeader {
+  char magic[8];
+  int64_t version, n, m, batches_since_reorth, round_counter;
+  int32_t d, directed, precision, ppr_on;
+  double alpha;
+};
+constexpr char kCkptMagic[8] = {'D', 'A', 'M', 'F', 'C', 'K', 'P', '1'};
+constexpr size_t kCkptChunk = size_t(64) << 20;  // bytes per staged copy
+
+// Device <-> file in chunks through one pinned buffer.
+hipError_t stream_out(FILE *f, const void *dev, size_t bytes, void *pin, hipStream_t s, bool *io_ok) {
+  for (size_t off = 0; off < bytes; off += kCkptChunk) {
+    const size_t len = std::min(kCkptChunk, bytes - off);
+    hipError_t e = hipMemcpyAsync(pin, (const char *)dev + off, len, hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+    if (std::fwrite(pin, 1, len, f) != len) {
+      *io_ok = false;
+      return hipSuccess;
+    }
+  }
+  return hipSuccess;
+}
+hipError_t stream_in(FILE *f, void *dev, size_t bytes, void *pin, hipStream_t s, bool *io_ok) {
+  for (size_t off = 0; off < bytes; off += kCkptChunk) {
+    const size_t len = std::min(kCkptChunk, bytes - off);
+    if (std::fread(pin, 1, len, f) != len) {
+      *io_ok = false;
+      return hipSuccess;
+    }
+    hipError_t e = hipMemcpyAsync((char *)dev + off, pin, len, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+}  // namespace
+
+damf_status damf_save(damf_ctx *c, const char *path) {
+  if (!c || !path) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  const int64_t n = c->n;
+  const int d = c->d;
+  int64_t m = 0;
+  API_HIP(c, csr_export(c, c->out, nullptr, nullptr, &m), "checkpoint CSR");
+  std::vector<int64_t> indptr(n + 1);
+  std::vector<int32_t> indices(m > 0 ? m : 1);
+  API_HIP(c, csr_export(c, c->out, indptr.data(), indices.data(), &m), "checkpoint CSR");
+  FILE *f = std::fopen(path, "wb");
+  if (!f) return fail(c, DAMF_E_INVALID_ARG, "cannot open the checkpoint file for writing");
+  CkptHeader h{};
+  std::memcpy(h.magic, kCkptMagic, 8);
+  h.version = 1;
+  h.n = n;
+  h.m = m;
+  h.batches_since_reorth = c->batches_since_reorth;
+  h.round_counter = c->round_counter;
+  h.d = d;
+  h.directed = c->cfg.directed;
+  h.precision = c->split ? 1 : 0;
+  h.ppr_on = c->ppr_on ? 1 : 0;
+  h.alpha = c->cfg.alpha;
+  bool io = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
+            std::fwrite(indptr.data(), sizeof(int64_t), n + 1, f) == (size_t)(n + 1) &&
+            (m == 0 || std::fwrite(indices.data(), sizeof(int32_t), m, f) == (size_t)m);
+  void *pin = nullptr;
+  hipError_t e = io ? hipHostMalloc(&pin, kCkptChunk) : hipSuccess;
+  const size_t nd = (size_t)n * d * sizeof(float);
+  if (io && e == hipSuccess) e = stream_out(f, c->P, 2 * (size_t)d * d * sizeof(double), pin, c->stream, &io);
+  if (io && e == hipSuccess) e = stream_out(f, c->sigma, kMaxCore * sizeof(double), pin, c->stream, &io);
+  if (io && e == hipSuccess) e = stream_out(f, c->Ub, nd, pin, c->stream, &io);
+  if (io && e == hipSuccess) e = stream_out(f, c->Vb, nd, pin, c->stream, &io);
+  if (c->ppr_on && io && e == hipSuccess) e = stream_out(f, c->Zb, nd, pin, c->stream, &io);
+  if (c->ppr_on && io && e == hipSuccess) e = stream_out(f, c->R, nd, pin, c->stream, &io);
+  if (pin) (void)hipHostFree(pin);
+  io = (std::fclose(f) == 0) && io;
+  if (e != hipSuccess) return dev_fail(c, e, "checkpoint");
+  if (!io) return fail(c, DAMF_E_INVALID_ARG, "checkpoint file write failed");
+  return DAMF_OK;
+}
+
+damf_status damf_load(const char *path, const damf_config *cfg, damf_ctx **out) {
+  if (!path || !cfg || !out) return DAMF_E_INVALID_ARG;
+  *out = nullptr;
+  FILE *f = std::fopen(path, "rb");
+  if (!f) return DAMF_E_INVALID_ARG;
+  CkptHeader h{};
+  const bool hdr_ok = std::fread(&h, sizeof(h), 1, f) == 1 &&
+                      std::memcmp(h.magic, kCkptMagic, 8) == 0 && h.version == 1;
+  const bool ppr_on = cfg->alpha < 1.0;
+  if (!hdr_ok || h.n != cfg->n || h.d != cfg->d || h.directed != cfg->directed ||
+      h.precision != cfg->precision || h.ppr_on != (ppr_on ? 1 : 0) ||
+      (ppr_on && h.alpha != cfg->alpha) || h.m < 0) {
+    std::fclose(f);
+    return DAMF_E_INVALID_ARG;
+  }
+  damf_ctx *c = nullptr;
+  damf_status st = new_ctx(cfg, out, &c);
+  if (st != DAMF_OK) {
+    std::fclose(f);
+    return st;
+  }
+  const int64_t n = h.n, m = h.m;
+  std::vector<int64_t> indptr(n + 1);
+  std::vector<int32_t> dst(m > 0 ? m : 1), src(m > 0 ? m : 1);
+  bool io = std::fread(indptr.data(), sizeof(int64_t), n + 1, f) == (size_t)(n + 1) &&
+            (m == 0 || std::fread(dst.data(), sizeof(int32_t), m, f) == (size_t)m) &&
+            indptr[0] == 0 && indptr[n] == m;
+  for (int64_t u = 0; io && u < n; ++u) {
+    if (indptr[u + 1] < indptr[u]) io = false;
+    for (int64_t e = indptr[u]; io && e < indptr[u + 1]; ++e) src[e] = (int32_t)u;
+  }
+  if (!io || (st = alloc_state(c)) != DAMF_OK || (st = build_graph(c, m, src.data(), dst.data(), 0)) != DAMF_OK) {
+    std::fclose(f);
+    free_ctx(c);
+    return io ? st : DAMF_E_INVALID_ARG;
+  }
+  void *pin = nullptr;
+  hipError_t e = hipHostMalloc(&pin, kCkptChunk);
+  const size_t nd = (size_t)n * h.d * sizeof(float);
+  if (e == hipSuccess) e = stream_in(f, c->P, 2 * (size_t)h.d * h.d * sizeof(double), pin, c->stream, &io);
+  if (io && e == hipSuccess) e = stream_in(f, c->sigma, kMaxCore * sizeof(double), pin, c->stream, &io);
+  if (io && e == hipSuccess) e = stream_in(f, c->Ub, nd, pin, c->stream, &io);
+  if (io && e == hipSuccess) e = stream_in(f, c->Vb, nd, pin, c->stream, &io);
+  if (ppr_on && io && e == hipSuccess) e = stream_in(f, c->Zb, nd, pin, c->stream, &io);
+  if (ppr_on && io && e == hipSuccess) e = stream_in(f, c->R, nd, pin, c->stream, &io);
+  if (pin) (void)hipHostFree(pin);
+  std::fclose(f);
+  if (e != hipSuccess || !io) {
+    free_ctx(c);
+    return e != hipSuccess ? DAMF_E_DEVICE : DAMF_E_INVALID_ARG;
+  }
+  c->batches_since_reorth = h.batches_since_reorth;
+  c->round_counter = h.round_counter;
+  *out = c;
+  return DAMF_OK;
+}
+
 void damf_destroy(damf_ctx *c) { free_ctx(c); }
 
 }  // extern "C"
