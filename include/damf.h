@@ -216,7 +216,9 @@ damf_status damf_reorthogonalize(damf_ctx *ctx);
 
 /* Rows of X, Y or Z for q nodes (nodes == NULL: all n rows, q must be n):
  * out is q x d row-major float32.  Row of X = U_b[u] P_U Sigma^(1/2)
- * (Sec. 4.6, O(d^2) per query). */
+ * (Sec. 4.6, O(d^2) per query).  A Z query after batches applied without
+ * Step 4 (auto_enhance = 0) runs damf_enhance first, so Z is within eps of
+ * PPR(X) for the current state. */
 damf_status damf_query(damf_ctx *ctx, damf_which which, int64_t q,
                        const int32_t *nodes, float *out, int32_t flags);
 

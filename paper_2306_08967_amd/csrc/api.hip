@@ -426,6 +426,8 @@ damf_status update_impl(damf_ctx *c, int64_t k, const int32_t *src, const int32_
     int64_t nrows = 0;
     if ((st = step_push_rows(c, h, nseg, &nrows)) != DAMF_OK) return st;
     API_HIP(c, ppr_push(c, s, c->ws.pend_rows, nrows, &rounds, &pushes, &edges), "PPR push");
+  } else if (c->ppr_on) {
+    c->enhance_pending = true;  // the next Z query or damf_enhance pushes from every node
   }
   API_HIP(c, hipEventRecord(c->ev[3], s), "event");
   if ((st = step_finish(c, h)) != DAMF_OK) return st;
@@ -619,6 +621,7 @@ damf_status damf_enhance(damf_ctx *c) {
   int64_t r, p, e;
   API_HIP(c, ppr_push(c, c->stream, nullptr, 0, &r, &p, &e), "PPR push");
   API_HIP(c, hipStreamSynchronize(c->stream), "PPR push");
+  c->enhance_pending = false;
   return DAMF_OK;
 }
 
@@ -649,6 +652,10 @@ damf_status damf_query(damf_ctx *c, damf_which which, int64_t q, const int32_t *
   const int d = c->d;
   hipStream_t s = c->stream;
   if (which == DAMF_Z && !c->ppr_on) which = DAMF_X;  // alpha = 1: Z = X
+  if (which == DAMF_Z && c->enhance_pending) {          // Z within eps of PPR(X) when read
+    const damf_status st = damf_enhance(c);
+    if (st != DAMF_OK) return st;
+  }
   const int32_t *dn = nodes;
   float *dout = out;
   int32_t *own_n = nullptr;
@@ -763,7 +770,7 @@ namespace {
 struct CkptHeader {
   char magic[8];
   int64_t version, n, m, batches_since_reorth, round_counter;
-  int32_t d, directed, precision, ppr_on;
+  int32_t d, directed, precision, ppr_on, enhance_pending, pad;
   double alpha;
 };
 constexpr char kCkptMagic[8] = {'D', 'A', 'M', 'F', 'C', 'K', 'P', '1'};
@@ -822,6 +829,7 @@ damf_status damf_save(damf_ctx *c, const char *path) {
   h.directed = c->cfg.directed;
   h.precision = c->split ? 1 : 0;
   h.ppr_on = c->ppr_on ? 1 : 0;
+  h.enhance_pending = c->enhance_pending ? 1 : 0;
   h.alpha = c->cfg.alpha;
   bool io = std::fwrite(&h, sizeof(h), 1, f) == 1 &&
             std::fwrite(indptr.data(), sizeof(int64_t), n + 1, f) == (size_t)(n + 1) &&
@@ -895,6 +903,7 @@ damf_status damf_load(const char *path, const damf_config *cfg, damf_ctx **out) 
   }
   c->batches_since_reorth = h.batches_since_reorth;
   c->round_counter = h.round_counter;
+  c->enhance_pending = h.enhance_pending != 0;
   *out = c;
   return DAMF_OK;
 }

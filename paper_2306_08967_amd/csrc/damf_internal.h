@@ -134,6 +134,7 @@ struct damf_ctx {
   int device = 0;
   bool poisoned = false;
   bool nonfinite = false;  // a residual maximum came out NaN or infinite
+  bool enhance_pending = false;  // batches ran without Step 4 since the last push
   std::string err;
   damf::Csr out, in;
   float *Ub = nullptr, *Vb = nullptr, *Zb = nullptr, *R = nullptr;

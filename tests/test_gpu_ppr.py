@@ -81,6 +81,29 @@ def test_ppr_dynamic_push(damf):
     ctx.close()
 
 
+def test_z_query_runs_pending_enhance(damf):
+    """With auto_enhance = 0 the batches leave Step 4 pending; a Z query runs it first,
+    so Z matches the oracle's PPR(X) as with auto_enhance = 1."""
+    _say("case ppr_pending")
+    n, eps = 400, 1e-6
+    s0, t0 = chung_lu_directed(n, 3000, 2.1, 24)
+    orc = DAMFOracle(n, 8, True, alpha=0.15, eps=eps, r=8, r_max=16, tau=1e-6).init_exact(s0, t0)
+    cfg = damf.default_config(n, 8, directed=True, alpha=0.15, eps=eps, max_core_rank=8,
+                              max_side=16, tau=1e-6, auto_enhance=0)
+    ctx = damf.Context.init_factors(cfg, s0, t0, orc.U, orc.s, orc.V)
+    rng = np.random.default_rng(10)
+    for b in range(6):
+        k = 30
+        s, t = rng.integers(0, n, k), rng.integers(0, n, k)
+        op = rng.choice(np.array([-1, 1, 1], dtype=np.int8), k)
+        orc.update(s, t, op)
+        info = ctx.update(s, t, op)
+        assert info["push_rounds"] == 0
+    assert ctx.residual_max() > eps  # Step 4 still pending
+    _check_z(ctx, orc, eps)          # the Z query inside runs it
+    ctx.close()
+
+
 def test_ppr_invariant_property(damf):
     """X - R == (Z_b - (1 - alpha) P Z_b) / alpha on the GPU's own state (any size)."""
     _say("case ppr_invariant")
