@@ -81,10 +81,11 @@ def parse():
                     help="1: the precision form (bases as BF16 pairs, BF16 MFMA rotations)")
     ap.add_argument("--mode", choices=("update", "serve"), default="update",
                     help="update: batches through damf_update (default); serve: the server")
-    ap.add_argument("--workload", choices=("c2", "billion"), default="c2",
-                    help="c2 (default): Chung-Lu 2.1, n=1e6, m=1e7, batches of 1000 ops; billion: "
-                         "Chung-Lu 2.0, n=4e7, m=1e9, precision form, batches of 100 inserts, "
-                         "eps=1e-6 (generated on the GPU)")
+    ap.add_argument("--workload", choices=("c2", "c3", "billion"), default="c2",
+                    help="c2 (default): Chung-Lu 2.1, n=1e6, m=1e7, batches of 1000 ops; c3: "
+                         "Chung-Lu 2.1, n=4e6, m=6e7, precision form, batches of 5000 ops, "
+                         "re-orthogonalisation every 64; billion: Chung-Lu 2.0, n=4e7, m=1e9, "
+                         "precision form, batches of 100 inserts, eps=1e-6 (both generated on the GPU)")
     ap.add_argument("--serve-n", type=int, default=10_000_000)
     ap.add_argument("--serve-m", type=int, default=200_000_000)
     ap.add_argument("--serve-requests", type=int, default=6000)
@@ -139,6 +140,25 @@ def cpu_baseline(w, batches, d, r):
                    "seeded orthonormal factors of the same shape (its cost does not depend on their "
                    "values); the oracle's Step 4 is a full PPR series recomputation and is not timed"),
     }
+
+
+def sample_agreement(a_xyz, r_xyz):
+    """Rotation-free comparison of two factorizations on the same row sample: the relative
+    Frobenius error of X Y^T (through d x d Grams) and the sine of the largest principal
+    angle between the column spaces of X (and of Y)."""
+    Xa, Ya = a_xyz
+    Xr, Yr = r_xyz
+    t1 = np.trace((Xa.T @ Xa) @ (Ya.T @ Ya))
+    t2 = np.trace((Xa.T @ Xr) @ (Yr.T @ Ya))
+    t3 = np.trace((Xr.T @ Xr) @ (Yr.T @ Yr))
+    prod = float(np.sqrt(max(t1 - 2 * t2 + t3, 0.0)) / np.sqrt(t3))
+
+    def sin_max(A, B):
+        qa, _ = np.linalg.qr(A)
+        qb, _ = np.linalg.qr(B)
+        return float(np.linalg.norm(qb - qa @ (qa.T @ qb), 2))  # ||(I - Qa Qa^T) Qb||_2
+
+    return {"product_rel_fro_err": prod, "subspace_sin_max": {"X": sin_max(Xa, Xr), "Y": sin_max(Ya, Yr)}}
 
 
 def hashed_subset(keys, m, seed):
@@ -472,6 +492,106 @@ def billion_main(args):
     print(json.dumps(out))
 
 
+def c3_main(args):
+    """Precision form at its own size: directed Chung-Lu 2.1, n = 4e6, m = 6e7, d = 128,
+    batches of 5,000 edits (95% inserts from the same sampler, 5% deletes of initial edges),
+    FP64 re-orthogonalisation every 64 batches; then the FP32 form replays the same stream
+    (untimed) for the accuracy report on a 1% row sample."""
+    import torch
+
+    from paper_2306_08967_amd import Context, default_config
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    n, m, d, K, W, bs = 4_000_000, 60_000_000, 128, args.steps, args.warmup, 5000
+    t0 = time.perf_counter()
+    src, dst, draw = chung_lu_edges_gpu(n, m, 2.1, args.seed)
+    g = torch.Generator(device="cuda")
+    g.manual_seed(args.seed + 1)
+    n_del = bs // 20
+    batches = []
+    for _ in range(W + K):
+        s, t = draw(bs - n_del)
+        j = torch.randint(0, m, (n_del,), generator=g, device="cuda")
+        s = torch.cat([s.to(torch.int32), src[j]])
+        t = torch.cat([t.to(torch.int32), dst[j]])
+        op = torch.cat([torch.ones(bs - n_del, dtype=torch.int8, device="cuda"),
+                        torch.full((n_del,), -1, dtype=torch.int8, device="cuda")])
+        perm = torch.randperm(bs, generator=g, device="cuda")
+        batches.append((s[perm].contiguous(), t[perm].contiguous(), op[perm].contiguous()))
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    log(f"c3 workload: n={n} m={m} on the GPU in {time.perf_counter() - t0:.1f}s; "
+        f"{W + K} batches of {bs} ops")
+
+    def config(precision):
+        return default_config(n, d, directed=True, alpha=0.15, eps=1e-5, oversample=10,
+                              power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64,
+                              precision=precision, reorth_every=64, kernel_timing=1)
+
+    t0 = time.perf_counter()
+    ctx = Context.init(config(1), src, dst)
+    torch.cuda.synchronize()
+    init_s = time.perf_counter() - t0
+    for b in range(W):
+        ctx.update(*batches[b])
+    torch.cuda.synchronize()
+    lat, infos = [], []
+    t_start = time.perf_counter()
+    for b in range(W, W + K):
+        t = time.perf_counter()
+        infos.append(ctx.update(*batches[b]))
+        lat.append(time.perf_counter() - t)
+        if (b - W) % 20 == 19:
+            log(f"step {b - W + 1}/{K}: last {lat[-1] * 1e3:.1f} ms")
+    torch.cuda.synchronize()
+    T = time.perf_counter() - t_start
+    value = K * bs / T
+
+    def mean(key):
+        return float(np.mean([i[key] for i in infos]))
+
+    log("fp32 reference replay for the accuracy report ...")
+    ref = Context.init(config(0), src, dst)
+    for b in range(W + K):
+        ref.update(*batches[b])
+    rng = np.random.default_rng(0)
+    rows = torch.from_numpy(np.sort(rng.choice(n, n // 100, replace=False)).astype(np.int32)).cuda()
+    err, got = {}, {}
+    for which in ("X", "Y", "Z"):
+        a = ctx.query(which, rows, torch.empty((len(rows), d), device="cuda")).double().cpu().numpy()
+        r = ref.query(which, rows, torch.empty((len(rows), d), device="cuda")).double().cpu().numpy()
+        got[which] = (a, r)
+        sign = np.sign((a * r).sum(axis=0))
+        sign[sign == 0] = 1.0
+        err[which] = float(np.linalg.norm(a * sign - r) / np.linalg.norm(r))
+    s_a, s_r = ctx.singular_values(), ref.singular_values()
+    accuracy = {"vs": "FP32 form on the same stream", "row_sample": int(len(rows)),
+                "sigma_max_rel_err": float(np.max(np.abs(s_a - s_r)) / s_r[0]),
+                "rows_rel_fro_err": err,
+                **sample_agreement((got["X"][0], got["Y"][0]), (got["X"][1], got["Y"][1]))}
+    out = {
+        "metric": "edge-updates/s", "value": value, "unit": "edge-updates/s", "n_gpus": 1,
+        "steps": K, "warmup": W, "ms_per_step": T / K * 1e3, "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "bf16x2", "data": "synthetic",
+        "config": {"workload": "chung-lu-2.1 n=4e6 m=6e7 d=128 batch=5000 (95% ins / 5% del), "
+                               "alpha=0.15 eps=1e-5, precision form, re-orthogonalisation every 64",
+                   "n": n, "m": m, "d": d, "batch": bs},
+        "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
+                       "mean": float(np.mean(lat)) * 1e3},
+        "init_s": init_s,
+        "stage_ms_mean": {k: mean(k) for k in ("ms_prepare", "ms_chain", "ms_enhance", "ms_reorth",
+                                               "ms_core_kernel", "ms_push_kernel")},
+        "per_batch_mean": {k: mean(k) for k in ("net_entries", "chunks", "sweeps", "push_rounds",
+                                                "pushes")},
+        "accuracy": accuracy,
+        "residual_max": ctx.residual_max(),
+        "cpu_baseline": None,
+    }
+    ref.close()
+    ctx.close()
+    print(json.dumps(out))
+
+
 def copy_calibration(mib):
     """A plain device-to-device copy of known size, for scaling PMC byte counters."""
     import torch
@@ -491,11 +611,11 @@ def main():
     if args.copy_calibration:
         copy_calibration(args.copy_calibration)
         return
-    if args.workload == "billion":
+    if args.workload in ("billion", "c3"):
         if args.gpus != 1:
             print("bench.py runs on one GPU only", file=sys.stderr)
             sys.exit(2)
-        billion_main(args)
+        (billion_main if args.workload == "billion" else c3_main)(args)
         return
     if args.mode == "serve":
         if args.gpus != 1:
@@ -607,17 +727,19 @@ def main():
             ref.update(*batches[b])
         rng = np.random.default_rng(0)
         rows = torch.from_numpy(np.sort(rng.choice(n, max(1, n // 100), replace=False)).astype(np.int32)).cuda()
-        out = {}
+        out, got = {}, {}
         for which in ("X", "Y", "Z"):
             a = ctx.query(which, rows, torch.empty((len(rows), d), device="cuda")).double().cpu().numpy()
             r = ref.query(which, rows, torch.empty((len(rows), d), device="cuda")).double().cpu().numpy()
+            got[which] = (a, r)
             sign = np.sign((a * r).sum(axis=0))
             sign[sign == 0] = 1.0
             out[which] = float(np.linalg.norm(a * sign - r) / np.linalg.norm(r))
         s_a, s_r = ctx.singular_values(), ref.singular_values()
         accuracy = {"vs": "FP32 form on the same stream", "row_sample": int(len(rows)),
                     "sigma_max_rel_err": float(np.max(np.abs(s_a - s_r)) / s_r[0]),
-                    "rows_rel_fro_err": out}
+                    "rows_rel_fro_err": out,
+                    **sample_agreement((got["X"][0], got["Y"][0]), (got["X"][1], got["Y"][1]))}
         ref.close()
     del src, dst
     line = {

@@ -413,6 +413,7 @@ damf_status update_impl(damf_ctx *c, int64_t k, const int32_t *src, const int32_
     API_HIP(c, hipEventRecord(c->ev[6], s), "event");
     int bad = 0;
     API_HIP(c, reorthogonalize(c, &bad), "re-orthogonalisation");
+    c->enhance_pending = c->enhance_pending || c->ppr_on;  // R was rotated: every row may exceed eps
     API_HIP(c, hipEventRecord(c->ev[7], s), "event");
     API_HIP(c, hipEventSynchronize(c->ev[7]), "event");
     ms_reorth = ms_between(c->ev[6], c->ev[7]);
@@ -423,9 +424,14 @@ damf_status update_impl(damf_ctx *c, int64_t k, const int32_t *src, const int32_
   c->push_ms = 0.0;
   c->push_bytes = 0.0;
   if (c->ppr_on && c->cfg.auto_enhance) {
+    // from this batch's rows, or from every node when R changed elsewhere
+    // (a re-orthogonalisation or flush rotates every row of R)
     int64_t nrows = 0;
     if ((st = step_push_rows(c, h, nseg, &nrows)) != DAMF_OK) return st;
-    API_HIP(c, ppr_push(c, s, c->ws.pend_rows, nrows, &rounds, &pushes, &edges), "PPR push");
+    const bool all = c->enhance_pending;
+    API_HIP(c, ppr_push(c, s, all ? nullptr : c->ws.pend_rows, all ? 0 : nrows, &rounds, &pushes, &edges),
+            "PPR push");
+    c->enhance_pending = false;
   } else if (c->ppr_on) {
     c->enhance_pending = true;  // the next Z query or damf_enhance pushes from every node
   }
@@ -629,6 +635,7 @@ damf_status damf_flush(damf_ctx *c) {
   if (!c) return DAMF_E_INVALID_ARG;
   if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
   API_HIP(c, flush_projections(c), "flush");
+  c->enhance_pending = c->enhance_pending || c->ppr_on;  // R rotated
   return DAMF_OK;
 }
 
@@ -639,6 +646,7 @@ damf_status damf_reorthogonalize(damf_ctx *c) {
   API_HIP(c, reorthogonalize(c, &bad), "re-orthogonalisation");
   if (bad) return fail(c, DAMF_E_NUMERIC, "re-orthogonalisation refused: basis far from orthonormal");
   c->batches_since_reorth = 0;
+  c->enhance_pending = c->enhance_pending || c->ppr_on;  // R rotated
   return DAMF_OK;
 }
 

@@ -120,8 +120,11 @@ void fail_all(damf_server *s, damf_status st) {
 damf_status run_pending_push(damf_server *s, hipStream_t st, bool beside_chain) {
   int64_t r = 0, p = 0, e = 0;
   const double t = s->now_us();
-  hipError_t err = ppr_push(s->c, st, s->c->ws.pend_rows, s->pending_rows, &r, &p, &e);
+  const bool all = s->c->enhance_pending;  // after a re-orthogonalisation
+  hipError_t err = ppr_push(s->c, st, all ? nullptr : s->c->ws.pend_rows, all ? 0 : s->pending_rows,
+                            &r, &p, &e);
   if (err != hipSuccess) return api_dev_fail(s->c, err, "PPR push");
+  s->c->enhance_pending = false;
   if (beside_chain) {
     std::lock_guard<std::mutex> lk(s->mu);
     s->push_overlap_ms += (s->now_us() - t) * 1e-3;
@@ -192,6 +195,7 @@ void do_step(damf_server *s, std::vector<Req *> &step) {
     int bad = 0;  // a refused re-orthogonalisation leaves the (valid) state as it is
     hipError_t e = reorthogonalize(c, &bad);
     if (e != hipSuccess) st = api_dev_fail(c, e, "re-orthogonalisation");
+    c->enhance_pending = c->enhance_pending || c->ppr_on;  // R rotated: push from every node
   }
   if (st != DAMF_OK) {
     finish_pending(s, c->stream, false);

@@ -160,6 +160,31 @@ def test_reorth_every_keeps_c1_parity(damf):
     ctx.close()
 
 
+def test_reorth_every_keeps_residual_bound(damf):
+    """A re-orthogonalisation rotates every row of R, so the push after it starts
+    from every node: max |R| <= eps after each batch, with one due every 2 batches."""
+    _say("case reorth_residual")
+    n, eps = 800, 1e-5
+    s0, t0 = chung_lu_directed(n, 8000, 2.1, 52)
+    cfg = damf.default_config(n, 16, directed=True, alpha=0.15, eps=eps, oversample=10,
+                              power_iters=2, seed=5, max_core_rank=8, max_side=16,
+                              reorth_every=2)
+    ctx = damf.Context.init(cfg, s0, t0)
+    rng = np.random.default_rng(8)
+    for b in range(6):
+        k = 40
+        s, t = rng.integers(0, n, k), rng.integers(0, n, k)
+        op = rng.choice(np.array([-1, 1, 1], dtype=np.int8), k)
+        info = ctx.update(s, t, op)
+        rmax = ctx.residual_max()
+        _say(f"  batch {b}: reorth {info['ms_reorth'] > 0} pushes {info['pushes']} max|R| {rmax:.2e}")
+        assert rmax <= eps
+    ctx.flush()
+    ctx.query("Z", np.arange(10, dtype=np.int32))  # runs the push the flush left pending
+    assert ctx.residual_max() <= eps
+    ctx.close()
+
+
 def test_reorth_rank_deficient_exact(damf):
     """d >= n: zero singular values get completed basis columns; X Y^T stays A."""
     _say("case reorth_rank_deficient")
