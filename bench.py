@@ -86,6 +86,8 @@ def parse():
                          "Chung-Lu 2.1, n=4e6, m=6e7, precision form, batches of 5000 ops, "
                          "re-orthogonalisation every 64; billion: Chung-Lu 2.0, n=4e7, m=1e9, "
                          "precision form, batches of 100 inserts, eps=1e-6 (both generated on the GPU)")
+    ap.add_argument("--billion-batch", type=int, default=100,
+                    help="insertions per batch of the billion-edge form (1: single-edge updates)")
     ap.add_argument("--serve-n", type=int, default=10_000_000)
     ap.add_argument("--serve-m", type=int, default=200_000_000)
     ap.add_argument("--serve-requests", type=int, default=6000)
@@ -428,7 +430,7 @@ def billion_main(args):
     from paper_2306_08967_amd import Context, default_config
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
-    n, m, d, K, W, bs = 40_000_000, 1_000_000_000, 128, args.steps, args.warmup, 100
+    n, m, d, K, W, bs = 40_000_000, 1_000_000_000, 128, args.steps, args.warmup, args.billion_batch
     t0 = time.perf_counter()
     src, dst, draw = chung_lu_edges_gpu(n, m, 2.0, args.seed)
     batches = []
@@ -477,7 +479,7 @@ def billion_main(args):
         "metric": "edge-updates/s", "value": value, "unit": "edge-updates/s", "n_gpus": 1,
         "steps": K, "warmup": W, "ms_per_step": T / K * 1e3, "higher_is_better": True,
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16x2", "data": "synthetic",
-        "config": {"workload": "chung-lu-2.0 n=4e7 m=1e9 d=128 batch=100 inserts, alpha=0.15 "
+        "config": {"workload": f"chung-lu-2.0 n=4e7 m=1e9 d=128 batch={bs} inserts, alpha=0.15 "
                                "eps=1e-6, precision form", "n": n, "m": m, "d": d, "batch": bs},
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
                        "mean": float(np.mean(lat)) * 1e3},
