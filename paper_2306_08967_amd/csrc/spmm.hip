@@ -26,32 +26,36 @@ template <int NC>
 __device__ __forceinline__ void gather_sum(const int32_t *row, int32_t L, const float *X, int ld,
                                            int k, float (&acc)[NC]) {
   const int lane = threadIdx.x & 63;
-  bool on[NC];
+  // columns past k read column k - 1 of the same row (a valid address) and
+  // count zero, so every gather of a group can be in flight at once
+  int colc[NC];
+  float msk[NC];
 #pragma unroll
   for (int c = 0; c < NC; ++c) {
-    on[c] = lane + 64 * c < k;
+    const int col = lane + 64 * c;
+    colc[c] = min(col, k - 1);
+    msk[c] = (col < k) ? 1.f : 0.f;
     acc[c] = 0.f;
   }
   int32_t e = 0;
   for (; e + 8 <= L; e += 8) {
     int64_t v[8];
 #pragma unroll
-    for (int q = 0; q < 8; ++q) v[q] = (int64_t)row[e + q] * ld + lane;
-#pragma unroll
-    for (int c = 0; c < NC; ++c) {
-      if (on[c]) {
-        float x[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) x[q] = X[v[q] + 64 * c];
-        acc[c] += ((x[0] + x[1]) + (x[2] + x[3])) + ((x[4] + x[5]) + (x[6] + x[7]));
-      }
-    }
-  }
-  for (; e < L; ++e) {
-    const int64_t v = (int64_t)row[e] * ld + lane;
+    for (int q = 0; q < 8; ++q) v[q] = (int64_t)row[e + q] * ld;
+    float x[NC][8];
 #pragma unroll
     for (int c = 0; c < NC; ++c)
-      if (on[c]) acc[c] += X[v + 64 * c];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) x[c][q] = X[v[q] + colc[c]];
+#pragma unroll
+    for (int c = 0; c < NC; ++c)
+      acc[c] += msk[c] * (((x[c][0] + x[c][1]) + (x[c][2] + x[c][3])) +
+                          ((x[c][4] + x[c][5]) + (x[c][6] + x[c][7])));
+  }
+  for (; e < L; ++e) {
+    const int64_t v = (int64_t)row[e] * ld;
+#pragma unroll
+    for (int c = 0; c < NC; ++c) acc[c] += msk[c] * X[v + colc[c]];
   }
 }
 
