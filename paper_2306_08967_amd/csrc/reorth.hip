@@ -330,54 +330,72 @@ typedef float v4f32 __attribute__((ext_vector_type(4)));
 __global__ __launch_bounds__(256) void gemm_split_kernel(float *M, int64_t n, int d,
                                                          const float *B) {
   __shared__ uint32_t As[64][DM + 4];          // row block, as stored (pairs)
-  __shared__ uint32_t Bs[DM][DM + 4];          // B as pairs
+  __shared__ uint32_t Bs[DM][DM + 4];          // B as pairs, encoded once per workgroup
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * 64;
   const int dp = (d + 15) & ~15;  // k and n padded to the 16-wide MFMA
-  for (int e = threadIdx.x; e < 64 * DM; e += 256) {
-    const int i = e / DM, k = e - i * DM;
-    const int64_t r = row0 + i;
-    As[i][k] = (r < n && k < d) ? __float_as_uint(M[r * d + k]) : 0u;
-  }
   for (int e = threadIdx.x; e < DM * DM; e += 256) {
     const int k = e / DM, j = e - k * DM;
     Bs[k][j] = (k < d && j < d) ? split_encode(B[k * d + j]) : 0u;
   }
-  __syncthreads();
-  v4f32 acc[DM / 16];
+  // row blocks of 64 in a grid-stride loop, B resident in LDS; the next
+  // block's rows are loaded into registers while this block's products run
+  constexpr int PER = 64 * DM / 256;
+  uint32_t pre[PER];
+  auto fetch = [&](int64_t r0) {
 #pragma unroll
-  for (int t = 0; t < DM / 16; ++t) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < dp; k0 += 16) {
-    v4s16 ah, al;
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const uint32_t a = As[w * 16 + (lane & 15)][k0 + 4 * (lane >> 4) + j];
-      ah[j] = (short)(a >> 16);
-      al[j] = (short)(a & 0xffffu);
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * 256;
+      const int i = e / DM, k = e - i * DM;
+      const int64_t r = r0 + i;
+      pre[q] = (r < n && k < d) ? __float_as_uint(M[r * d + k]) : 0u;
     }
+  };
+  const int64_t step = (int64_t)gridDim.x * 64;
+  fetch((int64_t)blockIdx.x * 64);
+  for (int64_t row0 = (int64_t)blockIdx.x * 64; row0 < n; row0 += step) {
+    __syncthreads();  // B written / the previous block's As reads done
 #pragma unroll
-    for (int t = 0; t < DM / 16; ++t) {
-      if (t * 16 >= dp) break;
-      v4s16 bh, bl;
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * 256;
+      As[e / DM][e - (e / DM) * DM] = pre[q];
+    }
+    __syncthreads();
+    if (row0 + step < n) fetch(row0 + step);
+    v4f32 acc[DM / 16];
+#pragma unroll
+    for (int t = 0; t < DM / 16; ++t) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < dp; k0 += 16) {
+      v4s16 ah, al;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
-        const uint32_t b = Bs[k0 + 4 * (lane >> 4) + j][t * 16 + (lane & 15)];
-        bh[j] = (short)(b >> 16);
-        bl[j] = (short)(b & 0xffffu);
+        const uint32_t a = As[w * 16 + (lane & 15)][k0 + 4 * (lane >> 4) + j];
+        ah[j] = (short)(a >> 16);
+        al[j] = (short)(a & 0xffffu);
       }
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
-      acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+#pragma unroll
+      for (int t = 0; t < DM / 16; ++t) {
+        if (t * 16 >= dp) break;
+        v4s16 bh, bl;
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const uint32_t b = Bs[k0 + 4 * (lane >> 4) + j][t * 16 + (lane & 15)];
+          bh[j] = (short)(b >> 16);
+          bl[j] = (short)(b & 0xffffu);
+        }
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
+        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+      }
     }
-  }
-  // every row of the block was read into LDS above, so the in-place store is safe
+    // every row of the block was read into LDS above, so the in-place store is safe
 #pragma unroll
-  for (int t = 0; t < DM / 16; ++t) {
-    const int j = t * 16 + (lane & 15);
+    for (int t = 0; t < DM / 16; ++t) {
+      const int j = t * 16 + (lane & 15);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t r = row0 + w * 16 + (lane >> 4) * 4 + q;
-      if (r < n && j < d) M[r * d + j] = __uint_as_float(split_encode(acc[t][q]));
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = row0 + w * 16 + (lane >> 4) * 4 + q;
+        if (r < n && j < d) M[r * d + j] = __uint_as_float(split_encode(acc[t][q]));
+      }
     }
   }
 }
@@ -398,7 +416,7 @@ hipError_t rotate_bases(damf_ctx *c, const float *RotU, const float *RotV) {
   const int64_t n = c->n;
   auto basis = [&](float *M, const float *Rot) -> hipError_t {
     if (c->split) {
-      gemm_split_kernel<<<ceil_div(n, 64), 256, 0, s>>>(M, n, d, Rot);
+      gemm_split_kernel<<<stride_grid(n, 64 * 64), 256, 0, s>>>(M, n, d, Rot);  // 64 row blocks each
       return hipGetLastError();
     }
     return gemm_tall(M, n, d, d, Rot, d, M, d, s);
