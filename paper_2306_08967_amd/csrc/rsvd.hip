@@ -644,6 +644,8 @@ hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B, 
                      int ldc, hipStream_t s) {
   if (d <= 128)
     gemm_tall_kernel<8><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+  else if (d <= 144)  // d + p = 138 at d = 128: nine column tiles, not twelve
+    gemm_tall_kernel<9><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else if (d <= 192)
     gemm_tall_kernel<12><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else
