@@ -324,77 +324,133 @@ __global__ void reset_projection_kernel(double *P, int d, double *sigma, const d
 // Precision form: M <- M B in place for a basis of BF16 pairs (n x d,
 // d <= 128) and FP32 B (d x d), on BF16 MFMA (v_mfma_f32_16x16x16 bf16):
 // with M = Mh + Ml and B = Bh + Bl, M B ~ Mh Bh + Mh Bl + Ml Bh accumulated
-// in FP32, then stored again as pairs.  Each workgroup owns 64 whole rows.
+// in FP32, then stored again as pairs.  The product reads and writes each
+// row once (2 x 4d bytes for 6d flops per element), so it is bound by HBM.
+// Workgroups of NW waves stride over blocks of 64 whole rows.  The waves
+// split the 128 output columns; each keeps the B fragments (hi and lo) of
+// its columns in registers for the whole launch, so LDS holds only the row
+// block (33 KB) and several workgroups share a CU.  Rows are loaded and
+// stored whole through that LDS tile, 16 B per lane when d is a multiple of
+// 4, and the next block is loaded into registers while the current one is
+// multiplied.  With NW = 4 the kernel takes 208 VGPRs (2 waves per SIMD);
+// NW = 8 still takes 178, so it is launched with 4.
 typedef short v4s16 __attribute__((ext_vector_type(4)));
 typedef float v4f32 __attribute__((ext_vector_type(4)));
-__global__ __launch_bounds__(256) void gemm_split_kernel(float *M, int64_t n, int d,
-                                                         const float *B) {
-  __shared__ uint32_t As[64][DM + 4];          // row block, as stored (pairs)
-  __shared__ uint32_t Bs[DM][DM + 4];          // B as pairs, encoded once per workgroup
+template <bool V4, int NW>
+__global__ __launch_bounds__(64 * NW) void gemm_split_kernel(float *M, int64_t n, int d,
+                                                             const float *B) {
+  __shared__ __align__(16) uint32_t As[64][DM + 4];  // row block as pairs; then the result
+  constexpr int KT = DM / 16;
+  constexpr int NT = DM / 16 / NW;   // 16-wide output tiles per wave
+  constexpr int CPW = 16 * NT;       // output columns per wave
+  constexpr int NTH = 64 * NW;
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  const int dp = (d + 15) & ~15;  // k and n padded to the 16-wide MFMA
-  for (int e = threadIdx.x; e < DM * DM; e += 256) {
-    const int k = e / DM, j = e - k * DM;
-    Bs[k][j] = (k < d && j < d) ? split_encode(B[k * d + j]) : 0u;
+  const int dp = (d + 15) & ~15;  // k and output columns padded to the 16-wide MFMA
+  const int nkt = dp >> 4;
+  bool tile_on[NT];
+  v4s16 bh[KT][NT], bl[KT][NT];
+#pragma unroll
+  for (int c = 0; c < NT; ++c) {
+    const int col = CPW * w + 16 * c + (lane & 15);
+    tile_on[c] = CPW * w + 16 * c < dp;
+#pragma unroll
+    for (int kt = 0; kt < KT; ++kt)
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int k = 16 * kt + 4 * (lane >> 4) + j;
+        const uint32_t b = (k < d && col < d) ? split_encode(B[k * d + col]) : 0u;
+        bh[kt][c][j] = (short)(b >> 16);
+        bl[kt][c][j] = (short)(b & 0xffffu);
+      }
   }
-  // row blocks of 64 in a grid-stride loop, B resident in LDS; the next
-  // block's rows are loaded into registers while this block's products run
-  constexpr int PER = 64 * DM / 256;
-  uint32_t pre[PER];
+  // row-block transfers: V4 moves 16 B per lane (d % 4 == 0), else 4 B
+  constexpr int CW = V4 ? 4 : 1;            // words per transfer
+  constexpr int PER = 64 * DM / NTH / CW;   // transfers per thread per block
+  constexpr int RW = DM / CW;               // transfers per row
+  uint4 pre4[V4 ? PER : 1];
+  uint32_t pre1[V4 ? 1 : PER];
   auto fetch = [&](int64_t r0) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * 256;
-      const int i = e / DM, k = e - i * DM;
+      const int e = threadIdx.x + q * NTH;
+      const int i = e / RW, k = (e - i * RW) * CW;
       const int64_t r = r0 + i;
-      pre[q] = (r < n && k < d) ? __float_as_uint(M[r * d + k]) : 0u;
+      const bool in = r < n && k < d;
+      if constexpr (V4) {
+        pre4[q] = in ? *reinterpret_cast<const uint4 *>(M + r * d + k) : uint4{0u, 0u, 0u, 0u};
+      } else {
+        pre1[q] = in ? __float_as_uint(M[r * d + k]) : 0u;
+      }
     }
   };
   const int64_t step = (int64_t)gridDim.x * 64;
   fetch((int64_t)blockIdx.x * 64);
   for (int64_t row0 = (int64_t)blockIdx.x * 64; row0 < n; row0 += step) {
-    __syncthreads();  // B written / the previous block's As reads done
+    __syncthreads();  // the previous block's results have been read out of As
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * 256;
-      As[e / DM][e - (e / DM) * DM] = pre[q];
+      const int e = threadIdx.x + q * NTH;
+      const int i = e / RW, k = (e - i * RW) * CW;
+      if constexpr (V4) {
+        *reinterpret_cast<uint4 *>(&As[i][k]) = pre4[q];
+      } else {
+        As[i][k] = pre1[q];
+      }
     }
     __syncthreads();
     if (row0 + step < n) fetch(row0 + step);
-    v4f32 acc[DM / 16];
+    v4f32 acc[4][NT];
 #pragma unroll
-    for (int t = 0; t < DM / 16; ++t) acc[t] = v4f32{0.f, 0.f, 0.f, 0.f};
-    for (int k0 = 0; k0 < dp; k0 += 16) {
-      v4s16 ah, al;
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const uint32_t a = As[w * 16 + (lane & 15)][k0 + 4 * (lane >> 4) + j];
-        ah[j] = (short)(a >> 16);
-        al[j] = (short)(a & 0xffffu);
-      }
+      for (int c = 0; c < NT; ++c) acc[rt][c] = v4f32{0.f, 0.f, 0.f, 0.f};
 #pragma unroll
-      for (int t = 0; t < DM / 16; ++t) {
-        if (t * 16 >= dp) break;
-        v4s16 bh, bl;
+    for (int kt = 0; kt < KT; ++kt) {
+      if (kt >= nkt) break;
+#pragma unroll
+      for (int rt = 0; rt < 4; ++rt) {
+        const uint4 a = *reinterpret_cast<const uint4 *>(
+            &As[16 * rt + (lane & 15)][16 * kt + 4 * (lane >> 4)]);
+        const uint32_t av[4] = {a.x, a.y, a.z, a.w};
+        v4s16 ah, al;
 #pragma unroll
         for (int j = 0; j < 4; ++j) {
-          const uint32_t b = Bs[k0 + 4 * (lane >> 4) + j][t * 16 + (lane & 15)];
-          bh[j] = (short)(b >> 16);
-          bl[j] = (short)(b & 0xffffu);
+          ah[j] = (short)(av[j] >> 16);
+          al[j] = (short)(av[j] & 0xffffu);
         }
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, acc[t], 0, 0, 0);
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, acc[t], 0, 0, 0);
+#pragma unroll
+        for (int c = 0; c < NT; ++c) {
+          if (!tile_on[c]) continue;
+          acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh[kt][c], acc[rt][c], 0, 0, 0);
+          acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl[kt][c], acc[rt][c], 0, 0, 0);
+          acc[rt][c] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh[kt][c], acc[rt][c], 0, 0, 0);
+        }
       }
     }
-    // every row of the block was read into LDS above, so the in-place store is safe
+    __syncthreads();  // every wave has read the row block
 #pragma unroll
-    for (int t = 0; t < DM / 16; ++t) {
-      const int j = t * 16 + (lane & 15);
+    for (int rt = 0; rt < 4; ++rt)
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t r = row0 + w * 16 + (lane >> 4) * 4 + q;
-        if (r < n && j < d) M[r * d + j] = __uint_as_float(split_encode(acc[t][q]));
+      for (int c = 0; c < NT; ++c) {
+        if (!tile_on[c]) continue;
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          As[16 * rt + 4 * (lane >> 4) + q][CPW * w + 16 * c + (lane & 15)] =
+              split_encode(acc[rt][c][q]);
+      }
+    __syncthreads();
+    // every row of the block was read before the first store, so in place is safe
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * NTH;
+      const int i = e / RW, k = (e - i * RW) * CW;
+      const int64_t r = row0 + i;
+      if (r < n && k < d) {
+        if constexpr (V4) {
+          *reinterpret_cast<uint4 *>(M + r * d + k) = *reinterpret_cast<const uint4 *>(&As[i][k]);
+        } else {
+          M[r * d + k] = __uint_as_float(As[i][k]);
+        }
       }
     }
   }
@@ -416,7 +472,13 @@ hipError_t rotate_bases(damf_ctx *c, const float *RotU, const float *RotV) {
   const int64_t n = c->n;
   auto basis = [&](float *M, const float *Rot) -> hipError_t {
     if (c->split) {
-      gemm_split_kernel<<<stride_grid(n, 64 * 64), 256, 0, s>>>(M, n, d, Rot);  // 64 row blocks each
+      // row blocks of 64, at least 16 per workgroup; 16-B row transfers need
+      // d % 4 == 0 and a 16-B aligned basis
+      const unsigned g = stride_grid(n, 64 * 16);
+      if (d % 4 == 0 && reinterpret_cast<uintptr_t>(M) % 16 == 0)
+        gemm_split_kernel<true, 4><<<g, 256, 0, s>>>(M, n, d, Rot);
+      else
+        gemm_split_kernel<false, 4><<<g, 256, 0, s>>>(M, n, d, Rot);
       return hipGetLastError();
     }
     return gemm_tall(M, n, d, d, Rot, d, M, d, s);

@@ -91,10 +91,12 @@ def test_precision_rsvd_and_ppr_invariant(damf):
     ctx.close()
 
 
-def test_precision_reorth_bf16_mfma(damf):
-    """Re-orthogonalisation rotates the BF16-pair bases with BF16 MFMA (three products)."""
-    _say("case precision_reorth")
-    n, d = 2500, 64
+@pytest.mark.parametrize("n,d", [(2500, 64), (5001, 128), (1500, 13)])
+def test_precision_reorth_bf16_mfma(damf, n, d):
+    """Re-orthogonalisation rotates the BF16-pair bases with BF16 MFMA (three products).
+    n = 5001 leaves a ragged last row block after several blocks per workgroup;
+    d = 13 pads the 16-wide MFMA tiles and moves rows 4 bytes at a time."""
+    _say(f"case precision_reorth n={n} d={d}")
     rng = np.random.default_rng(3)
     U, _ = np.linalg.qr(rng.standard_normal((n, d)))
     V, _ = np.linalg.qr(rng.standard_normal((n, d)))
