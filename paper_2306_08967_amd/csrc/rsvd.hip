@@ -429,6 +429,86 @@ __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t 
   }
 }
 
+// The same product with B resident in LDS, for d <= 16 TL and l <= 192: one
+// workgroup of 8 waves per CU (B takes up to 111 KB) strides over blocks of
+// 128 rows, so B is read from L2 once per workgroup instead of once per 64
+// rows.  A moves through a double-buffered 128 x 32 LDS tile, the next tile
+// loaded into registers while the current one is multiplied, one barrier per
+// k step.  Each wave owns 16 rows of a block and all 16 TL columns.
+constexpr int GM2 = 128;
+constexpr int GK2 = 32;
+constexpr int kTallLmax = 192;
+template <int TL>
+__global__ __launch_bounds__(512) void gemm_tall_res_kernel(const float *A, int64_t n, int l, int lda,
+                                                            const float *__restrict__ B, int d,
+                                                            float *C, int ldc) {
+  constexpr int BW = 16 * TL;
+  __shared__ float Bs[kTallLmax][BW + 4];
+  __shared__ float As[2][GM2][GK2 + 1];
+  const int lane = threadIdx.x & 63;
+  const int w = threadIdx.x >> 6;
+  for (int e = threadIdx.x; e < kTallLmax * BW; e += 512) {
+    const int k = e / BW, j = e - k * BW;
+    Bs[k][j] = (k < l && j < d) ? B[(int64_t)k * d + j] : 0.f;
+  }
+  constexpr int PER = GM2 * GK2 / 512;  // A values per thread per tile
+  const int nk = (l + GK2 - 1) / GK2;
+  float pre[PER];
+  auto fetch = [&](int64_t r0, int k0) {
+#pragma unroll
+    for (int q = 0; q < PER; ++q) {
+      const int e = threadIdx.x + q * 512;
+      const int i = e / GK2, k = e - i * GK2;
+      const int64_t r = r0 + i;
+      pre[q] = (r < n && k0 + k < l) ? A[r * lda + k0 + k] : 0.f;
+    }
+  };
+  const int64_t step = (int64_t)gridDim.x * GM2;
+  int buf = 0;
+  fetch((int64_t)blockIdx.x * GM2, 0);
+  for (int64_t row0 = (int64_t)blockIdx.x * GM2; row0 < n; row0 += step) {
+    v4f acc[TL];
+#pragma unroll
+    for (int t = 0; t < TL; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int kt = 0; kt < nk; ++kt) {
+#pragma unroll
+      for (int q = 0; q < PER; ++q) {
+        const int e = threadIdx.x + q * 512;
+        As[buf][e / GK2][e - (e / GK2) * GK2] = pre[q];
+      }
+      // B written (first pass); the tile in As[buf] complete; every wave is
+      // past its reads of As[buf] from two k steps back
+      __syncthreads();
+      if (kt + 1 < nk)
+        fetch(row0, (kt + 1) * GK2);
+      else if (row0 + step < n)
+        fetch(row0 + step, 0);
+      const int k0 = kt * GK2;
+#pragma unroll
+      for (int kk = 0; kk < GK2; kk += 4) {
+        if (k0 + kk >= l) break;
+        const float a = As[buf][w * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int t = 0; t < TL; ++t) {
+          const float b = Bs[k0 + kk + (lane >> 4)][t * 16 + (lane & 15)];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        }
+      }
+      buf ^= 1;
+    }
+    // the whole block's rows were read by this workgroup before these stores
+#pragma unroll
+    for (int t = 0; t < TL; ++t) {
+      const int j = t * 16 + (lane & 15);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = row0 + w * 16 + (lane >> 4) * 4 + q;
+        if (r < n && j < d) C[r * ldc + j] = acc[t][q];
+      }
+    }
+  }
+}
+
 // ---------------------------------------------------------------- CholeskyQR2
 // Tall-skinny QR of Y (m x l, l <= 192) as two CholeskyQR passes: the Gram
 // G = Y^T Y in FP64 (one read of Y), G = R^T R by Cholesky in FP64, then
@@ -642,10 +722,13 @@ hipError_t tsqr(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) 
 
 hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B, int d, float *C,
                      int ldc, hipStream_t s) {
+  if (l < 1 || l > kTallLmax || n < 1) return hipErrorInvalidValue;
+  // one workgroup per CU, B resident; at most as many as there are row blocks
+  const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, GM2), 256);
   if (d <= 128)
-    gemm_tall_kernel<8><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+    gemm_tall_res_kernel<8><<<g, 512, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else if (d <= 144)  // d + p = 138 at d = 128: nine column tiles, not twelve
-    gemm_tall_kernel<9><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+    gemm_tall_res_kernel<9><<<g, 512, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else if (d <= 192)
     gemm_tall_kernel<12><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else
