@@ -430,34 +430,36 @@ __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t 
 }
 
 // The same product with B resident in LDS, for d <= 16 TL and l <= 192: one
-// workgroup of 8 waves per CU (B takes up to 111 KB) strides over blocks of
-// 128 rows, so B is read from L2 once per workgroup instead of once per 64
-// rows.  A moves through a double-buffered 128 x 32 LDS tile, the next tile
-// loaded into registers while the current one is multiplied, one barrier per
-// k step.  Each wave owns 16 rows of a block and all 16 TL columns.
-constexpr int GM2 = 128;
-constexpr int GK2 = 32;
+// workgroup of NWV waves per CU (B takes up to 111 KB) strides over blocks
+// of 16 NWV rows, so B is read from L2 once per workgroup instead of once
+// per 64 rows.  A moves through a double-buffered LDS tile GK2 wide, the
+// next tile loaded into registers while the current one is multiplied, one
+// barrier per k step.  Each wave owns 16 rows of a block and all 16 TL
+// columns.  Launched with 16 waves and GK2 = 16 (4 waves per SIMD, 148 KB
+// of LDS at TL = 9); 8 waves with GK2 = 32 ran 6% slower.
 constexpr int kTallLmax = 192;
-template <int TL>
-__global__ __launch_bounds__(512) void gemm_tall_res_kernel(const float *A, int64_t n, int l, int lda,
+template <int TL, int NWV, int GK2>
+__global__ __launch_bounds__(64 * NWV) void gemm_tall_res_kernel(const float *A, int64_t n, int l, int lda,
                                                             const float *__restrict__ B, int d,
                                                             float *C, int ldc) {
   constexpr int BW = 16 * TL;
+  constexpr int GM2 = 16 * NWV;  // rows per block
+  constexpr int NTH = 64 * NWV;
   __shared__ float Bs[kTallLmax][BW + 4];
   __shared__ float As[2][GM2][GK2 + 1];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  for (int e = threadIdx.x; e < kTallLmax * BW; e += 512) {
+  for (int e = threadIdx.x; e < kTallLmax * BW; e += NTH) {
     const int k = e / BW, j = e - k * BW;
     Bs[k][j] = (k < l && j < d) ? B[(int64_t)k * d + j] : 0.f;
   }
-  constexpr int PER = GM2 * GK2 / 512;  // A values per thread per tile
+  constexpr int PER = GM2 * GK2 / NTH;  // A values per thread per tile
   const int nk = (l + GK2 - 1) / GK2;
   float pre[PER];
   auto fetch = [&](int64_t r0, int k0) {
 #pragma unroll
     for (int q = 0; q < PER; ++q) {
-      const int e = threadIdx.x + q * 512;
+      const int e = threadIdx.x + q * NTH;
       const int i = e / GK2, k = e - i * GK2;
       const int64_t r = r0 + i;
       pre[q] = (r < n && k0 + k < l) ? A[r * lda + k0 + k] : 0.f;
@@ -473,7 +475,7 @@ __global__ __launch_bounds__(512) void gemm_tall_res_kernel(const float *A, int6
     for (int kt = 0; kt < nk; ++kt) {
 #pragma unroll
       for (int q = 0; q < PER; ++q) {
-        const int e = threadIdx.x + q * 512;
+        const int e = threadIdx.x + q * NTH;
         As[buf][e / GK2][e - (e / GK2) * GK2] = pre[q];
       }
       // B written (first pass); the tile in As[buf] complete; every wave is
@@ -724,11 +726,12 @@ hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B, 
                      int ldc, hipStream_t s) {
   if (l < 1 || l > kTallLmax || n < 1) return hipErrorInvalidValue;
   // one workgroup per CU, B resident; at most as many as there are row blocks
-  const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, GM2), 256);
+  constexpr int NWV = 16, GK2 = 16;
+  const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 16 * NWV), 256);
   if (d <= 128)
-    gemm_tall_res_kernel<8><<<g, 512, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+    gemm_tall_res_kernel<8, NWV, GK2><<<g, 64 * NWV, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else if (d <= 144)  // d + p = 138 at d = 128: nine column tiles, not twelve
-    gemm_tall_res_kernel<9><<<g, 512, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+    gemm_tall_res_kernel<9, NWV, GK2><<<g, 64 * NWV, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else if (d <= 192)
     gemm_tall_kernel<12><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else
