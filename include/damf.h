@@ -129,6 +129,10 @@ typedef struct {
   double ms_spmm_kernel;  /* propagation SpMM kernels, summed                  */
   double spmm_bytes;      /* compulsory HBM bytes of those SpMM kernels        */
   int64_t nnz;            /* edges of A                                        */
+  int64_t qr_fallbacks;   /* tall QRs of the t-SVD that took the Householder
+                             TSQR because the sketch's Gram was not clearly
+                             positive definite (rank below d + p, or cond above
+                             about 1e5); the others ran as CholeskyQR2         */
 } damf_init_info;
 
 /* Defaults: d=128, directed, p=10, q=2, alpha=0.15, eps=1e-5, r=64,

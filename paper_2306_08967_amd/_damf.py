@@ -90,6 +90,7 @@ class DamfInitInfo(C.Structure):
         ("ms_spmm_kernel", C.c_double),
         ("spmm_bytes", C.c_double),
         ("nnz", C.c_int64),
+        ("qr_fallbacks", C.c_int64),
     ]
 
     def as_dict(self):

@@ -524,58 +524,104 @@ constexpr int LM = kMaxCore;     // widest sketch, d + p <= 192
 constexpr int kCqrParts = 256;   // workgroups of a Gram pass
 constexpr double kCqrPivot = 1e-10;
 
-// Partial Grams: workgroup b sums its share of the rows into part[b] (LM x
-// LM).  Thread (ti, tj) of a 16 x 32 grid owns rows 12 ti .. + 12 and
-// columns 6 tj .. + 6.
+// Partial Grams on FP64 MFMA (v_mfma_f64_16x16x4 f64): workgroup b sums
+// its share of the rows into part[b] (LM x LM, upper-triangle 16 x 16 tiles
+// only; the reduction mirrors them).  The tiles I <= J are dealt to the 8
+// waves in turn, so every SIMD carries about the same number; each MFMA
+// takes four rows of Y, converted to FP64 from a 64-row LDS tile, and the
+// next 64 rows are loaded into registers while the current ones are used.
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+constexpr int kGramSlots = (12 * 13 / 2 + 7) / 8;  // tiles per wave at l = 192
 __global__ __launch_bounds__(512) void cqr_gram_kernel(const float *Y, int64_t m, int l, int ld,
                                                        double *part) {
   __shared__ float tile[64][LM + 4];
-  const int ti = threadIdx.x >> 5, tj = threadIdx.x & 31;
-  const bool active = 12 * ti < l && 6 * tj < l;
-  double acc[12][6];
+  const int lane = threadIdx.x & 63;
+  const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // uniform per wave
+  const int nt = (l + 15) >> 4;           // 16-wide column tiles
+  const int ntiles = nt * (nt + 1) / 2;   // tiles with I <= J
+  int ti[kGramSlots], tj[kGramSlots];
 #pragma unroll
-  for (int i = 0; i < 12; ++i)
+  for (int q = 0; q < kGramSlots; ++q) {
+    int u = w + 8 * q, I = 0;
 #pragma unroll
-    for (int j = 0; j < 6; ++j) acc[i][j] = 0.0;
+    for (int t = 0; t < 12; ++t) {  // row I of the triangle holds nt - I tiles
+      const bool past = I < nt && u >= nt - I;
+      u -= past ? nt - I : 0;
+      I += past ? 1 : 0;
+    }
+    // slots past the last tile (I == nt) read tile nt - 1 and are not used
+    ti[q] = min(I, nt - 1);
+    tj[q] = min(I + u, nt - 1);
+  }
+  const int nslot = (ntiles - w + 7) / 8;  // slots q with w + 8 q < ntiles
+  v4f64 acc[kGramSlots];
+#pragma unroll
+  for (int q = 0; q < kGramSlots; ++q) acc[q] = v4f64{0.0, 0.0, 0.0, 0.0};
   const int64_t per = (m + gridDim.x - 1) / gridDim.x;
   const int64_t r0 = (int64_t)blockIdx.x * per;
   const int64_t r1 = min<int64_t>(m, r0 + per);
+  // tile loads: thread t moves columns t % 64 + 64 j (j < 3) of rows
+  // t / 64 + 8 i (i < 8)
+  const int fc = threadIdx.x & 63, fr = threadIdx.x >> 6;
+  bool col_in[LM / 64];
+#pragma unroll
+  for (int j = 0; j < LM / 64; ++j) col_in[j] = fc + 64 * j < l;
+  float pre[8][LM / 64];
+  auto fetch = [&](int64_t base) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t r = base + fr + 8 * i;
+      const float *row = Y + r * ld + fc;
+#pragma unroll
+      for (int j = 0; j < LM / 64; ++j) pre[i][j] = (r < r1 && col_in[j]) ? row[64 * j] : 0.f;
+    }
+  };
+  if (r0 < r1) fetch(r0);
   for (int64_t base = r0; base < r1; base += 64) {
-    for (int e = threadIdx.x; e < 64 * LM; e += 512) {
-      const int rr = e / LM, c = e - rr * LM;
-      const int64_t r = base + rr;
-      tile[rr][c] = (r < r1 && c < l) ? Y[r * ld + c] : 0.f;
-    }
+    __syncthreads();  // every wave is done with the previous rows
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+#pragma unroll
+      for (int j = 0; j < LM / 64; ++j) tile[fr + 8 * i][fc + 64 * j] = pre[i][j];
     __syncthreads();
-    if (active) {
-      for (int rr = 0; rr < 64; ++rr) {
-        double a[12], b[6];
+    if (base + 64 < r1) fetch(base + 64);
+#pragma unroll 1
+    for (int k = 0; k < 64; k += 4) {
+      const int rr = k + (lane >> 4);
+      float a[kGramSlots], b[kGramSlots];  // all reads first, one wait
 #pragma unroll
-        for (int i = 0; i < 12; ++i) a[i] = (double)tile[rr][12 * ti + i];
-#pragma unroll
-        for (int j = 0; j < 6; ++j) b[j] = (double)tile[rr][6 * tj + j];
-#pragma unroll
-        for (int i = 0; i < 12; ++i)
-#pragma unroll
-          for (int j = 0; j < 6; ++j) acc[i][j] = fma(a[i], b[j], acc[i][j]);
+      for (int q = 0; q < kGramSlots; ++q) {
+        a[q] = tile[rr][16 * ti[q] + (lane & 15)];
+        b[q] = tile[rr][16 * tj[q] + (lane & 15)];
       }
+#pragma unroll
+      for (int q = 0; q < kGramSlots; ++q)
+        if (q < nslot)
+          acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)a[q], (double)b[q], acc[q], 0, 0, 0);
     }
-    __syncthreads();
   }
+  // output layout of the FP64 16 x 16 x 4 MFMA: register v of lane group g
+  // (lanes 16 g .. 16 g + 15) holds row 4 v + g, column lane % 16
   double *out = part + (size_t)blockIdx.x * LM * LM;
 #pragma unroll
-  for (int i = 0; i < 12; ++i)
+  for (int q = 0; q < kGramSlots; ++q) {
+    if (q < nslot) {
 #pragma unroll
-    for (int j = 0; j < 6; ++j) out[(12 * ti + i) * LM + 6 * tj + j] = acc[i][j];
+      for (int v = 0; v < 4; ++v)
+        out[(16 * ti[q] + 4 * v + (lane >> 4)) * LM + 16 * tj[q] + (lane & 15)] = acc[q][v];
+    }
+  }
 }
 
-// G[i][j] = sum over the parts (i, j < l), row stride LM.
+// G[i][j] = sum over the parts (i, j < l), row stride LM; the parts hold the
+// upper triangle (i <= j).
 __global__ void cqr_reduce_kernel(const double *part, int nparts, int l, double *G) {
   const int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= l * l) return;
   const int i = e / l, j = e - i * l;
+  const int src = (i <= j) ? i * LM + j : j * LM + i;
   double s = 0.0;
-  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * LM * LM + i * LM + j];
+  for (int b = 0; b < nparts; ++b) s += part[(size_t)b * LM * LM + src];
   G[i * LM + j] = s;
 }
 
@@ -743,7 +789,8 @@ namespace {
 
 // CholeskyQR2 of Y in place (Rtop = R2 R1); the Householder TSQR when the
 // first Gram is not clearly positive definite.
-hipError_t tall_qr(float *Y, int64_t m, int l, int ld, float *Rtop, hipStream_t s) {
+hipError_t tall_qr(float *Y, int64_t m, int l, int ld, float *Rtop, hipStream_t s,
+                   int64_t *fallbacks) {
   if (l > LM) return hipErrorInvalidValue;
   const int nparts = (int)std::min<int64_t>(kCqrParts, (m + 63) / 64);
   double *part = nullptr, *G = nullptr, *R1 = nullptr, *R2 = nullptr;
@@ -769,6 +816,7 @@ hipError_t tall_qr(float *Y, int64_t m, int l, int ld, float *Rtop, hipStream_t 
       (err = hipMalloc(&bad, sizeof(int))) == hipSuccess) {
     err = pass(R1);
     if (err == hipSuccess && hbad) {
+      ++*fallbacks;
       err = tsqr(Y, m, l, ld, Rtop, s);  // Y untouched by the failed pass
     } else if (err == hipSuccess) {
       err = pass(R2);
@@ -809,18 +857,18 @@ hipError_t rsvd_init(damf_ctx *c) {
   DAMF_HIP(spmm_plan_build(c, c->out, ld, &pout));
   DAMF_HIP(spmm_plan_build(c, c->in, ld, &pin));
   DAMF_HIP(csr_spmm(c->out, pout, T, Y, n, l, ld, s));  // Y = A Omega
-  DAMF_HIP(tall_qr(Y, n, l, ld, Rt, s));
+  DAMF_HIP(tall_qr(Y, n, l, ld, Rt, s, &c->init_info.qr_fallbacks));
   for (int it = 0; it < c->cfg.power_iters; ++it) {
     DAMF_HIP(csr_spmm(c->in, pin, Y, T, n, l, ld, s));  // A^T Q
-    DAMF_HIP(tall_qr(T, n, l, ld, Rt, s));
+    DAMF_HIP(tall_qr(T, n, l, ld, Rt, s, &c->init_info.qr_fallbacks));
     DAMF_HIP(csr_spmm(c->out, pout, T, Y, n, l, ld, s));  // A Q
-    DAMF_HIP(tall_qr(Y, n, l, ld, Rt, s));
+    DAMF_HIP(tall_qr(Y, n, l, ld, Rt, s, &c->init_info.qr_fallbacks));
   }
   DAMF_HIP(csr_spmm(c->in, pin, Y, T, n, l, ld, s));  // B^T = A^T Q
   DAMF_HIP(hipStreamSynchronize(s));
   spmm_plan_free(pout);
   spmm_plan_free(pin);
-  DAMF_HIP(tall_qr(T, n, l, ld, Rt, s));     // T = Q2, Rt = R2
+  DAMF_HIP(tall_qr(T, n, l, ld, Rt, s, &c->init_info.qr_fallbacks));     // T = Q2, Rt = R2
   small_svd_kernel<<<1, 1024, 0, s>>>(Rt, l, d, E, th, H);
   DAMF_HIP(hipGetLastError());
   to_float_kernel<<<ceil_div((int64_t)l * d, 256), 256, 0, s>>>(E, Ef, (int64_t)l * d);

@@ -43,7 +43,12 @@ def test_rsvd_exact_on_low_rank(damf, n):
     err = np.abs(X @ Y.T - A).max()
     sv = np.linalg.svd(A, compute_uv=False)[:d]
     sg = ctx.singular_values()
-    _say(f"  max|XY^T - A| {err:.2e} sigma err {np.abs(sg - sv).max() / sv[0]:.2e}")
+    fb = ctx.init_info()["qr_fallbacks"]
+    _say(f"  max|XY^T - A| {err:.2e} sigma err {np.abs(sg - sv).max() / sv[0]:.2e} "
+         f"QR fallbacks {fb}")
+    # rank 6 < d + p = 12: every sketch's Gram is singular, so the QRs take
+    # the Householder TSQR
+    assert fb > 0
     assert err <= 1e-4
     assert np.abs(sg - sv).max() <= 1e-5 * sv[0]
     ctx.close()
@@ -62,7 +67,9 @@ def test_rsvd_matches_oracle_same_sketch(damf):
     err_s = np.abs(sg - s).max() / s[0]
     err_p = product_rel_err(X, Y, U * np.sqrt(s), V * np.sqrt(s))
     eo = max(orth_err(unit_factor(X, sg)), orth_err(unit_factor(Y, sg)))
-    _say(f"  sigma err {err_s:.2e} product err {err_p:.2e} orth {eo:.2e}")
+    fb = ctx.init_info()["qr_fallbacks"]
+    _say(f"  sigma err {err_s:.2e} product err {err_p:.2e} orth {eo:.2e} QR fallbacks {fb}")
+    assert fb == 0  # full-rank sketches: every QR ran as CholeskyQR2
     assert err_s <= 1e-5 and err_p <= 1e-5 and eo <= 1e-5
     ctx.close()
 
@@ -96,7 +103,9 @@ def test_rsvd_parity_with_hub_rows(damf):
     X, Y = ctx.query("X"), ctx.query("Y")
     err_s = np.abs(sg - s).max() / s[0]
     err_p = product_rel_err(X, Y, U * np.sqrt(s), V * np.sqrt(s))
-    _say(f"  sigma err {err_s:.2e} product err {err_p:.2e}")
+    fb = ctx.init_info()["qr_fallbacks"]
+    _say(f"  sigma err {err_s:.2e} product err {err_p:.2e} QR fallbacks {fb}")
+    assert fb == 0
     assert err_s <= 1e-5 and err_p <= 1e-5
     ctx.close()
 
