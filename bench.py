@@ -79,6 +79,8 @@ def parse():
     ap.add_argument("--cpu-batches", type=int, default=1)
     ap.add_argument("--precision", type=int, default=0, choices=(0, 1),
                     help="1: the precision form (bases as BF16 pairs, BF16 MFMA rotations)")
+    ap.add_argument("--jacobi-tol", type=float, default=0.0,
+                    help="core SVD Jacobi tolerance of the measured context (0: the library default)")
     ap.add_argument("--mode", choices=("update", "serve"), default="update",
                     help="update: batches through damf_update (default); serve: the server")
     ap.add_argument("--workload", choices=("c2", "c3", "billion"), default="c2",
@@ -444,7 +446,7 @@ def billion_main(args):
         f"{W + K} batches of {bs} inserts")
     cfg = default_config(n, d, directed=True, alpha=0.15, eps=1e-6, oversample=10,
                          power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64,
-                         precision=1, kernel_timing=1)
+                         precision=1, kernel_timing=1, jacobi_tol=args.jacobi_tol)
     t0 = time.perf_counter()
     ctx = Context.init(cfg, src, dst)
     torch.cuda.synchronize()
@@ -528,7 +530,8 @@ def c3_main(args):
     def config(precision):
         return default_config(n, d, directed=True, alpha=0.15, eps=1e-5, oversample=10,
                               power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64,
-                              precision=precision, reorth_every=64, kernel_timing=1)
+                              precision=precision, reorth_every=64, kernel_timing=1,
+                              jacobi_tol=args.jacobi_tol if precision == 1 else 0.0)
 
     t0 = time.perf_counter()
     ctx = Context.init(config(1), src, dst)
@@ -577,7 +580,7 @@ def c3_main(args):
         "scaling": "weak", "vs_baseline": None, "dtype": "bf16x2", "data": "synthetic",
         "config": {"workload": "chung-lu-2.1 n=4e6 m=6e7 d=128 batch=5000 (95% ins / 5% del), "
                                "alpha=0.15 eps=1e-5, precision form, re-orthogonalisation every 64",
-                   "n": n, "m": m, "d": d, "batch": bs},
+                   "n": n, "m": m, "d": d, "batch": bs, "jacobi_tol": args.jacobi_tol or 1e-8},
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
                        "mean": float(np.mean(lat)) * 1e3},
         "init_s": init_s,
@@ -645,7 +648,7 @@ def main():
     dst = torch.from_numpy(w["init"][1]).cuda()
     cfg = default_config(n, d, directed=True, alpha=0.15, eps=1e-5, oversample=10,
                          power_iters=2, seed=args.seed, max_core_rank=args.r, max_side=64,
-                         precision=args.precision, kernel_timing=1)
+                         precision=args.precision, kernel_timing=1, jacobi_tol=args.jacobi_tol)
     t0 = time.perf_counter()
     ctx = Context.init(cfg, src, dst)
     torch.cuda.synchronize()
@@ -760,7 +763,8 @@ def main():
         "config": {"workload": "chung-lu-2.1 n=1e6 m=1e7 d=128 batch=1000 (95% ins / 5% del), "
                                "alpha=0.15 eps=1e-5",
                    "n": n, "m": m, "d": d, "batch": args.batch, "chunk_rank": args.r,
-                   "precision": "bf16 pairs" if args.precision == 1 else "fp32"},
+                   "precision": "bf16 pairs" if args.precision == 1 else "fp32",
+                   "jacobi_tol": args.jacobi_tol or (1e-8 if args.precision == 1 else 1e-9)},
         "accuracy": accuracy,
         "latency_ms": {"p50": pct(lat, 50) * 1e3, "p99": pct(lat, 99) * 1e3,
                        "mean": float(np.mean(lat)) * 1e3},

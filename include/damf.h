@@ -88,6 +88,13 @@ typedef struct {
                             pair of HIP events (up to 256 chunks per batch) and
                             report the sum in damf_batch_info.ms_core_kernel;
                             0 (default): no per-launch events              */
+  double jacobi_tol;     /* Step 2 core SVD (one-sided Jacobi): a column pair
+                            is rotated while |a_i . a_j| > jacobi_tol
+                            ||a_i|| ||a_j||.  0 (default) means 1e-9 for FP32
+                            bases, which keeps the products at FP32 rounding,
+                            and 1e-8 for the precision form, whose stored
+                            bases carry about 16 significant bits.  Valid:
+                            0, or 1e-14 .. 1e-6                            */
 } damf_config;
 
 /* Per-batch statistics written by damf_update when `info` is non-NULL. */

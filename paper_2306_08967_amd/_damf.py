@@ -47,6 +47,7 @@ class DamfConfig(C.Structure):
         ("hip_stream", C.c_void_p),
         ("precision", C.c_int32),
         ("kernel_timing", C.c_int32),
+        ("jacobi_tol", C.c_double),
     ]
 
 

@@ -64,6 +64,8 @@ damf_status check_config(const damf_config *cfg) {
   if (cfg->reorth_every < 0) return DAMF_E_INVALID_ARG;
   if (cfg->precision != 0 && cfg->precision != 1) return DAMF_E_INVALID_ARG;
   if (cfg->kernel_timing != 0 && cfg->kernel_timing != 1) return DAMF_E_INVALID_ARG;
+  if (!(cfg->jacobi_tol == 0.0 || (cfg->jacobi_tol >= 1e-14 && cfg->jacobi_tol <= 1e-6)))
+    return DAMF_E_INVALID_ARG;
   return DAMF_OK;
 }
 

@@ -42,11 +42,14 @@ def test_precision_c1_parity(damf):
     _say("case precision_c1")
     w = c1_workload()
     orc = DAMFOracle(w["n"], w["d"], False, alpha=1.0, r=32, r_max=64, tau=1e-6).init_exact(*w["init"])
+    # (precision form, core Jacobi tolerance; 0 = the default: 1e-9 for FP32
+    # bases, 1e-8 for the precision form)
+    forms = ((0, 0.0), (1, 1e-9), (1, 0.0), (1, 1e-7))
     ctxs = {}
-    for prec in (0, 1):
+    for prec, jtol in forms:
         cfg = damf.default_config(orc.n, orc.d, directed=False, alpha=1.0, max_core_rank=32,
-                                  max_side=64, tau=1e-6, precision=prec)
-        ctxs[prec] = damf.Context.init_factors(cfg, *w["init"], orc.U, orc.s, orc.V)
+                                  max_side=64, tau=1e-6, precision=prec, jacobi_tol=jtol)
+        ctxs[(prec, jtol)] = damf.Context.init_factors(cfg, *w["init"], orc.U, orc.s, orc.V)
     errs = {}
     for b, (s, t, op) in enumerate(w["stream"]):
         orc.update(s, t, op)
@@ -57,11 +60,12 @@ def test_precision_c1_parity(damf):
         X, Y = ctx.query("X"), ctx.query("Y")
         errs[prec] = (np.max(np.abs(sg - orc.s)) / orc.s[0], product_rel_err(X, Y, orc.X(), orc.Y()),
                       max(orth_err(unit_factor(X, sg)), orth_err(unit_factor(Y, sg))))
-        _say(f"  precision {prec}: sigma err {errs[prec][0]:.2e} product err {errs[prec][1]:.2e} "
-             f"orth {errs[prec][2]:.2e}")
+        _say(f"  precision {prec[0]} jacobi_tol {prec[1]:g}: sigma err {errs[prec][0]:.2e} "
+             f"product err {errs[prec][1]:.2e} orth {errs[prec][2]:.2e}")
         ctx.close()
-    assert errs[0][0] <= 1e-5 and errs[0][1] <= 1e-5
-    assert errs[1][0] <= 1e-5 and errs[1][1] <= 1e-4 and errs[1][2] <= 1e-4
+    assert errs[(0, 0.0)][0] <= 1e-5 and errs[(0, 0.0)][1] <= 1e-5
+    for form in forms[1:]:
+        assert errs[form][0] <= 1e-5 and errs[form][1] <= 1e-5 and errs[form][2] <= 1e-4, form
 
 
 def test_precision_rsvd_and_ppr_invariant(damf):
