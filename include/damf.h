@@ -124,7 +124,9 @@ typedef struct {
                              around each launch; needs kernel_timing = 1)     */
   int64_t core_launches;  /* launches timed into ms_core_kernel                */
   double core_flops;      /* counted FP64 flops of all core-SVD launches: Jacobi
-                             sweeps x 4N^2(N-1) + 2N^2 d (H) + 2N^2 k (K)      */
+                             sweeps x N(N-1)/2 pairs x (2N for the dot + 6N f
+                             for the rotation, f the share of steps in which
+                             any pair rotated) + 2N^2 d (H) + 2N^2 k (K)      */
 } damf_batch_info;
 
 /* Statistics of the initialisation (damf_init / damf_init_factors). */

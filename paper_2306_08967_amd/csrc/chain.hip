@@ -435,6 +435,9 @@ __device__ __noinline__ int core_svd(const ChunkState &cs, int d, const double *
   }
   __syncthreads();
   int *flag = ilds;
+  int *skipped = ilds + 2;  // steps without a rotation, counted by jw_sweeps
+  if (tid() == 0) *skipped = 0;
+  __syncthreads();
   uint64_t tj0 = wall_clock64();
   const int sweeps = jw_sweeps<S>(J, lds, flag, 40, jtol);
   if (tid() == 0) ticks[1] += wall_clock64() - tj0;
@@ -1089,12 +1092,18 @@ __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
   for (int c = tid(); c < d; c += NT) p.sigma[c] = scr[OFF_TH + c];
   clk.tick(p.stats, 3);
   if (tid() == 0) {
-    // counted FP64 work of this chunk: Jacobi (dot + rotation = 8N flops per
-    // pair, N(N-1)/2 pairs per sweep), H = K^T E, F, P F, LU and solves
+    // counted FP64 work of this chunk: Jacobi (N(N-1)/2 pairs per sweep, a
+    // dot of 2N flops each and a rotation of 6N flops in the steps whose
+    // shears ran, share shf), H = K^T E, F, P F, LU and solves
     const double Nn = (double)N, dd = (double)d, kk = (double)k;
-    atomicAdd(&p.stats->core_flops, sw * 4.0 * Nn * Nn * (Nn - 1.0) + 2.0 * Nn * Nn * dd +
-                                        2.0 * Nn * Nn * kk);
-    double flops = sw * 4.0 * Nn * Nn * (Nn - 1.0) + 2.0 * Nn * Nn * dd;
+    // ilds[2]: steps (over the waves) without a rotation, from core_svd; a
+    // sweep has 8 waves x (16 B - 1) steps, B = NP / 16 columns per half-block
+    const int np = N <= 64 ? 64 : (N <= 128 ? 128 : 192);
+    const double all_steps = (double)sw * 8.0 * (np - 1.0);
+    const double shf = sw > 0 ? 1.0 - ilds[2] / all_steps : 1.0;
+    const double jac = sw * 0.5 * Nn * (Nn - 1.0) * (2.0 * Nn + 6.0 * Nn * shf);
+    atomicAdd(&p.stats->core_flops, jac + 2.0 * Nn * Nn * dd + 2.0 * Nn * Nn * kk);
+    double flops = jac + 2.0 * Nn * Nn * dd;
     flops += 2.0 * (2.0 * dd * dd * kk + 2.0 * dd * dd * dd + (2.0 / 3.0) * dd * dd * dd +
                     2.0 * 2.0 * (double)max(cs.s1, cs.s2) * dd * dd);
     flops += 2.0 * (double)(cs.s1 + cs.s2) * dd * dd + 4.0 * kk * kk * dd;

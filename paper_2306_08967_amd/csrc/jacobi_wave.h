@@ -178,7 +178,7 @@ struct JWIntra {
 template <class S, class PM, class IdF>
 __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
                                         double floor2, double tol2, double conv2, IdF ids, int &rot,
-                                        int &big) {
+                                        int &big, int &skip) {
   constexpr int B = S::B, Q = S::QS, RPL = S::RPL;
   const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
   double v[B], g[Q];
@@ -223,6 +223,11 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
     ns[ib] = make_double2(fma(t, gt, be), cs * dj);
   }
   rot += doit ? 1 : 0;
+  // a step in which no pair rotates would only add zeros (t = 0): skip its
+  // shears; finite results are unchanged bit for bit
+  const bool none = __builtin_amdgcn_ballot_w64(doit) == 0;  // uniform over the wave
+  skip += none ? 1 : 0;
+  if (none) return;
   if (plane) bc[pair] = make_double2(t1, t2);
   __builtin_amdgcn_wave_barrier();
 #pragma unroll
@@ -343,7 +348,8 @@ __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int
 template <class S, int U, int... SH>
 __device__ __forceinline__ void jw_cross_steps(JWRegs<S> &J, double2 *ns, double2 *bc, double floor2,
                                                double tol2, double conv2, int ht, int hb, int sh,
-                                               int &rot, int &big, std::integer_sequence<int, SH...>) {
+                                               int &rot, int &big, int &skip,
+                                               std::integer_sequence<int, SH...>) {
   constexpr int B = S::B;
   (jw_step<S, JWCross<S, SH>>(J, ns, bc, floor2, tol2, conv2,
                               [&](int p, int &it, int &ib) {
@@ -352,19 +358,21 @@ __device__ __forceinline__ void jw_cross_steps(JWRegs<S> &J, double2 *ns, double
                                 it = ht * B + p;
                                 ib = hb * B + q;
                               },
-                              rot, big),
+                              rot, big, skip),
    ...);
 }
 
 // Sweeps until one applies no rotation or all its rotations were below
-// sqrt(tol) (or max_sweeps); returns the sweep count.  lds_flag points to 2
-// ints of LDS.  A pair is rotated when |a_i . a_j| > tol ||a_i|| ||a_j|| and
+// sqrt(tol) (or max_sweeps); returns the sweep count.  lds_flag points to 3
+// ints of LDS; the third, cleared by the caller, counts the steps (over all
+// waves) in which no pair rotated and whose shears were skipped.  A pair is rotated when |a_i . a_j| > tol ||a_i|| ||a_j|| and
 // neither column is numerically zero (norm^2 below 1e-30 of the largest).
 // Every thread of the 64 NW-thread workgroup calls it; on return the columns
 // are back in their sweep-boundary slots (jw_col) and the squared norms are
 // in lds[S::NS_OFF + 2 id] (jw_norm2).
 template <class S>
 __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweeps, double tol) {
+  int skip = 0;  // this wave's steps without a rotation
   constexpr int B = S::B, RPL = S::RPL, XU = S::XU;
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
@@ -394,14 +402,14 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
                                    it = h * B + j16_top_id<B>(i, st);
                                    ib = h * B + j16_bot_id<B>(i, st);
                                  },
-                                 rot, big);
+                                 rot, big, skip);
           jw_intra_move<S>(J);
         }
       }
       // cross pairs of the two half-blocks: B steps, XU per iteration (step u
       // with the bottom offset by u slots), then the bottom turned by XU
       for (int sh = 0; sh < B; sh += XU) {
-        jw_cross_steps<S, XU>(J, ns, bc, floor2, tol2, conv2, ht, hb, sh, rot, big,
+        jw_cross_steps<S, XU>(J, ns, bc, floor2, tol2, conv2, ht, hb, sh, rot, big, skip,
                               std::make_integer_sequence<int, XU>{});
         jw_cross_move<S, XU>(J);
       }
@@ -436,6 +444,7 @@ __device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweep
       break;
     }
   }
+  if (lane == 0) atomicAdd(lds_flag + 2, skip);
   return sweeps;
 }
 
