@@ -517,7 +517,13 @@ damf_status damf_init_factors(const damf_config *cfg, int64_t m, const int32_t *
     free_ctx(c);
     return st;
   }
-  std::vector<float> buf((size_t)n * d);
+  std::vector<float> buf;
+  try {
+    buf.resize((size_t)n * d);
+  } catch (...) {
+    free_ctx(c);
+    return DAMF_E_OOM;
+  }
   for (int side = 0; side < 2; ++side) {
     const double *M = side ? V : U;
     for (size_t i = 0; i < buf.size(); ++i) {
@@ -611,7 +617,7 @@ damf_status damf_update_requests(damf_ctx *c, int32_t nreq, const int64_t *req_o
   if (!c) return DAMF_E_INVALID_ARG;
   if (nreq < 1 || nreq > kMaxRequests || !req_ops)
     return fail(c, DAMF_E_INVALID_ARG, "request count out of range");
-  std::vector<int32_t> seg_end(nreq);
+  int32_t seg_end[kMaxRequests];
   int64_t k = 0;
   for (int i = 0; i < nreq; ++i) {
     if (req_ops[i] < 0) return fail(c, DAMF_E_INVALID_ARG, "negative request size");
@@ -619,7 +625,7 @@ damf_status damf_update_requests(damf_ctx *c, int32_t nreq, const int64_t *req_o
     if (k > kMaxBatch) return fail(c, DAMF_E_INVALID_ARG, "batch size out of range");
     seg_end[i] = (int32_t)k;
   }
-  return update_impl(c, k, src, dst, op, flags, nreq, seg_end.data(), info, per_request);
+  return update_impl(c, k, src, dst, op, flags, nreq, seg_end, info, per_request);
 }
 
 damf_status damf_enhance(damf_ctx *c) {
@@ -670,6 +676,15 @@ damf_status damf_query(damf_ctx *c, damf_which which, int64_t q, const int32_t *
   float *dout = out;
   int32_t *own_n = nullptr;
   float *own_o = nullptr;
+  if ((flags & DAMF_DEVICE_PTRS) && nodes) {
+    // device list: a read-only counting pass before any row is read
+    int64_t *bad = c->ws.counters + 12;
+    API_HIP(c, launch_count_bad_ids(nodes, q, c->n, bad, s), "query id check");
+    API_HIP(c, hipMemcpyAsync(c->ws.counters_host + 12, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s),
+            "query id check");
+    API_HIP(c, hipStreamSynchronize(s), "query id check");
+    if (c->ws.counters_host[12] != 0) return fail(c, DAMF_E_OUT_OF_RANGE, "query id out of range");
+  }
   if (!(flags & DAMF_DEVICE_PTRS)) {
     if (nodes) {
       for (int64_t i = 0; i < q; ++i)
@@ -715,6 +730,11 @@ damf_status damf_export_state(damf_ctx *c, double *Ub, double *Vb, double *PU, d
   const int d = c->d;
   API_HIP(c, hipStreamSynchronize(c->stream), "export");
   std::vector<float> buf;
+  try {
+    buf.resize(nd);
+  } catch (...) {
+    return fail(c, DAMF_E_OOM, "export: host memory");
+  }
   bool split = c->split;
   auto pull = [&](const float *src, double *dst) -> hipError_t {
     if (!dst) return hipSuccess;
@@ -722,7 +742,6 @@ damf_status damf_export_state(damf_ctx *c, double *Ub, double *Vb, double *PU, d
       std::fill(dst, dst + nd, 0.0);
       return hipSuccess;
     }
-    buf.resize(nd);
     hipError_t e = hipMemcpy(buf.data(), src, nd * sizeof(float), hipMemcpyDeviceToHost);
     for (size_t i = 0; i < nd; ++i) {
       if (split) {
@@ -823,8 +842,14 @@ damf_status damf_save(damf_ctx *c, const char *path) {
   const int d = c->d;
   int64_t m = 0;
   API_HIP(c, csr_export(c, c->out, nullptr, nullptr, &m), "checkpoint CSR");
-  std::vector<int64_t> indptr(n + 1);
-  std::vector<int32_t> indices(m > 0 ? m : 1);
+  std::vector<int64_t> indptr;
+  std::vector<int32_t> indices;
+  try {
+    indptr.resize(n + 1);
+    indices.resize(m > 0 ? m : 1);
+  } catch (...) {
+    return fail(c, DAMF_E_OOM, "checkpoint: host memory for the CSR");
+  }
   API_HIP(c, csr_export(c, c->out, indptr.data(), indices.data(), &m), "checkpoint CSR");
   FILE *f = std::fopen(path, "wb");
   if (!f) return fail(c, DAMF_E_INVALID_ARG, "cannot open the checkpoint file for writing");
@@ -871,7 +896,45 @@ damf_status damf_load(const char *path, const damf_config *cfg, damf_ctx **out) 
   const bool ppr_on = cfg->alpha < 1.0;
   if (!hdr_ok || h.n != cfg->n || h.d != cfg->d || h.directed != cfg->directed ||
       h.precision != cfg->precision || h.ppr_on != (ppr_on ? 1 : 0) ||
-      (ppr_on && h.alpha != cfg->alpha) || h.m < 0) {
+      (ppr_on && h.alpha != cfg->alpha) || h.m < 0 || check_config(cfg) != DAMF_OK) {
+    std::fclose(f);
+    return DAMF_E_INVALID_ARG;
+  }
+  // the file must hold exactly what the header promises: this bounds m
+  // before anything is allocated from it
+  {
+    const int64_t nd_bytes = h.n * (int64_t)h.d * (int64_t)sizeof(float);
+    const int64_t fixed = (int64_t)sizeof(CkptHeader) + 8 * (h.n + 1) +
+                          2 * (int64_t)h.d * h.d * (int64_t)sizeof(double) +
+                          kMaxCore * (int64_t)sizeof(double) + (ppr_on ? 4 : 2) * nd_bytes;
+    int64_t size = -1;
+    if (fseeko(f, 0, SEEK_END) == 0) size = (int64_t)ftello(f);
+    if (size < fixed || (size - fixed) % 4 != 0 || (size - fixed) / 4 != h.m ||
+        fseeko(f, (off_t)sizeof(CkptHeader), SEEK_SET) != 0) {
+      std::fclose(f);
+      return DAMF_E_INVALID_ARG;
+    }
+  }
+  const int64_t n = h.n, m = h.m;
+  std::vector<int64_t> indptr;
+  std::vector<int32_t> dst, src;
+  try {
+    indptr.resize(n + 1);
+    dst.resize(m > 0 ? m : 1);
+    src.resize(m > 0 ? m : 1);
+  } catch (...) {
+    std::fclose(f);
+    return DAMF_E_OOM;
+  }
+  bool io = std::fread(indptr.data(), sizeof(int64_t), n + 1, f) == (size_t)(n + 1) &&
+            (m == 0 || std::fread(dst.data(), sizeof(int32_t), m, f) == (size_t)m) &&
+            indptr[0] == 0 && indptr[n] == m;
+  // every row range inside [0, m] and in order, before src is written
+  for (int64_t u = 0; io && u < n; ++u)
+    if (indptr[u + 1] < indptr[u] || indptr[u + 1] > m) io = false;
+  for (int64_t u = 0; io && u < n; ++u)
+    for (int64_t e = indptr[u]; e < indptr[u + 1]; ++e) src[e] = (int32_t)u;
+  if (!io) {
     std::fclose(f);
     return DAMF_E_INVALID_ARG;
   }
@@ -881,20 +944,10 @@ damf_status damf_load(const char *path, const damf_config *cfg, damf_ctx **out) 
     std::fclose(f);
     return st;
   }
-  const int64_t n = h.n, m = h.m;
-  std::vector<int64_t> indptr(n + 1);
-  std::vector<int32_t> dst(m > 0 ? m : 1), src(m > 0 ? m : 1);
-  bool io = std::fread(indptr.data(), sizeof(int64_t), n + 1, f) == (size_t)(n + 1) &&
-            (m == 0 || std::fread(dst.data(), sizeof(int32_t), m, f) == (size_t)m) &&
-            indptr[0] == 0 && indptr[n] == m;
-  for (int64_t u = 0; io && u < n; ++u) {
-    if (indptr[u + 1] < indptr[u]) io = false;
-    for (int64_t e = indptr[u]; io && e < indptr[u + 1]; ++e) src[e] = (int32_t)u;
-  }
-  if (!io || (st = alloc_state(c)) != DAMF_OK || (st = build_graph(c, m, src.data(), dst.data(), 0)) != DAMF_OK) {
+  if ((st = alloc_state(c)) != DAMF_OK || (st = build_graph(c, m, src.data(), dst.data(), 0)) != DAMF_OK) {
     std::fclose(f);
     free_ctx(c);
-    return io ? st : DAMF_E_INVALID_ARG;
+    return st;
   }
   void *pin = nullptr;
   hipError_t e = hipHostMalloc(&pin, kCkptChunk);

@@ -5,6 +5,8 @@
 
 #include <cstdint>
 
+#include "launch_geom.h"
+
 namespace damf {
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -38,16 +40,6 @@ __device__ __forceinline__ int64_t lower_bound(const T *a, int64_t n, T x) {
 }
 
 inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
-
-// Workgroups for a grid-stride loop over `count` items taken `per_block` per
-// workgroup pass.  A dispatch holds at most 2^32 - 1 work-items in x, so a
-// grid over n x d elements (5e9 at n = 4e7, d = 128) or with one workgroup
-// per node must stride rather than grow with the problem.
-constexpr int64_t kMaxStrideBlocks = 1 << 16;
-inline unsigned stride_grid(int64_t count, int64_t per_block) {
-  const int64_t b = (count + per_block - 1) / per_block;
-  return (unsigned)(b < 1 ? 1 : (b > kMaxStrideBlocks ? kMaxStrideBlocks : b));
-}
 
 // ---- precision form: a basis element as a pair of BF16 numbers in one
 // 32-bit word, hi = bf16(x) in the upper half and lo = bf16(x - hi) in the

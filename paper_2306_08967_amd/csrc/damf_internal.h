@@ -118,7 +118,8 @@ struct Workspace {
   int32_t *cand = nullptr;       // candidate list (n)
   int32_t *cand2 = nullptr;      // next round's candidates (n)
   int32_t *frontier = nullptr;   // frontier list (n)
-  int64_t *counters = nullptr;   // device counters (cand, frontier, edges, ...)
+  int64_t *counters = nullptr;   // device counters: 0-7 Step 4 (cand, frontier, edges, ...),
+                                 // 8-11 CSR pool tops and needs, 12 bad query ids
   int64_t *counters_host = nullptr;
   double *dscratch_host = nullptr;
 };
@@ -239,9 +240,12 @@ hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B,
 hipError_t flush_projections(damf_ctx *c);
 hipError_t reorthogonalize(damf_ctx *c, int *numeric_bad);
 
-// ---- query.hip
+// ---- state.hip
 hipError_t launch_query(damf_ctx *c, int which, int64_t q,
                         const int32_t *d_nodes, float *d_out);
+// *d_bad = number of ids of d_nodes[0..q) outside [0, n) (cleared first)
+hipError_t launch_count_bad_ids(const int32_t *d_nodes, int64_t q, int64_t n, int64_t *d_bad,
+                                hipStream_t s);
 
 }  // namespace damf
 

@@ -98,10 +98,11 @@ template <typename F>
 hipError_t exclusive_scan(F f, int64_t n, int64_t *out, int64_t *tmp, int64_t *total,
                           hipStream_t s) {
   if (n <= 0) return hipMemsetAsync(total, 0, sizeof(int64_t), s);
-  unsigned nb = ceil_div(n, 1024);
-  scan_blocks_kernel<<<nb, 1024, 0, s>>>(f, n, out, tmp);
+  const Grid g = geom_scan(n);
+  const unsigned nb = g.blocks;
+  scan_blocks_kernel<<<nb, g.threads, 0, s>>>(f, n, out, tmp);
   scan_sums_kernel<<<1, 1024, 0, s>>>(tmp, nb, total);
-  scan_add_kernel<<<nb, 1024, 0, s>>>(out, n, tmp);
+  scan_add_kernel<<<nb, g.threads, 0, s>>>(out, n, tmp);
   return hipGetLastError();
 }
 
@@ -233,46 +234,50 @@ __global__ __launch_bounds__(256) void sort_rows_small_kernel(int64_t n, const i
   }
 }
 
-__global__ __launch_bounds__(1024) void sort_rows_large_kernel(const int32_t *big,
+__global__ __launch_bounds__(1024) void sort_rows_large_kernel(const int32_t *big, int32_t nbig,
                                                                const int64_t *off, int32_t *len,
                                                                int32_t *tmp) {
   __shared__ int32_t buf[kLargeRow];
-  int32_t r = big[blockIdx.x];
-  int32_t L = len[r];
-  if (L > kLargeRow) {
-    // rows beyond LDS: sorting network in global memory (rare: hub rows).
-    // Every comparator is ascending (i < p): the first one of each merge
-    // stage pairs i with its mirror i ^ (k - 1), the rest pair i with i ^ j.
-    // Positions >= L are a virtual +inf pad that no comparator moves, so
-    // nothing is ever written past the row.
-    int32_t *seg = tmp + off[r];
-    int P = 1;
-    while (P < L) P <<= 1;
-    for (int k = 2; k <= P; k <<= 1) {
-      for (int j = k >> 1; j > 0; j >>= 1) {
-        for (int i = threadIdx.x; i < P; i += 1024) {
-          const int p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
-          if (p > i && p < L) {
-            const int32_t a = seg[i], b = seg[p];
-            if (a > b) {
-              seg[i] = b;
-              seg[p] = a;
+  // rows are workgroup-uniform: the continue keeps barriers aligned
+  for (int32_t bi = blockIdx.x; bi < nbig; bi += gridDim.x) {
+    __syncthreads();  // the previous row is done with buf
+    const int32_t r = big[bi];
+    const int32_t L = len[r];
+    if (L > kLargeRow) {
+      // rows beyond LDS: sorting network in global memory (rare: hub rows).
+      // Every comparator is ascending (i < p): the first one of each merge
+      // stage pairs i with its mirror i ^ (k - 1), the rest pair i with i ^ j.
+      // Positions >= L are a virtual +inf pad that no comparator moves, so
+      // nothing is ever written past the row.
+      int32_t *seg = tmp + off[r];
+      int P = 1;
+      while (P < L) P <<= 1;
+      for (int k = 2; k <= P; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+          for (int i = threadIdx.x; i < P; i += 1024) {
+            const int p = (j == (k >> 1)) ? (i ^ (k - 1)) : (i ^ j);
+            if (p > i && p < L) {
+              const int32_t a = seg[i], b = seg[p];
+              if (a > b) {
+                seg[i] = b;
+                seg[p] = a;
+              }
             }
           }
+          __syncthreads();
         }
-        __syncthreads();
       }
+      // unique in place, single thread (rare path)
+      if (threadIdx.x == 0) {
+        int32_t w = 0;
+        for (int32_t i = 0; i < L; ++i)
+          if (i == 0 || seg[i] != seg[i - 1]) seg[w++] = seg[i];
+        len[r] = w;
+      }
+      continue;
     }
-    // unique in place, single thread (rare path)
-    if (threadIdx.x == 0) {
-      int32_t w = 0;
-      for (int32_t i = 0; i < L; ++i)
-        if (i == 0 || seg[i] != seg[i - 1]) seg[w++] = seg[i];
-      len[r] = w;
-    }
-    return;
+    sort_unique_segment<1024, kLargeRow>(tmp + off[r], L, buf, &len[r]);
   }
-  sort_unique_segment<1024, kLargeRow>(tmp + off[r], L, buf, &len[r]);
 }
 
 __global__ void copy_rows_kernel(int64_t n, const int64_t *src_off, const int32_t *tmp,
@@ -351,7 +356,8 @@ hipError_t csr_build(damf_ctx *c, Csr &g, const int32_t *d_rows, const int32_t *
   DAMF_HIP(hipMemcpyAsync(&h_nbig, nbig, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   DAMF_HIP(hipStreamSynchronize(s));
   if (h_nbig > 0) {
-    sort_rows_large_kernel<<<h_nbig, 1024, 0, s>>>(big, off, g.len, tmpcol);
+    const Grid gl = geom_sort_large(h_nbig);
+    sort_rows_large_kernel<<<gl.blocks, gl.threads, 0, s>>>(big, h_nbig, off, g.len, tmpcol);
     DAMF_HIP(hipGetLastError());
   }
   set_caps_kernel<<<stride_grid(n, 256), 256, 0, s>>>(n, g.len, g.cap);

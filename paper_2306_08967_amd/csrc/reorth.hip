@@ -474,7 +474,7 @@ hipError_t rotate_bases(damf_ctx *c, const float *RotU, const float *RotV) {
     if (c->split) {
       // row blocks of 64, at least 16 per workgroup; 16-B row transfers need
       // d % 4 == 0 and a 16-B aligned basis
-      const unsigned g = stride_grid(n, 64 * 16);
+      const unsigned g = geom_gemm_split(n).blocks;
       if (d % 4 == 0 && reinterpret_cast<uintptr_t>(M) % 16 == 0)
         gemm_split_kernel<true, 4><<<g, 256, 0, s>>>(M, n, d, Rot);
       else

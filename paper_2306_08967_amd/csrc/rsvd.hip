@@ -392,39 +392,41 @@ __global__ __launch_bounds__(256) void gemm_tall_kernel(const float *A, int64_t 
   __shared__ float Bs[GK][BW + 4];
   const int lane = threadIdx.x & 63;
   const int w = threadIdx.x >> 6;
-  const int64_t row0 = (int64_t)blockIdx.x * GM;
-  v4f acc[TL];
+  // row blocks in a grid-stride loop (workgroup-uniform, so barriers align)
+  for (int64_t row0 = (int64_t)blockIdx.x * GM; row0 < n; row0 += (int64_t)gridDim.x * GM) {
+    v4f acc[TL];
 #pragma unroll
-  for (int t = 0; t < TL; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < l; k0 += GK) {
-    for (int e = threadIdx.x; e < GM * GK; e += 256) {
-      const int i = e / GK, k = e - i * GK;
-      const int64_t r = row0 + i;
-      As[i][k] = (r < n && k0 + k < l) ? A[r * lda + k0 + k] : 0.f;
-    }
-    for (int e = threadIdx.x; e < GK * BW; e += 256) {
-      const int k = e / BW, j = e - k * BW;
-      Bs[k][j] = (k0 + k < l && j < d) ? B[(k0 + k) * d + j] : 0.f;
-    }
-    __syncthreads();
-#pragma unroll
-    for (int kk = 0; kk < GK; kk += 4) {
-      const float a = As[w * 16 + (lane & 15)][kk + (lane >> 4)];
-#pragma unroll
-      for (int t = 0; t < TL; ++t) {
-        const float b = Bs[kk + (lane >> 4)][t * 16 + (lane & 15)];
-        acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+    for (int t = 0; t < TL; ++t) acc[t] = v4f{0.f, 0.f, 0.f, 0.f};
+    for (int k0 = 0; k0 < l; k0 += GK) {
+      for (int e = threadIdx.x; e < GM * GK; e += 256) {
+        const int i = e / GK, k = e - i * GK;
+        const int64_t r = row0 + i;
+        As[i][k] = (r < n && k0 + k < l) ? A[r * lda + k0 + k] : 0.f;
       }
+      for (int e = threadIdx.x; e < GK * BW; e += 256) {
+        const int k = e / BW, j = e - k * BW;
+        Bs[k][j] = (k0 + k < l && j < d) ? B[(k0 + k) * d + j] : 0.f;
+      }
+      __syncthreads();
+#pragma unroll
+      for (int kk = 0; kk < GK; kk += 4) {
+        const float a = As[w * 16 + (lane & 15)][kk + (lane >> 4)];
+#pragma unroll
+        for (int t = 0; t < TL; ++t) {
+          const float b = Bs[kk + (lane >> 4)][t * 16 + (lane & 15)];
+          acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc[t], 0, 0, 0);
+        }
+      }
+      __syncthreads();
     }
-    __syncthreads();
-  }
 #pragma unroll
-  for (int t = 0; t < TL; ++t) {
-    const int j = t * 16 + (lane & 15);
+    for (int t = 0; t < TL; ++t) {
+      const int j = t * 16 + (lane & 15);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t r = row0 + w * 16 + (lane >> 4) * 4 + q;
-      if (r < n && j < d) C[r * ldc + j] = acc[t][q];
+      for (int q = 0; q < 4; ++q) {
+        const int64_t r = row0 + w * 16 + (lane >> 4) * 4 + q;
+        if (r < n && j < d) C[r * ldc + j] = acc[t][q];
+      }
     }
   }
 }
@@ -736,7 +738,8 @@ hipError_t tsqr(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) 
     if ((err = hipMalloc(&tau, nb * l * sizeof(float))) != hipSuccess) break;
     if ((err = hipMalloc(&S, nb * l * (int64_t)l * sizeof(float))) != hipSuccess) break;
     taus.push_back(tau);
-    tsqr_factor_kernel<<<(unsigned)nb, TNT, 0, s>>>(mats.back(), mm, l, lds.back(), tau, S);
+    static_assert(TB == 512 && TNT == 1024, "geom_tsqr assumes 512-row blocks of 1024 threads");
+    tsqr_factor_kernel<<<geom_tsqr(mm).blocks, TNT, 0, s>>>(mats.back(), mm, l, lds.back(), tau, S);
     if ((err = hipGetLastError()) != hipSuccess) break;
     if (nb == 1) {
       // S holds the final R
@@ -756,7 +759,7 @@ hipError_t tsqr(float *A, int64_t m, int l, int ld, float *Rtop, hipStream_t s) 
       const int64_t mm = rows[lev];
       const int64_t nb = (mm + TB - 1) / TB;
       const float *QS = (lev == levels - 1) ? nullptr : mats[lev + 1];
-      tsqr_formq_kernel<<<(unsigned)nb, TNT, 0, s>>>(mats[lev], mm, l, lds[lev], taus[lev], QS);
+      tsqr_formq_kernel<<<geom_tsqr(mm).blocks, TNT, 0, s>>>(mats[lev], mm, l, lds[lev], taus[lev], QS);
       if ((err = hipGetLastError()) != hipSuccess) break;
     }
   }
@@ -773,13 +776,15 @@ hipError_t gemm_tall(const float *A, int64_t n, int l, int lda, const float *B, 
   if (l < 1 || l > kTallLmax || n < 1) return hipErrorInvalidValue;
   // one workgroup per CU, B resident; at most as many as there are row blocks
   constexpr int NWV = 16, GK2 = 16;
-  const unsigned g = (unsigned)std::min<int64_t>(ceil_div(n, 16 * NWV), 256);
+  static_assert(64 * NWV == 1024 && 16 * NWV == 256, "geom_gemm_tall_res assumes 16 waves");
+  const Grid g = geom_gemm_tall_res(n);
+  const Grid g12 = geom_gemm_tall(n);
   if (d <= 128)
-    gemm_tall_res_kernel<8, NWV, GK2><<<g, 64 * NWV, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+    gemm_tall_res_kernel<8, NWV, GK2><<<g.blocks, g.threads, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else if (d <= 144)  // d + p = 138 at d = 128: nine column tiles, not twelve
-    gemm_tall_res_kernel<9, NWV, GK2><<<g, 64 * NWV, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+    gemm_tall_res_kernel<9, NWV, GK2><<<g.blocks, g.threads, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else if (d <= 192)
-    gemm_tall_kernel<12><<<ceil_div(n, GM), 256, 0, s>>>(A, n, l, lda, B, d, C, ldc);
+    gemm_tall_kernel<12><<<g12.blocks, g12.threads, 0, s>>>(A, n, l, lda, B, d, C, ldc);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

@@ -243,13 +243,13 @@ template <int NC>
 static hipError_t spmm_launch(const Csr &g, const SpmmPlan &p, const float *X, float *Y, float *Z,
                               int64_t n, int k, int ld, int mode, float alpha, unsigned *maxbits,
                               hipStream_t s) {
-  const unsigned grid = (unsigned)std::min<int64_t>(ceil_div(n, 4), 8192);
-  spmm_rows_kernel<NC><<<grid, 256, 0, s>>>(g, X, Y, Z, n, k, ld, mode, alpha, maxbits);
+  const Grid gr = geom_spmm_rows(n), gs = geom_spmm_segments(p.nseg), gl = geom_spmm_long(p.nlong);
+  spmm_rows_kernel<NC><<<gr.blocks, gr.threads, 0, s>>>(g, X, Y, Z, n, k, ld, mode, alpha, maxbits);
   DAMF_HIP(hipGetLastError());
   if (p.nlong > 0) {
-    spmm_segments_kernel<NC><<<ceil_div(p.nseg, 4), 256, 0, s>>>(g, p.seg_row, p.seg_idx, p.nseg,
-                                                                 X, p.part, k, ld);
-    spmm_long_finish_kernel<NC><<<ceil_div(p.nlong, 4), 256, 0, s>>>(
+    spmm_segments_kernel<NC><<<gs.blocks, gs.threads, 0, s>>>(g, p.seg_row, p.seg_idx, p.nseg,
+                                                              X, p.part, k, ld);
+    spmm_long_finish_kernel<NC><<<gl.blocks, gl.threads, 0, s>>>(
         g, p.long_row, p.long_seg0, p.nlong, p.part, X, Y, Z, k, ld, mode, alpha, maxbits);
     DAMF_HIP(hipGetLastError());
   }

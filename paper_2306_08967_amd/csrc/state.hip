@@ -1,6 +1,6 @@
 // state.hip -- small kernels on the embedding state: node queries
-// (Sec. 4.6: X[u] = X_b[u] P_X at O(d^2) per node), identity projections,
-// residual norms.
+// (Sec. 4.6: X[u] = X_b[u] P_X at O(d^2) per node) and the range check of
+// device node lists.
 #include <hip/hip_runtime.h>
 
 #include "common.h"
@@ -8,25 +8,60 @@
 
 namespace damf {
 
-// out[q][c] = sum_k M_b[node_q][k] P[k][c] * sqrt(sigma_c), FP64 accumulate.
-// One wave per queried row; lanes own columns c = lane + 64 j.
+// *bad = 0; a kernel rather than a memset, so the sequence stays valid inside
+// a captured HIP graph.
+__global__ void clear_counter_kernel(int64_t *bad) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *bad = 0;
+}
+
+// *bad += number of ids outside [0, n).  Reads the list only.
+__global__ __launch_bounds__(256) void count_bad_ids_kernel(const int32_t *nodes, int64_t q,
+                                                            int64_t n, int64_t *bad) {
+  int64_t cnt = 0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < q;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const int32_t v = nodes[i];
+    cnt += (v < 0 || (int64_t)v >= n) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off >= 1; off >>= 1) cnt += __shfl_xor(cnt, off, 64);
+  if ((threadIdx.x & 63) == 0 && cnt)
+    atomicAdd((unsigned long long *)bad, (unsigned long long)cnt);
+}
+
+// out[i][c] = sum_k M_b[node_i][k] P[k][c] * sqrt(sigma_c), FP64 accumulate.
+// One wave per queried row, rows taken in a grid-stride loop; lanes own
+// columns c = lane + 64 j.
 __global__ __launch_bounds__(256) void query_kernel(const float *Mb, const double *P,
                                                     const double *sigma, int d, int64_t q,
                                                     const int32_t *nodes, float *out,
                                                     bool split) {
   __shared__ double row[4][kMaxD];
   const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-  const int64_t i = (int64_t)blockIdx.x * 4 + w;
-  if (i >= q) return;
-  const int64_t node = nodes ? nodes[i] : i;
-  for (int k = lane; k < d; k += 64) row[w][k] = (double)basis_ld(Mb, node * d + k, split);
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  for (int c = lane; c < d; c += 64) {
-    double acc = 0.0;
-    for (int k = 0; k < d; ++k) acc = fma(row[w][k], P[k * d + c], acc);
-    out[i * d + c] = (float)(acc * sqrt(sigma[c]));
+  for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < q; i += (int64_t)gridDim.x * 4) {
+    const int64_t node = nodes ? nodes[i] : i;
+    for (int k = lane; k < d; k += 64) row[w][k] = (double)basis_ld(Mb, node * d + k, split);
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    for (int c = lane; c < d; c += 64) {
+      double acc = 0.0;
+      for (int k = 0; k < d; ++k) acc = fma(row[w][k], P[k * d + c], acc);
+      out[i * d + c] = (float)(acc * sqrt(sigma[c]));
+    }
+    // the row buffer is rewritten by the next pass
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
+}
+
+hipError_t launch_count_bad_ids(const int32_t *d_nodes, int64_t q, int64_t n, int64_t *d_bad,
+                                hipStream_t s) {
+  clear_counter_kernel<<<1, 64, 0, s>>>(d_bad);
+  if (q > 0) {
+    const Grid g = geom_check_ids(q);
+    count_bad_ids_kernel<<<g.blocks, g.threads, 0, s>>>(d_nodes, q, n, d_bad);
+  }
+  return hipGetLastError();
 }
 
 hipError_t launch_query(damf_ctx *c, int which, int64_t q, const int32_t *d_nodes,
@@ -34,8 +69,9 @@ hipError_t launch_query(damf_ctx *c, int which, int64_t q, const int32_t *d_node
   const float *Mb = (which == DAMF_X) ? c->Ub : (which == DAMF_Y) ? c->Vb : c->Zb;
   const double *P = (which == DAMF_Y) ? c->P + (size_t)c->d * c->d : c->P;
   if (q <= 0) return hipSuccess;
-  query_kernel<<<ceil_div(q, 4), 256, 0, c->stream>>>(Mb, P, c->sigma, c->d, q, d_nodes,
-                                                       d_out, c->split && which != DAMF_Z);
+  const Grid g = geom_query(q);
+  query_kernel<<<g.blocks, g.threads, 0, c->stream>>>(Mb, P, c->sigma, c->d, q, d_nodes, d_out,
+                                                      c->split && which != DAMF_Z);
   return hipGetLastError();
 }
 
