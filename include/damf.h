@@ -235,6 +235,23 @@ damf_status damf_reorthogonalize(damf_ctx *ctx);
 damf_status damf_query(damf_ctx *ctx, damf_which which, int64_t q,
                        const int32_t *nodes, float *out, int32_t flags);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, serving loops that forbid hipMalloc): damf_query without any
+ * allocation.  Same arguments, layout and results as damf_query.  Its
+ * temporaries live in a fixed 4 MiB array that the library holds on each
+ * device for the life of the process: a 256-byte counter slot, then, with
+ * host pointers only, the q node ids (rounded up to 256 bytes) and the q x d
+ * output rows.  Limits: with host pointers 256 + round256(4 q) + 4 q d must
+ * not exceed 4 MiB (q <= 8,128 rows at d = 128, nodes given), else
+ * DAMF_E_INVALID_ARG; with DAMF_DEVICE_PTRS only the counter is used and q is
+ * not limited.  A Z query while Step 4 is pending (auto_enhance = 0) returns
+ * DAMF_E_INVALID_ARG (call damf_enhance first, which may allocate).  Every
+ * call on one device shares that array: calls that overlap on one device
+ * (contexts on different streams or threads) race and must be serialised by
+ * the caller.  Errors otherwise as damf_query. */
+damf_status damf_query_static(damf_ctx *ctx, damf_which which, int64_t q,
+                              const int32_t *nodes, float *out, int32_t flags);
+
 /* The d singular values, descending (host float64 array of d). */
 damf_status damf_singular_values(damf_ctx *ctx, double *out);
 

@@ -197,6 +197,7 @@ def lib():
     L.damf_flush.argtypes = [p]
     L.damf_reorthogonalize.argtypes = [p]
     L.damf_query.argtypes = [p, C.c_int, C.c_int64, p, p, C.c_int32]
+    L.damf_query_static.argtypes = [p, C.c_int, C.c_int64, p, p, C.c_int32]
     L.damf_singular_values.argtypes = [p, p]
     L.damf_export_csr.argtypes = [p, C.c_int32, p, p, C.POINTER(C.c_int64)]
     L.damf_export_state.argtypes = [p, p, p, p, p, p, p]
@@ -212,7 +213,7 @@ def lib():
     L.damf_status_string.argtypes = [C.c_int]
     L.damf_status_string.restype = C.c_char_p
     for name in ("damf_init", "damf_init_factors", "damf_update", "damf_enhance", "damf_flush",
-                 "damf_reorthogonalize", "damf_query",
+                 "damf_reorthogonalize", "damf_query", "damf_query_static",
                  "damf_singular_values", "damf_export_csr", "damf_export_state",
                  "damf_residual_max", "damf_sync", "damf_get_init_info", "damf_save", "damf_load"):
         getattr(L, name).restype = C.c_int
@@ -348,6 +349,24 @@ class Context:
             raise ValueError("nodes and out must both be host or both be device")
         self._check(lib().damf_query(self._h, WHICH[which], C.c_int64(q), pn, po,
                                      C.c_int32(DAMF_DEVICE_PTRS if odev else 0)))
+        return out
+
+    def query_static(self, which, nodes=None, out=None):
+        """damf_query_static: as query(), with no device allocation."""
+        if nodes is None:
+            q = self.n
+            pn = None
+            dev = False
+        else:
+            pn, dev, ka = _ptr(nodes, np.int32)
+            q = len(nodes)
+        if out is None:
+            out = np.empty((q, self.d), dtype=np.float32)
+        po, odev, kb = _ptr(out, np.float32)
+        if dev != odev and nodes is not None:
+            raise ValueError("nodes and out must both be host or both be device")
+        self._check(lib().damf_query_static(self._h, WHICH[which], C.c_int64(q), pn, po,
+                                            C.c_int32(DAMF_DEVICE_PTRS if odev else 0)))
         return out
 
     def singular_values(self):

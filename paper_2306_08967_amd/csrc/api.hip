@@ -222,6 +222,10 @@ damf_status new_ctx(const damf_config *cfg, damf_ctx **out, damf_ctx **cptr) {
     delete c;
     return DAMF_E_DEVICE;
   }
+  if (static_scratch_setup(c->device) != hipSuccess) {
+    delete c;
+    return DAMF_E_DEVICE;
+  }
   int khz = 0;
   if (hipDeviceGetAttribute(&khz, hipDeviceAttributeWallClockRate, c->device) == hipSuccess && khz > 0)
     c->wall_khz = (double)khz;
@@ -703,6 +707,54 @@ damf_status damf_query(damf_ctx *c, damf_which which, int64_t q, const int32_t *
   API_HIP(c, hipStreamSynchronize(s), "query");
   if (own_n) (void)hipFree(own_n);
   if (own_o) (void)hipFree(own_o);
+  return DAMF_OK;
+}
+
+damf_status damf_query_static(damf_ctx *c, damf_which which, int64_t q, const int32_t *nodes,
+                              float *out, int32_t flags) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  if (which < DAMF_X || which > DAMF_Z || q < 0 || !out) return fail(c, DAMF_E_INVALID_ARG, "bad query");
+  if (!nodes && q != c->n) return fail(c, DAMF_E_INVALID_ARG, "q must be n without a node list");
+  if (q == 0) return DAMF_OK;
+  const int d = c->d;
+  hipStream_t s = c->stream;
+  if (which == DAMF_Z && !c->ppr_on) which = DAMF_X;  // alpha = 1: Z = X
+  // Step 4 may grow its workspace, so a pending enhancement is not run here
+  if (which == DAMF_Z && c->enhance_pending)
+    return fail(c, DAMF_E_INVALID_ARG, "Z query with Step 4 pending: call damf_enhance first");
+  const bool dev = (flags & DAMF_DEVICE_PTRS) != 0;
+  // scratch layout: counter slot [0, 256); ids from 256; rows after the ids
+  const size_t ids_bytes = (!dev && nodes) ? (((size_t)q * sizeof(int32_t) + 255) / 256) * 256 : 0;
+  const size_t need = dev ? 256 : 256 + ids_bytes + (size_t)q * d * sizeof(float);
+  if (need > kStaticScratchBytes)
+    return fail(c, DAMF_E_INVALID_ARG, "query larger than the 4 MiB static scratch (host pointers)");
+  unsigned char *base = static_cast<unsigned char *>(static_scratch_ptr(c->device));
+  if (!base) return fail(c, DAMF_E_STATE, "static scratch not set up on this device");
+  int64_t *bad = reinterpret_cast<int64_t *>(base);
+  const int32_t *dn = nodes;
+  float *dout = out;
+  if (dev && nodes) {
+    API_HIP(c, launch_count_bad_ids(nodes, q, c->n, bad, s), "query id check");
+    API_HIP(c, hipMemcpyAsync(c->ws.counters_host + 12, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s),
+            "query id check");
+    API_HIP(c, hipStreamSynchronize(s), "query id check");
+    if (c->ws.counters_host[12] != 0) return fail(c, DAMF_E_OUT_OF_RANGE, "query id out of range");
+  }
+  if (!dev) {
+    if (nodes) {
+      for (int64_t i = 0; i < q; ++i)
+        if (nodes[i] < 0 || nodes[i] >= c->n) return fail(c, DAMF_E_OUT_OF_RANGE, "query id out of range");
+      int32_t *ids = reinterpret_cast<int32_t *>(base + 256);
+      API_HIP(c, hipMemcpyAsync(ids, nodes, q * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy query");
+      dn = ids;
+    }
+    dout = reinterpret_cast<float *>(base + 256 + ids_bytes);
+  }
+  API_HIP(c, launch_query(c, which, q, dn, dout), "query");
+  if (!dev)
+    API_HIP(c, hipMemcpyAsync(out, dout, (size_t)q * d * sizeof(float), hipMemcpyDeviceToHost, s), "copy query");
+  API_HIP(c, hipStreamSynchronize(s), "query");
   return DAMF_OK;
 }
 

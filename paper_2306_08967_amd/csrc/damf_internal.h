@@ -246,6 +246,14 @@ hipError_t launch_query(damf_ctx *c, int which, int64_t q,
 // *d_bad = number of ids of d_nodes[0..q) outside [0, n) (cleared first)
 hipError_t launch_count_bad_ids(const int32_t *d_nodes, int64_t q, int64_t n, int64_t *d_bad,
                                 hipStream_t s);
+// Fixed per-device scratch of damf_query_static: a 256-byte counter slot,
+// then (host pointers only) the node ids and the output rows.
+constexpr size_t kStaticScratchBytes = size_t(4) << 20;
+// Looks up this device's address of the scratch array (once per device;
+// the device must be current).  Called by context creation.
+hipError_t static_scratch_setup(int device);
+// That address, or nullptr before static_scratch_setup(device) succeeded.
+void *static_scratch_ptr(int device);
 
 }  // namespace damf
 

@@ -3,6 +3,8 @@
 // device node lists.
 #include <hip/hip_runtime.h>
 
+#include <mutex>
+
 #include "common.h"
 #include "damf_internal.h"
 
@@ -73,6 +75,37 @@ hipError_t launch_query(damf_ctx *c, int which, int64_t q, const int32_t *d_node
   query_kernel<<<g.blocks, g.threads, 0, c->stream>>>(Mb, P, c->sigma, c->d, q, d_nodes, d_out,
                                                       c->split && which != DAMF_Z);
   return hipGetLastError();
+}
+
+// ---- fixed scratch of damf_query_static, for callers that cannot allocate.
+// Each device holds its own copy of the array until the process ends; host
+// code reaches it only through the address hipGetSymbolAddress returns on
+// that device (static_scratch_setup, called once per device by context
+// creation with the device current).
+static __device__ __align__(256) unsigned char scratch[kStaticScratchBytes];
+
+namespace {
+constexpr int kMaxDevices = 64;
+void *g_scratch_ptr[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+}  // namespace
+
+hipError_t static_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_ptr[device]) return hipSuccess;
+  void *ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  if (e != hipSuccess) return e;
+  if (!ptr) return hipErrorInvalidSymbol;
+  g_scratch_ptr[device] = ptr;
+  return hipSuccess;
+}
+
+void *static_scratch_ptr(int device) {
+  if (device < 0 || device >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  return g_scratch_ptr[device];
 }
 
 }  // namespace damf
