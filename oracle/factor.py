@@ -52,12 +52,14 @@ def _qr_q(M):
     return q
 
 
-def tsvd_randomized(A, d, oversample, power_iters, seed):
+def tsvd_randomized(A, d, oversample, power_iters, seed, full_spectrum=False):
     """Randomized rank-d t-SVD of a (sparse or dense) A, in the order the GPU follows.
 
     Y = A Omega, Q = qr(Y); q times: Q = qr(A^T Q), Q = qr(A Q);
     B^T = A^T Q = Q2 R2; svd(R2^T) = Ut S Vt;  U = Q Ut[:, :d], V = Q2 Vt^T[:, :d].
     Then A ~ Q Q^T A = Q B = (Q Ut) S (Q2 Vt^T)^T.
+    With full_spectrum, also returns all d + p singular values of R2^T (the
+    gap after the d-th one decides how well the truncation is determined).
     """
     n = A.shape[0]
     l = d + oversample
@@ -72,4 +74,6 @@ def tsvd_randomized(A, d, oversample, power_iters, seed):
     U = Q @ Ut[:, :d]
     V = Q2 @ Vth.T[:, :d]
     assert U.shape == (n, d)
+    if full_spectrum:
+        return U, s[:d].copy(), V, s.copy()
     return U, s[:d].copy(), V
