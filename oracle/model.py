@@ -16,7 +16,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from . import factor, ppr, update
+from . import factor, node, ppr, update
 from .graph import EdgeSet
 
 
@@ -58,6 +58,27 @@ class DAMFOracle:
                 self.U, self.s, self.V, S1, S2, D, self.tau)
             infos.append(dict(s1=len(S1), s2=len(S2), rho_b=info["rho_b"], rho_c=info["rho_c"]))
         return dict(net=net, chunks=chunks, chunk_info=infos)
+
+    # ---- node change (Algorithm 2, node branch; Theorem 1)
+    def add_node(self, new, in_nbrs, out_nbrs=()):
+        """Node `new`, without edges so far, joins with in-edges (v, new) and
+        out-edges (new, w) (undirected: the neighbours in in_nbrs): the graph
+        gains the edges, and the factorisation takes Theorem 1's column step
+        then its row step, each cut into pieces of at most r_max entries."""
+        if any(u == new or v == new for (u, v) in self.graph.E):
+            raise ValueError("node change needs a node without edges")
+        ins = [int(v) for v in in_nbrs]
+        outs = ins if not self.directed else [int(w) for w in out_nbrs]
+        if self.directed:
+            src = [v for v in ins] + [new] * len(outs)
+            dst = [new] * len(ins) + outs
+        else:
+            src, dst = [new] * len(ins), ins
+        self.graph.apply(np.array(src, dtype=np.int64), np.array(dst, dtype=np.int64),
+                         np.ones(len(src), dtype=np.int64))
+        self.U, self.s, self.V, info = node.node_event(self.U, self.s, self.V, new, ins, outs,
+                                                       self.tau, self.r_max)
+        return info
 
     # ---- query (Sec. 4.1 and Sec. 4.4)
     def X(self):
