@@ -9,6 +9,7 @@ from .graphs import (  # noqa: F401
     chung_lu_directed,
     rmat_directed,
     block_graph,
+    planted_directed,
     EdgeStream,
     c1_workload,
     c2_workload,

@@ -73,6 +73,24 @@ def er_undirected(n, m, seed):
     return _distinct_fill(draw, m, rng, undirected=True)
 
 
+def planted_directed(n, m, blocks, inside, seed):
+    """Directed planted-partition graph: ``m`` distinct loop-free edges; with
+    probability ``inside`` an edge joins two uniform nodes of one uniform block
+    (blocks are contiguous id ranges of n // blocks nodes), else two uniform
+    nodes.  Low-rank structure for link-prediction checks."""
+    rng = np.random.default_rng(seed)
+    size = n // blocks
+
+    def draw(c, r):
+        inb = r.random(c) < inside
+        b = r.integers(0, blocks, c)
+        u = np.where(inb, b * size + r.integers(0, size, c), r.integers(0, n, c))
+        v = np.where(inb, b * size + r.integers(0, size, c), r.integers(0, n, c))
+        return u, v
+
+    return _distinct_fill(draw, m, rng, undirected=False)
+
+
 def _chung_lu_weights(n, m, beta):
     """w_i = (i + i0)^(-1/(beta-1)), with i0 chosen so the largest expected degree is sqrt(m)."""
     gamma = 1.0 / (beta - 1.0)
@@ -262,7 +280,8 @@ def chung_lu_workload(n, m, beta, seed, batches, batch, insert_frac, d=128,
     init = (src[:n_init].copy(), dst[:n_init].copy())
     stream_gen = EdgeStream(n, init[0], init[1], seed + 1000)
     stream = [stream_gen.batch(batch, insert_frac) for _ in range(batches)]
-    return dict(n=n, d=d, directed=True, init=init, stream=stream)
+    heldout = (src[n_init:].copy(), dst[n_init:].copy())
+    return dict(n=n, d=d, directed=True, init=init, stream=stream, heldout=heldout)
 
 
 def c2_workload(seed=2, n=1_000_000, m=10_000_000, batches=1000, batch=1000):
