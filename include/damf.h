@@ -52,7 +52,7 @@ typedef enum {
 
 typedef enum { DAMF_X = 0, DAMF_Y = 1, DAMF_Z = 2 } damf_which;
 
-enum { DAMF_DEVICE_PTRS = 1 };
+enum { DAMF_DEVICE_PTRS = 1, DAMF_SCORE_BOTH_WAYS = 2 };
 
 /* Configuration.  Fill with damf_config_default() and override fields. */
 typedef struct {
@@ -95,6 +95,24 @@ typedef struct {
                             and 1e-8 for the precision form, whose stored
                             bases carry about 16 significant bits.  Valid:
                             0, or 1e-14 .. 1e-6                            */
+  double flush_cond;     /* lazy projection limit (Sec. 4.1 lazy update): after
+                            a batch whose new P has a condition estimate
+                            (LU pivot spread) above flush_cond, damf_update
+                            flushes (as damf_flush) before Step 4, since the
+                            FP32 rounding of the stored bases is amplified by
+                            up to cond(P) in U = U_b P.  0 (default) means
+                            1e3; a negative value never flushes; else >= 1.
+                            A single chunk whose new P passes max(flush_cond,
+                            1e3) is applied explicitly (see damf_update)   */
+  int32_t graph_chunks;  /* 0 (default): Steps 1-3 are launched kernel by kernel.
+                            1..64: a batch of at most graph_chunks chunks runs
+                            its Steps 1-3 launches (four per chunk on two
+                            streams) as one captured HIP graph, built on the
+                            first batch of its shape (chunk count and which
+                            chunks wait for their predecessor) and replayed
+                            after; results are bit-identical.  Ignored while
+                            kernel_timing = 1                               */
+  int32_t pad0_;
 } damf_config;
 
 /* Per-batch statistics written by damf_update when `info` is non-NULL. */
@@ -127,6 +145,24 @@ typedef struct {
                              sweeps x N(N-1)/2 pairs x (2N for the dot + 6N f
                              for the rotation, f the share of steps in which
                              any pair rotated) + 2N^2 d (H) + 2N^2 k (K)      */
+  double core_flops_model; /* the same launches priced by the textbook count of
+                             one-sided Jacobi: 9 N^3 FP64 flops per sweep (the
+                             dots, the column rotation and the accumulation of
+                             the right vectors, which this kernel forms after
+                             the sweeps as H = K^T E instead)              */
+  double p_cond;          /* condition estimate of the projections after the
+                             chunks (largest LU pivot spread; 1 after a flush) */
+  int32_t flushed;        /* 1: this batch flushed P (flush_cond reached)      */
+  int32_t explicit_chunks;/* chunks whose new projection was too ill-conditioned
+                             and that were applied explicitly (damf_update)    */
+  int64_t graph_launches; /* batches of the context so far whose Steps 1-3 ran
+                             as a captured graph (graph_chunks)                */
+  int32_t small_sv_columns;/* right singular vectors of the cores that were
+                             re-orthogonalised because their singular value
+                             was below 1e7 jacobi_tol sigma_1 (H = K^T E
+                             Theta^-1 amplifies E's residual non-orthogonality
+                             by sigma_1 / theta there)                        */
+  int32_t pad1_;
 } damf_batch_info;
 
 /* Statistics of the initialisation (damf_init / damf_init_factors). */
@@ -175,8 +211,18 @@ damf_status damf_init_factors(const damf_config *cfg, int64_t m,
  * absent one changes nothing).  The net change of A is cut into chunks of
  * rank <= r; each chunk is one Steps 1-3 update (Theorem 2 with B, C of k
  * columns).  Then Step 4 runs if auto_enhance.  0 <= k <= 8192; k == 0 is a
- * no-op.  Errors: DAMF_E_INVALID_ARG, DAMF_E_OUT_OF_RANGE (state unchanged),
- * DAMF_E_NUMERIC, DAMF_E_DEVICE. */
+ * no-op.  The lazy update keeps U = U_b P and solves with the new P, so the
+ * FP32 rounding of the rows it writes is amplified by up to cond(P).  When a
+ * chunk's new P has a condition estimate (LU pivot spread) above
+ * max(flush_cond, 1e3) (above 1e10 when flushing is off), such as when a kept
+ * direction has almost no component in span(U) (an edge between two nodes
+ * without basis weight while a zero singular value is kept), the batch's
+ * chunks are undone and re-run one by one, and that chunk is applied
+ * explicitly (every row rotated by P F, then its row corrections with P = I);
+ * info->explicit_chunks counts them.  Errors: DAMF_E_INVALID_ARG,
+ * DAMF_E_OUT_OF_RANGE (state unchanged), DAMF_E_NUMERIC (non-finite values
+ * in the core: the state is corrupt and the context is poisoned),
+ * DAMF_E_DEVICE. */
 damf_status damf_update(damf_ctx *ctx, int64_t k, const int32_t *src,
                         const int32_t *dst, const int8_t *op, int32_t flags,
                         damf_batch_info *info);
@@ -202,6 +248,31 @@ damf_status damf_update_requests(damf_ctx *ctx, int32_t nreq, const int64_t *req
                                  const int8_t *op, int32_t flags,
                                  damf_batch_info *info,
                                  damf_request_stats *per_request);
+
+/* Node change (Sec. 4.2, Theorem 1; Algorithm 2, node branch).  Node `node`,
+ * which must have no edges yet (a free slot of the fixed node range), joins
+ * with in-edges (v, node) for v in in_nbrs and out-edges (node, w) for w in
+ * out_nbrs.  The update runs Theorem 1's two steps: the column step
+ * A' = [A, B1] with B1 the in-edges (a self-loop excluded), then the row step
+ * with B2 the out-edges and the self-loop (node, node) when either list
+ * names `node`.  Each step is one rank-1 space projection ((d+1) x (d+1)
+ * core); a step with more than max_side (r_max) entries is applied as
+ * consecutive rank-1 pieces of at most r_max entries, the first Theorem 1's
+ * step and the later ones edge updates of the existing column (row).  Then
+ * Step 4 runs if auto_enhance.  Undirected graphs: the neighbours go in
+ * in_nbrs and k_out must be 0 (the row step takes the same list).  Host
+ * arrays; duplicates collapse; k_in + k_out <= 8192.  Errors:
+ * DAMF_E_OUT_OF_RANGE (an id outside [0, n)), DAMF_E_INVALID_ARG (the node
+ * has edges, bad sizes or lists), both with the state unchanged; otherwise as
+ * damf_update.  info (nullable) as damf_update's. */
+damf_status damf_add_node(damf_ctx *ctx, int32_t node, int64_t k_in, const int32_t *in_nbrs,
+                          int64_t k_out, const int32_t *out_nbrs, damf_batch_info *info);
+
+/* Chunk rank r (max_core_rank) for the batches that follow: 1 <= r <= max_side
+ * and d + r <= 192, else DAMF_E_INVALID_ARG.  The chunking of a batch depends
+ * on r, so the factorisation after a batch does too (the serving tuner
+ * changes it; a replay sets the rank each request reports). */
+damf_status damf_set_chunk_rank(damf_ctx *ctx, int32_t r);
 
 /* Step 4 (Sec. 4.4): push PPR residuals until max |R| <= eps. */
 damf_status damf_enhance(damf_ctx *ctx);
@@ -251,6 +322,19 @@ damf_status damf_query(damf_ctx *ctx, damf_which which, int64_t q,
  * the caller.  Errors otherwise as damf_query. */
 damf_status damf_query_static(damf_ctx *ctx, damf_which which, int64_t q,
                               const int32_t *nodes, float *out, int32_t flags);
+
+/* Link scores (Sec. 5.2 link prediction and graph reconstruction; the
+ * appendix on link prediction): out[i] = <A[u[i]], B[v[i]]> where A and B
+ * are the rows of X, Y or Z chosen by which_a and which_b (the paper scores a
+ * pair (u, v) by u's context vector, Z, against v's content vector, Y).
+ * With DAMF_SCORE_BOTH_WAYS in flags, out[i] = max(<A[u], B[v]>,
+ * <A[v], B[u]>), the paper's score for undirected graphs.  u, v: q int32 ids;
+ * out: q float32 (host, or device with DAMF_DEVICE_PTRS).  Rows are formed
+ * as in damf_query (FP64 accumulation); a Z side runs a pending Step 4
+ * first.  Errors: DAMF_E_OUT_OF_RANGE (an id outside [0, n)),
+ * DAMF_E_INVALID_ARG, DAMF_E_DEVICE. */
+damf_status damf_score_pairs(damf_ctx *ctx, damf_which which_a, damf_which which_b, int64_t q,
+                             const int32_t *u, const int32_t *v, float *out, int32_t flags);
 
 /* The d singular values, descending (host float64 array of d). */
 damf_status damf_singular_values(damf_ctx *ctx, double *out);

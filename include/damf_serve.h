@@ -1,9 +1,12 @@
 /* damf_serve.h -- continuous-batching update server on one DAMF context.
  *
- * Clients submit edge-update requests (batches of edits of any size up to
- * 8192 ops) from any thread; a server thread admits them by memory, coalesces
- * every admitted request that fits into the next update step, and runs the
- * steps back to back.  The result equals applying the requests one by one in
+ * Clients submit edge-update requests (batches of edits, up to
+ * max_request_ops each) from any thread; a server thread admits them by
+ * memory (host staging, and the device memory their graph edits may claim),
+ * coalesces every admitted request that fits into the next update step, and
+ * runs the steps back to back.  A request longer than max_step_ops runs alone
+ * as consecutive parts of max_step_ops ops (its ops in order: the graph ends
+ * as after one batch; the factorisation follows the parts' chunks).  The result equals applying the requests one by one in
  * admission order with damf_update (Algorithm 2's per-event loop with one
  * request as the event): within a step, each request's net change is taken
  * against the graph the earlier requests leave and no chunk mixes two
@@ -36,6 +39,21 @@ typedef struct {
   int32_t overlap_push;      /* 1: a step's Step 4 overlaps the next step (1)  */
   int32_t start_paused;      /* 1: admit but do not start steps until
                                 damf_server_resume (0)                         */
+  int64_t admit_device_bytes;/* admission cap on the device memory admitted,
+                                incomplete requests may claim: 24 bytes per op
+                                (a CSR entry in the out- and in-pools, with a
+                                moved row's reservation and the copy compaction
+                                frees later); 0 (default): half the device
+                                memory free when the server starts           */
+  int32_t max_request_ops;   /* largest request, 1..2^20 (65536)               */
+  int32_t autotune;          /* 1: pick the chunk rank r (max_core_rank) among
+                                16, 32, 48, 64 (those <= max_side and
+                                d + r <= 192): 4 steps at each, the rank with
+                                the least Steps 1-3 time per net entry is kept
+                                and appended to tune_cache; a cache entry for
+                                the same device architecture, n, d, precision
+                                and log2(m) is used without tuning (0)       */
+  const char *tune_cache;    /* tuner cache file path, or NULL (NULL)          */
 } damf_server_config;
 
 /* Per-request result, filled by damf_wait. */
@@ -51,6 +69,8 @@ typedef struct {
   double start_us;           /* its step started                               */
   double done_us;            /* visible                                        */
   double latency_ms;         /* done - submit                                  */
+  int32_t parts;             /* steps that carried it (> 1 above max_step_ops) */
+  int32_t chunk_rank;        /* r of its (last) step, for an exact replay      */
 } damf_request_info;
 
 typedef struct {
@@ -68,6 +88,11 @@ typedef struct {
   double mean_requests_per_step;
   double mean_ops_per_step;
   double push_overlapped_ms; /* Step 4 time that ran beside a chain kernel     */
+  int64_t admitted_device_bytes_peak;
+  int64_t device_cap_bytes;  /* the device admission cap in force               */
+  int32_t tuned_chunk_rank;  /* the tuner's choice (0: not tuned)               */
+  int32_t pad_;
+  int64_t tuner_steps;       /* steps the tuner measured                        */
 } damf_server_stats;
 
 void damf_server_config_default(damf_server_config *cfg);
@@ -78,9 +103,9 @@ damf_status damf_server_create(damf_ctx *ctx, const damf_server_config *cfg,
                                damf_server **out);
 
 /* Admits one request: k ops (host arrays, read during the call; ids in
- * [0, n), op +1 insert / -1 delete), 1 <= k <= max_step_ops.  On success
+ * [0, n), op +1 insert / -1 delete), 1 <= k <= max_request_ops.  On success
  * *ticket identifies it.  DAMF_E_BUSY: admitting it would exceed admit_bytes
- * (nothing is kept; retry after requests complete).  DAMF_E_OUT_OF_RANGE /
+ * or the device cap (nothing is kept; retry after requests complete).  DAMF_E_OUT_OF_RANGE /
  * DAMF_E_INVALID_ARG: bad ops or size (nothing is kept).  DAMF_E_STATE: the
  * server stopped after a device error. */
 damf_status damf_submit(damf_server *srv, int64_t k, const int32_t *src, const int32_t *dst,

@@ -25,6 +25,7 @@ DAMF_E_STATE = 6
 DAMF_E_BUSY = 7
 DAMF_E_TIMEOUT = 8
 DAMF_DEVICE_PTRS = 1
+DAMF_SCORE_BOTH_WAYS = 2
 WHICH = {"X": 0, "Y": 1, "Z": 2}
 
 
@@ -48,6 +49,9 @@ class DamfConfig(C.Structure):
         ("precision", C.c_int32),
         ("kernel_timing", C.c_int32),
         ("jacobi_tol", C.c_double),
+        ("flush_cond", C.c_double),
+        ("graph_chunks", C.c_int32),
+        ("pad0_", C.c_int32),
     ]
 
 
@@ -74,6 +78,13 @@ class DamfBatchInfo(C.Structure):
         ("ms_core_kernel", C.c_double),
         ("core_launches", C.c_int64),
         ("core_flops", C.c_double),
+        ("core_flops_model", C.c_double),
+        ("p_cond", C.c_double),
+        ("flushed", C.c_int32),
+        ("explicit_chunks", C.c_int32),
+        ("graph_launches", C.c_int64),
+        ("small_sv_columns", C.c_int32),
+        ("pad1_", C.c_int32),
     ]
 
     def as_dict(self):
@@ -109,6 +120,10 @@ class DamfServerConfig(C.Structure):
         ("max_step_requests", C.c_int32),
         ("overlap_push", C.c_int32),
         ("start_paused", C.c_int32),
+        ("admit_device_bytes", C.c_int64),
+        ("max_request_ops", C.c_int32),
+        ("autotune", C.c_int32),
+        ("tune_cache", C.c_char_p),
     ]
 
 
@@ -125,6 +140,8 @@ class DamfRequestInfo(C.Structure):
         ("start_us", C.c_double),
         ("done_us", C.c_double),
         ("latency_ms", C.c_double),
+        ("parts", C.c_int32),
+        ("chunk_rank", C.c_int32),
     ]
 
     def as_dict(self):
@@ -147,6 +164,11 @@ class DamfServerStats(C.Structure):
         ("mean_requests_per_step", C.c_double),
         ("mean_ops_per_step", C.c_double),
         ("push_overlapped_ms", C.c_double),
+        ("admitted_device_bytes_peak", C.c_int64),
+        ("device_cap_bytes", C.c_int64),
+        ("tuned_chunk_rank", C.c_int32),
+        ("pad_", C.c_int32),
+        ("tuner_steps", C.c_int64),
     ]
 
     def as_dict(self):
@@ -182,6 +204,8 @@ def lib():
     L.damf_update_requests.argtypes = [p, C.c_int32, C.POINTER(C.c_int64), p, p, p, C.c_int32,
                                        C.POINTER(DamfBatchInfo), C.POINTER(DamfRequestStats)]
     L.damf_enhance.argtypes = [p]
+    L.damf_set_chunk_rank.argtypes = [p, C.c_int32]
+    L.damf_add_node.argtypes = [p, C.c_int32, C.c_int64, p, C.c_int64, p, C.POINTER(DamfBatchInfo)]
     L.damf_server_config_default.argtypes = [C.POINTER(DamfServerConfig)]
     L.damf_server_config_default.restype = None
     L.damf_server_create.argtypes = [p, C.POINTER(DamfServerConfig), C.POINTER(p)]
@@ -199,6 +223,7 @@ def lib():
     L.damf_query.argtypes = [p, C.c_int, C.c_int64, p, p, C.c_int32]
     L.damf_query_static.argtypes = [p, C.c_int, C.c_int64, p, p, C.c_int32]
     L.damf_singular_values.argtypes = [p, p]
+    L.damf_score_pairs.argtypes = [p, C.c_int, C.c_int, C.c_int64, p, p, p, C.c_int32]
     L.damf_export_csr.argtypes = [p, C.c_int32, p, p, C.POINTER(C.c_int64)]
     L.damf_export_state.argtypes = [p, p, p, p, p, p, p]
     L.damf_residual_max.argtypes = [p, C.POINTER(C.c_double)]
@@ -212,9 +237,11 @@ def lib():
     L.damf_last_error.restype = C.c_char_p
     L.damf_status_string.argtypes = [C.c_int]
     L.damf_status_string.restype = C.c_char_p
-    for name in ("damf_init", "damf_init_factors", "damf_update", "damf_enhance", "damf_flush",
+    for name in ("damf_init", "damf_init_factors", "damf_update", "damf_add_node", "damf_enhance",
+                 "damf_set_chunk_rank",
+                 "damf_flush",
                  "damf_reorthogonalize", "damf_query", "damf_query_static",
-                 "damf_singular_values", "damf_export_csr", "damf_export_state",
+                 "damf_singular_values", "damf_score_pairs", "damf_export_csr", "damf_export_state",
                  "damf_residual_max", "damf_sync", "damf_get_init_info", "damf_save", "damf_load"):
         getattr(L, name).restype = C.c_int
     del i32p
@@ -325,6 +352,21 @@ class Context:
                                                C.byref(info), per))
         return info.as_dict(), [dict(net_entries=x.net_entries, chunks=x.chunks) for x in per]
 
+    def add_node(self, node, in_nbrs, out_nbrs=()):
+        """Node change (damf_add_node): `node` joins with in-edges (v, node) and
+        out-edges (node, w); undirected graphs take the neighbours in in_nbrs."""
+        a = np.ascontiguousarray(np.asarray(in_nbrs, dtype=np.int32))
+        b = np.ascontiguousarray(np.asarray(out_nbrs, dtype=np.int32))
+        info = DamfBatchInfo()
+        self._check(lib().damf_add_node(self._h, C.c_int32(int(node)), C.c_int64(len(a)),
+                                        a.ctypes.data_as(C.c_void_p), C.c_int64(len(b)),
+                                        b.ctypes.data_as(C.c_void_p), C.byref(info)))
+        return info.as_dict()
+
+    def set_chunk_rank(self, r):
+        """damf_set_chunk_rank: chunk rank r for the batches that follow."""
+        self._check(lib().damf_set_chunk_rank(self._h, C.c_int32(int(r))))
+
     def enhance(self):
         self._check(lib().damf_enhance(self._h))
 
@@ -367,6 +409,25 @@ class Context:
             raise ValueError("nodes and out must both be host or both be device")
         self._check(lib().damf_query_static(self._h, WHICH[which], C.c_int64(q), pn, po,
                                             C.c_int32(DAMF_DEVICE_PTRS if odev else 0)))
+        return out
+
+    def score_pairs(self, u, v, which_a="Z", which_b="Y", both_ways=False, out=None):
+        """damf_score_pairs: <A[u_i], B[v_i]> (max over both directions with both_ways)."""
+        pu, dev, ka = _ptr(u, np.int32)
+        pv, dev2, kb = _ptr(v, np.int32)
+        if dev != dev2:
+            raise ValueError("u and v must both be host or both be device")
+        q = len(u)
+        if out is None:
+            if dev:
+                import torch
+                out = torch.empty(q, dtype=torch.float32, device=u.device)
+            else:
+                out = np.empty(q, dtype=np.float32)
+        po, odev, kc = _ptr(out, np.float32)
+        flags = (DAMF_DEVICE_PTRS if dev else 0) | (DAMF_SCORE_BOTH_WAYS if both_ways else 0)
+        self._check(lib().damf_score_pairs(self._h, WHICH[which_a], WHICH[which_b], C.c_int64(q),
+                                           pu, pv, po, C.c_int32(flags)))
         return out
 
     def singular_values(self):
@@ -443,6 +504,8 @@ def server_config(**kw):
     for k, v in kw.items():
         if not hasattr(cfg, k):
             raise KeyError(k)
+        if k == "tune_cache" and isinstance(v, str):
+            v = os.fsencode(v)
         setattr(cfg, k, v)
     return cfg
 

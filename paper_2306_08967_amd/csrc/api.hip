@@ -66,6 +66,8 @@ damf_status check_config(const damf_config *cfg) {
   if (cfg->kernel_timing != 0 && cfg->kernel_timing != 1) return DAMF_E_INVALID_ARG;
   if (!(cfg->jacobi_tol == 0.0 || (cfg->jacobi_tol >= 1e-14 && cfg->jacobi_tol <= 1e-6)))
     return DAMF_E_INVALID_ARG;
+  if (!(cfg->flush_cond <= 0.0 || cfg->flush_cond >= 1.0)) return DAMF_E_INVALID_ARG;
+  if (cfg->graph_chunks < 0 || cfg->graph_chunks > 64) return DAMF_E_INVALID_ARG;
   return DAMF_OK;
 }
 
@@ -111,6 +113,9 @@ damf_status alloc_state(damf_ctx *c) {
   API_HIP(c, hipHostMalloc((void **)&w.cstats_host, sizeof(ChainStats)), "alloc pinned");
   w.scratch_doubles = chain_scratch_doubles();
   API_HIP(c, dalloc(&w.scratch, w.scratch_doubles), "alloc scratch");
+  API_HIP(c, dalloc(&w.undo_u, (size_t)(2 * kMaxBatch + kMaxSide) * d), "alloc undo log");
+  API_HIP(c, dalloc(&w.undo_v, (size_t)(2 * kMaxBatch + kMaxSide) * d), "alloc undo log");
+  API_HIP(c, dalloc(&w.psave, 2 * (size_t)d * d + kMaxCore), "alloc undo log");
   API_HIP(c, dalloc(&w.counters, 16), "alloc ws");
   API_HIP(c, hipHostMalloc((void **)&w.counters_host, 16 * sizeof(int64_t)), "alloc pinned");
   API_HIP(c, hipHostMalloc((void **)&w.dscratch_host, 16 * sizeof(double)), "alloc pinned");
@@ -146,7 +151,7 @@ void free_ctx(damf_ctx *c) {
                   c->ws.cand2, c->ws.frontier, c->ws.unit_seg, c->ws.units_comb,
                   c->ws.seg_end, c->ws.seg_stats, c->ws.pend_rows, c->ws.edit_stage,
                   c->ws.edit_stage_top, c->ws.hbuf, c->ws.hnode, c->ws.hseg,
-                  c->ws.push_ring, c->ws.push_log};
+                  c->ws.push_ring, c->ws.push_log, c->ws.undo_u, c->ws.undo_v, c->ws.psave};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->ws.hdr_host) (void)hipHostFree(c->ws.hdr_host);
@@ -165,6 +170,8 @@ void free_ctx(damf_ctx *c) {
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->ev_scatter)
     if (e) (void)hipEventDestroy(e);
+  for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+  c->graphs.clear();
   if (c->scatter_stream) {
     (void)hipStreamSynchronize(c->scatter_stream);
     (void)hipStreamDestroy(c->scatter_stream);
@@ -322,9 +329,131 @@ damf_status step_graph(damf_ctx *c, const BatchHeader &h) {
 damf_status step_chain(damf_ctx *c, const BatchHeader &h) {
   if (h.n_chunks <= 0) return DAMF_OK;
   hipStream_t s = c->stream;
+  // undo log: the touched rows of U_b, V_b, and P, Sigma before the chunks
+  const size_t dd = 2 * (size_t)c->d * c->d;
+  API_HIP(c, launch_undo_rows(c, 0, h.s1_total, 0, h.s2_total, false), "undo log");
+  API_HIP(c, hipMemcpyAsync(c->ws.psave, c->P, dd * sizeof(double), hipMemcpyDeviceToDevice, s), "undo log");
+  API_HIP(c, hipMemcpyAsync(c->ws.psave + dd, c->sigma, kMaxCore * sizeof(double), hipMemcpyDeviceToDevice, s),
+          "undo log");
   API_HIP(c, hipEventRecord(c->ev[4], s), "event");
-  API_HIP(c, launch_chain(c, h.n_chunks, h.meets_prev), "chain");
+  bool graphed = false;
+  API_HIP(c, launch_chain_graph(c, h.n_chunks, h.meets_prev, &graphed), "chain (graph)");
+  if (graphed)
+    ++c->graph_launches;
+  else
+    API_HIP(c, launch_chain(c, 0, h.n_chunks, h.n_chunks, h.meets_prev), "chain");
   API_HIP(c, hipEventRecord(c->ev[5], s), "event");
+  return DAMF_OK;
+}
+
+namespace {
+
+void add_stats(ChainStats &a, const ChainStats &b, bool with_cond) {
+  a.max_core = std::max(a.max_core, b.max_core);
+  a.dropped += b.dropped;
+  a.sweeps += b.sweeps;
+  a.flops += b.flops;
+  a.core_flops += b.core_flops;
+  a.core_flops_model += b.core_flops_model;
+  a.small_sv_columns += b.small_sv_columns;
+  for (int i = 0; i < 8; ++i) a.phase_ticks[i] += b.phase_ticks[i];
+  if (with_cond) a.p_cond_bits = std::max(a.p_cond_bits, b.p_cond_bits);
+}
+
+// A chunk left a projection P F too ill-conditioned for the lazy scatter (a
+// kept direction with little or no component in span(U_b P), e.g. an edge
+// between two nodes without basis weight while a zero singular value is
+// kept): its solve would amplify the FP32 rounding of the rows it writes by
+// cond(P F), or fail.  Undo the batch's chunks and run them again one by
+// one; a chunk whose new projection passes the limit is applied explicitly,
+// U_b <- U_b P F + dU (the flush rotation by P F over all rows, then the row
+// corrections with P = I), which is the update of Theorem 2 without the lazy
+// projection.
+damf_status chain_recover(damf_ctx *c, const BatchHeader &h, ChainStats *out) {
+  hipStream_t s = c->stream;
+  Workspace &w = c->ws;
+  const size_t dd = 2 * (size_t)c->d * c->d;
+  API_HIP(c, launch_undo_rows(c, 0, h.s1_total, 0, h.s2_total, true), "undo");
+  API_HIP(c, hipMemcpyAsync(c->P, w.psave, dd * sizeof(double), hipMemcpyDeviceToDevice, s), "undo");
+  API_HIP(c, hipMemcpyAsync(c->sigma, w.psave + dd, kMaxCore * sizeof(double), hipMemcpyDeviceToDevice, s),
+          "undo");
+  std::vector<ChunkDesc> desc;
+  try {
+    desc.resize(h.n_chunks);
+  } catch (...) {
+    return fail(c, DAMF_E_OOM, "host memory");
+  }
+  API_HIP(c, hipMemcpyAsync(desc.data(), w.chunks, h.n_chunks * sizeof(ChunkDesc), hipMemcpyDeviceToHost, s),
+          "chunk list");
+  API_HIP(c, hipStreamSynchronize(s), "chunk list");
+  ChainStats acc{};
+  for (int ch = 0; ch < h.n_chunks; ++ch) {
+    // the chunk's own rows, so that a side whose scatter went through while
+    // the other refused can be taken back
+    const ChunkDesc &cd = desc[ch];
+    API_HIP(c, launch_undo_rows(c, cd.s1_off, cd.s1, cd.s2_off, cd.s2, false), "undo log (chunk)");
+    API_HIP(c, launch_chain(c, ch, ch + 1, h.n_chunks, h.meets_prev), "chain (one chunk)");
+    API_HIP(c, hipMemcpyAsync(w.cstats_host, w.cstats, sizeof(ChainStats), hipMemcpyDeviceToHost, s), "stats");
+    API_HIP(c, hipStreamSynchronize(s), "chain (one chunk)");
+    const ChainStats one = *w.cstats_host;
+    if (one.numeric_error & kNumericCore) {
+      c->poisoned = true;
+      return fail(c, DAMF_E_NUMERIC, "non-finite core in the update");
+    }
+    const bool singular = (one.numeric_error & kNumericSingularP) != 0;
+    add_stats(acc, one, !singular);
+    if (singular) {
+      // one side's scatter may have run: take its rows back; then c->P holds
+      // P F: rotate every basis by it (P <- I) and add the row corrections of
+      // this chunk with the identity projection
+      API_HIP(c, launch_undo_rows(c, cd.s1_off, cd.s1, cd.s2_off, cd.s2, true), "undo (chunk)");
+      API_HIP(c, flush_projections(c), "explicit chunk (rotation)");
+      API_HIP(c, launch_chunk_scatter(c, ch, h.n_chunks, c->P), "explicit chunk (rows)");
+      c->enhance_pending = c->enhance_pending || c->ppr_on;  // R rotated
+      ++c->last_explicit;
+    }
+  }
+  API_HIP(c, hipStreamSynchronize(s), "explicit chunks");
+  acc.numeric_error = 0;
+  *out = acc;
+  *w.cstats_host = acc;
+  API_HIP(c, hipMemcpyAsync(w.cstats, w.cstats_host, sizeof(ChainStats), hipMemcpyHostToDevice, s), "stats");
+  API_HIP(c, hipStreamSynchronize(s), "stats");
+  return DAMF_OK;
+}
+
+}  // namespace
+
+damf_status step_check(damf_ctx *c, const BatchHeader &h) {
+  c->last_p_cond = 0.0;
+  c->last_flushed = 0;
+  c->last_explicit = 0;
+  if (h.n_chunks <= 0) return DAMF_OK;
+  Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  API_HIP(c, hipMemcpyAsync(w.cstats_host, w.cstats, sizeof(ChainStats), hipMemcpyDeviceToHost, s), "stats");
+  API_HIP(c, hipStreamSynchronize(s), "chain");
+  ChainStats cs = *w.cstats_host;
+  if (cs.numeric_error & kNumericCore) {
+    c->poisoned = true;
+    return fail(c, DAMF_E_NUMERIC, "non-finite core in the update");
+  }
+  if (cs.numeric_error & kNumericSingularP) {
+    const damf_status st = chain_recover(c, h, &cs);
+    if (st != DAMF_OK) return st;
+  }
+  double cond;
+  std::memcpy(&cond, &cs.p_cond_bits, sizeof(double));
+  c->last_p_cond = cond;
+  // the lazy projection's conditioning bounds how much FP32 rounding of the
+  // stored bases is amplified in U = U_b P: flush once it passes the limit
+  const double limit = c->cfg.flush_cond == 0.0 ? kDefaultFlushCond : c->cfg.flush_cond;
+  if (limit > 0.0 && cond > limit) {
+    API_HIP(c, flush_projections(c), "flush");
+    c->enhance_pending = c->enhance_pending || c->ppr_on;  // R rotated
+    c->last_flushed = 1;
+    c->last_p_cond = 1.0;
+  }
   return DAMF_OK;
 }
 
@@ -346,10 +475,6 @@ damf_status step_finish(damf_ctx *c, const BatchHeader &h) {
     API_HIP(c, csr_compact(c, c->out, c->cfg.graph_slack, 0), "CSR compaction");
   if (c->in.pool_cap - w.counters_host[9] < c->in.pool_cap / 8)
     API_HIP(c, csr_compact(c, c->in, c->cfg.graph_slack, 0), "CSR^T compaction");
-  if (h.n_chunks > 0 && w.cstats_host->numeric_error) {
-    c->poisoned = true;
-    return fail(c, DAMF_E_NUMERIC, "singular projection or non-finite core in the lazy update");
-  }
   return DAMF_OK;
 }
 
@@ -365,11 +490,17 @@ void step_info(damf_ctx *c, const BatchHeader &h, int64_t k, damf_batch_info *in
   info->ms_chain_kernel = ch ? ms_between(c->ev[4], c->ev[5]) : 0.0;
   info->chain_flops = ch ? w.cstats_host->flops : 0.0;
   info->core_flops = ch ? w.cstats_host->core_flops : 0.0;
+  info->core_flops_model = ch ? w.cstats_host->core_flops_model : 0.0;
   info->ms_core_kernel = 0.0;
   info->core_launches = ch ? c->core_timed : 0;
   for (int i = 0; ch && i < c->core_timed; ++i)
     info->ms_core_kernel += ms_between(c->ev_core[2 * i], c->ev_core[2 * i + 1]);
   info->sweeps = ch ? w.cstats_host->sweeps : 0;
+  info->p_cond = c->last_p_cond;
+  info->flushed = c->last_flushed;
+  info->explicit_chunks = c->last_explicit;
+  info->graph_launches = c->graph_launches;
+  info->small_sv_columns = ch ? w.cstats_host->small_sv_columns : 0;
   for (int i = 0; i < 8; ++i)
     info->chain_phase_ms[i] = ch ? (double)w.cstats_host->phase_ticks[i] / c->wall_khz : 0.0;
 }
@@ -399,7 +530,6 @@ damf_status update_impl(damf_ctx *c, int64_t k, const int32_t *src, const int32_
   if (info) info->ops = k;
   if (per_request) std::memset(per_request, 0, nseg * sizeof(damf_request_stats));
   if (k == 0) return DAMF_OK;
-  hipStream_t s = c->stream;
   BatchHeader h{};
   damf_status st = step_prepare(c, k, src, dst, op, flags, nseg, seg_end, &h);
   if (st != DAMF_OK) return st;
@@ -408,8 +538,16 @@ damf_status update_impl(damf_ctx *c, int64_t k, const int32_t *src, const int32_
       per_request[i].net_entries = c->ws.seg_stats_host[2 * i];
       per_request[i].chunks = c->ws.seg_stats_host[2 * i + 1];
     }
+  return update_apply(c, h, k, nseg, info);
+}
+
+damf_status update_apply(damf_ctx *c, const BatchHeader &h, int64_t k, int nseg,
+                         damf_batch_info *info) {
+  hipStream_t s = c->stream;
+  damf_status st;
   if ((st = step_graph(c, h)) != DAMF_OK) return st;
   if ((st = step_chain(c, h)) != DAMF_OK) return st;
+  if ((st = step_check(c, h)) != DAMF_OK) return st;
   // re-orthogonalisation due: before Step 4, so the push restores max |R| <= eps
   bool reorth_refused = false;
   double ms_reorth = 0.0;
@@ -632,6 +770,28 @@ damf_status damf_update_requests(damf_ctx *c, int32_t nreq, const int64_t *req_o
   return update_impl(c, k, src, dst, op, flags, nreq, seg_end, info, per_request);
 }
 
+damf_status damf_add_node(damf_ctx *c, int32_t node, int64_t k_in, const int32_t *in_nbrs,
+                          int64_t k_out, const int32_t *out_nbrs, damf_batch_info *info) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (info) std::memset(info, 0, sizeof(*info));
+  if (info) info->ops = k_in + k_out;
+  BatchHeader h{};
+  API_HIP(c, hipEventRecord(c->ev[0], c->stream), "event");
+  damf_status st = node_prepare(c, node, k_in, in_nbrs, k_out, out_nbrs, &h);
+  if (st != DAMF_OK) return st;
+  API_HIP(c, hipEventRecord(c->ev[1], c->stream), "event");
+  if (h.n_net == 0) return DAMF_OK;
+  return update_apply(c, h, k_in + k_out, 1, info);
+}
+
+damf_status damf_set_chunk_rank(damf_ctx *c, int32_t r) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (r < 1 || r > c->cfg.max_side || c->d + r > kMaxCore)
+    return fail(c, DAMF_E_INVALID_ARG, "chunk rank out of range");
+  c->cfg.max_core_rank = r;
+  return DAMF_OK;
+}
+
 damf_status damf_enhance(damf_ctx *c) {
   if (!c) return DAMF_E_INVALID_ARG;
   if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
@@ -755,6 +915,60 @@ damf_status damf_query_static(damf_ctx *c, damf_which which, int64_t q, const in
   if (!dev)
     API_HIP(c, hipMemcpyAsync(out, dout, (size_t)q * d * sizeof(float), hipMemcpyDeviceToHost, s), "copy query");
   API_HIP(c, hipStreamSynchronize(s), "query");
+  return DAMF_OK;
+}
+
+damf_status damf_score_pairs(damf_ctx *c, damf_which which_a, damf_which which_b, int64_t q,
+                             const int32_t *u, const int32_t *v, float *out, int32_t flags) {
+  if (!c) return DAMF_E_INVALID_ARG;
+  if (c->poisoned) return fail(c, DAMF_E_STATE, "context poisoned");
+  if (which_a < DAMF_X || which_a > DAMF_Z || which_b < DAMF_X || which_b > DAMF_Z || q < 0 ||
+      (q > 0 && (!u || !v || !out)))
+    return fail(c, DAMF_E_INVALID_ARG, "bad pair scoring arguments");
+  if (q == 0) return DAMF_OK;
+  hipStream_t s = c->stream;
+  if (!c->ppr_on) {  // alpha = 1: Z = X
+    if (which_a == DAMF_Z) which_a = DAMF_X;
+    if (which_b == DAMF_Z) which_b = DAMF_X;
+  }
+  if ((which_a == DAMF_Z || which_b == DAMF_Z) && c->enhance_pending) {
+    const damf_status st = damf_enhance(c);
+    if (st != DAMF_OK) return st;
+  }
+  const bool both = (flags & DAMF_SCORE_BOTH_WAYS) != 0;
+  const int32_t *du = u, *dv = v;
+  float *dout = out;
+  int32_t *own = nullptr;
+  float *own_o = nullptr;
+  if (flags & DAMF_DEVICE_PTRS) {
+    int64_t *bad = c->ws.counters + 12;
+    API_HIP(c, launch_count_bad_ids(u, q, c->n, bad, s), "pair id check");
+    API_HIP(c, hipMemcpyAsync(c->ws.counters_host + 12, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s),
+            "pair id check");
+    API_HIP(c, hipStreamSynchronize(s), "pair id check");
+    if (c->ws.counters_host[12] != 0) return fail(c, DAMF_E_OUT_OF_RANGE, "pair id out of range");
+    API_HIP(c, launch_count_bad_ids(v, q, c->n, bad, s), "pair id check");
+    API_HIP(c, hipMemcpyAsync(c->ws.counters_host + 12, bad, sizeof(int64_t), hipMemcpyDeviceToHost, s),
+            "pair id check");
+    API_HIP(c, hipStreamSynchronize(s), "pair id check");
+    if (c->ws.counters_host[12] != 0) return fail(c, DAMF_E_OUT_OF_RANGE, "pair id out of range");
+  } else {
+    for (int64_t i = 0; i < q; ++i)
+      if (u[i] < 0 || u[i] >= c->n || v[i] < 0 || v[i] >= c->n)
+        return fail(c, DAMF_E_OUT_OF_RANGE, "pair id out of range");
+    API_HIP(c, dalloc(&own, 2 * q), "alloc pairs");
+    API_HIP(c, dalloc(&own_o, q), "alloc pairs");
+    API_HIP(c, hipMemcpyAsync(own, u, q * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy pairs");
+    API_HIP(c, hipMemcpyAsync(own + q, v, q * sizeof(int32_t), hipMemcpyHostToDevice, s), "copy pairs");
+    du = own;
+    dv = own + q;
+    dout = own_o;
+  }
+  API_HIP(c, launch_score_pairs(c, which_a, which_b, q, du, dv, dout, both), "score pairs");
+  if (own_o) API_HIP(c, hipMemcpyAsync(out, own_o, q * sizeof(float), hipMemcpyDeviceToHost, s), "copy scores");
+  API_HIP(c, hipStreamSynchronize(s), "score pairs");
+  if (own) (void)hipFree(own);
+  if (own_o) (void)hipFree(own_o);
   return DAMF_OK;
 }
 

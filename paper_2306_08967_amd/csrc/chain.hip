@@ -44,6 +44,14 @@ constexpr int LDS_DOUBLES = 19200;  // 150 KB
 // 5.9e-6 either way, and a batch takes about 10% fewer sweeps.
 // damf_config.jacobi_tol overrides both.
 constexpr double kJacobiTol = 1e-9;
+// The lazy scatter solves with the new projection P and stores U_b's rows in
+// FP32, so its rounding reaches U = U_b P amplified by up to cond(P).  A pivot
+// ratio max |u_ii| / min |u_ii| of P's LU above the chunk limit marks P as too
+// ill-conditioned for that, and the chunk is applied explicitly instead
+// (api.hip).  The limit is the flush limit, at least kMinExplicitCond; with
+// flushing off it is kSingularCond (only numerically singular P).
+constexpr double kSingularCond = 1e10;
+constexpr double kMinExplicitCond = 1e3;
 constexpr double kJacobiTolSplit = 1e-8;
 
 // global scratch layout (doubles)
@@ -88,6 +96,7 @@ struct ChainParams {
   double *scr;
   double tau;
   double jtol;  // relative tolerance of the core's Jacobi
+  double explicit_cond;  // pivot ratio of the new P above which a chunk goes explicit
   ChainStats *stats;
   bool split;  // U_b, V_b as BF16 pairs
 };
@@ -573,17 +582,75 @@ __device__ __noinline__ int core_svd(const ChunkState &cs, int d, const double *
   return nonfinite;
 }
 
+// H = K^T E Theta^-1 carries the Jacobi's residual non-orthogonality of E
+// amplified by sigma_1 / theta_c: with |e_c . e_j| <= jtol, h_c . h_j can reach
+// jtol sigma_j / theta_c, which is O(1) for a theta_c at the rounding floor of
+// a kept zero singular value.  Columns c < d with cut < theta_c <= hrel
+// sigma_1 (ascending rank, so every larger column is final first) are
+// re-orthogonalised against the columns before them (classical Gram-Schmidt,
+// twice, all waves) and normalised: that moves K^T e_c - theta_c h_c by about
+// jtol sigma_1, far below the FP32 bases' rounding.  A column left with less
+// than half its length lies in the span of the earlier ones; it is zeroed and
+// marked in `redo` for complete_basis.  Returns the number of columns treated.
+__device__ __noinline__ int orthonormalize_small_h(int d, int NC, double hrel, double *scr, double *lds,
+                                                   int *redo) {
+  const double *TH = scr + OFF_TH;
+  double *HG = scr + OFF_HG;
+  const double cut = 1e-10 * TH[0], hcut = hrel * TH[0];
+  const int lane = tid() & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid() >> 6);
+  double *dots = lds;  // d
+  __shared__ double s_nn;
+  int treated = 0;
+  for (int c = 0; c < d; ++c) {
+    if (tid() == 0) redo[c] = 0;
+    if (!(TH[c] <= hcut) || TH[c] <= cut) continue;
+    ++treated;
+    for (int pass = 0; pass < 2; ++pass) {
+      for (int o = w; o < c; o += NW) {
+        double sdot = 0.0;
+        for (int j = lane; j < NC; j += 64) sdot = fma(HG[j * DMAX + o], HG[j * DMAX + c], sdot);
+        sdot = wave_sum(sdot);
+        if (lane == 0) dots[o] = sdot;
+      }
+      __syncthreads();
+      for (int j = tid(); j < NC; j += NT) {
+        double v = HG[j * DMAX + c];
+        for (int o = 0; o < c; ++o) v = fma(-dots[o], HG[j * DMAX + o], v);
+        HG[j * DMAX + c] = v;
+      }
+      __syncthreads();
+    }
+    if (w == 0) {
+      double nn = 0.0;
+      for (int j = lane; j < NC; j += 64) nn = fma(HG[j * DMAX + c], HG[j * DMAX + c], nn);
+      nn = wave_sum(nn);
+      if (lane == 0) s_nn = nn;
+    }
+    __syncthreads();
+    const double nn = s_nn;
+    const bool keep = nn > 0.25;
+    const double sc = keep ? 1.0 / sqrt(nn) : 0.0;
+    for (int j = tid(); j < NC; j += NT) HG[j * DMAX + c] *= sc;
+    if (tid() == 0 && !keep) redo[c] = 1;
+    __syncthreads();
+  }
+  return treated;
+}
+
 // Orthonormal completion of columns c < d whose singular value is <= cut:
-// E (NB rows, col-major stride NPMAX) and H (NC rows, row-major stride DMAX).
-__device__ __noinline__ void complete_basis(int d, int NB, int NC, double *scr) {
+// E (NB rows, col-major stride NPMAX) and H (NC rows, row-major stride DMAX);
+// also the H columns that orthonormalize_small_h marked in `redo`.
+__device__ __noinline__ void complete_basis(int d, int NB, int NC, double *scr, const int *redo) {
   const double *TH = scr + OFF_TH;
   double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
   const double cut = 1e-10 * TH[0];
   if (tid() >= 64) return;
   const int lane = tid() & 63;
   for (int c = 0; c < d; ++c) {
-    if (TH[c] > cut) continue;
-    for (int side = 0; side < 2; ++side) {
+    const bool zero = TH[c] <= cut, hredo = redo != nullptr && redo[c] != 0;
+    if (!zero && !hredo) continue;
+    for (int side = zero ? 0 : 1; side < 2; ++side) {
       const int N = side ? NC : NB;
       auto at = [&](int i, int cc) -> double & {
         return side ? HG[i * DMAX + cc] : EG[cc * NPMAX + i];
@@ -821,11 +888,12 @@ __device__ __forceinline__ void lu_panel(double *A, int d, int j0, int jb, int *
 // a zero pivot was met.
 __device__ __forceinline__ int lu_solve_scatter(int d, const double *Pn, const double *Dl, const int32_t *rows,
                                 int nrows, float *Mb, float *Rr, double *lds, int *ilds,
-                                bool split) {
+                                bool split, double limit, double *cond_out) {
   double *A = lds;  // d x d
   int *piv = ilds;  // d
   int *src = ilds + DMAX;
   __shared__ int s_bad;
+  __shared__ double s_cond;
   for (int e = tid(); e < d * d; e += NT) A[e] = Pn[e];
   if (tid() == 0) s_bad = 0;
   __syncthreads();
@@ -914,7 +982,27 @@ __device__ __forceinline__ int lu_solve_scatter(int d, const double *Pn, const d
       src[piv[j]] = t;
     }
   }
+  if (tid() < 64) {
+    // condition estimate of the new P: the spread of the LU's pivots
+    double mx = 0.0, mn = INFINITY;
+    for (int c = tid(); c < d; c += 64) {
+      const double u = fabs(A[c * d + c]);
+      mx = fmax(mx, u);
+      mn = fmin(mn, u);
+    }
+#pragma unroll
+    for (int off = 32; off >= 1; off >>= 1) {
+      mx = fmax(mx, __shfl_xor(mx, off, 64));
+      mn = fmin(mn, __shfl_xor(mn, off, 64));
+    }
+    if (tid() == 0) {
+      const double cond = (mn > 0.0) ? mx / mn : INFINITY;
+      s_cond = (cond == cond) ? cond : INFINITY;
+      if (!(s_cond <= limit)) s_bad = 1;
+    }
+  }
   __syncthreads();
+  if (tid() == 0) *cond_out = s_cond;
   if (s_bad) return 1;
   // Row-vector solves X Pn = Dl: wave w takes rows w, w + NW, ... (up to
   // SR of them at once, interleaved for latency); lanes own columns
@@ -1083,11 +1171,22 @@ __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
     nonfinite = core_svd<2>(cs, d, p.sigma, scr, lds, ilds, &sw, jt, p.jtol);
   else
     nonfinite = core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw, jt, p.jtol);
-  if (nonfinite && tid() == 0) atomicOr(&p.stats->numeric_error, 1);
+  if (nonfinite && tid() == 0) atomicOr(&p.stats->numeric_error, kNumericCore);
   clk.tick(p.stats, 2);
-  if (scr[OFF_TH + d - 1] <= 1e-10 * scr[OFF_TH]) {
-    complete_basis(d, d + cs.rhoB, d + cs.rhoC, scr);
+  // small singular values: H's columns re-orthogonalised (the threshold puts
+  // the amplified Jacobi tolerance at 1e-7), zero ones completed
+  const double hrel = fmin(0.5, p.jtol * 1e7);
+  int *redo = ilds + 600;
+  int small_h = 0;
+  if (scr[OFF_TH + d - 1] <= hrel * scr[OFF_TH]) {
+    small_h = orthonormalize_small_h(d, d + cs.rhoC, hrel, scr, lds, redo);
     __syncthreads();
+    bool any_redo = false;
+    for (int c = 0; c < d; ++c) any_redo = any_redo || redo[c] != 0;
+    if (any_redo || scr[OFF_TH + d - 1] <= 1e-10 * scr[OFF_TH]) {
+      complete_basis(d, d + cs.rhoB, d + cs.rhoC, scr, redo);
+      __syncthreads();
+    }
   }
   for (int c = tid(); c < d; c += NT) p.sigma[c] = scr[OFF_TH + c];
   clk.tick(p.stats, 3);
@@ -1103,12 +1202,14 @@ __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
     const double shf = sw > 0 ? 1.0 - ilds[2] / all_steps : 1.0;
     const double jac = sw * 0.5 * Nn * (Nn - 1.0) * (2.0 * Nn + 6.0 * Nn * shf);
     atomicAdd(&p.stats->core_flops, jac + 2.0 * Nn * Nn * dd + 2.0 * Nn * Nn * kk);
+    atomicAdd(&p.stats->core_flops_model, sw * 9.0 * Nn * Nn * Nn);
     double flops = jac + 2.0 * Nn * Nn * dd;
     flops += 2.0 * (2.0 * dd * dd * kk + 2.0 * dd * dd * dd + (2.0 / 3.0) * dd * dd * dd +
                     2.0 * 2.0 * (double)max(cs.s1, cs.s2) * dd * dd);
     flops += 2.0 * (double)(cs.s1 + cs.s2) * dd * dd + 4.0 * kk * kk * dd;
     atomicAdd(&p.stats->flops, flops);
     atomicAdd(&p.stats->sweeps, sw);
+    if (small_h) atomicAdd(&p.stats->small_sv_columns, small_h);
     atomicMax(&p.stats->max_core, N);
     atomicAdd((unsigned long long *)&p.stats->phase_ticks[1], (unsigned long long)jt[1]);
   }
@@ -1143,10 +1244,18 @@ __global__ __launch_bounds__(NT) void chain_scatter_kernel(ChainParams p, int ch
   const int d = p.d;
   ChunkState cs = chunk_state(p, ch, nullptr);
   PhaseClock clk;
+  double cond = 0.0;
   const int bad = lu_solve_scatter(d, Pn + side * d * d, p.scr + off_dl(side, ch),
                                    side ? cs.S2 : cs.S1, side ? cs.s2 : cs.s1,
-                                   side ? p.Vb : p.Ub, side ? nullptr : p.R, lds, ilds, p.split);
-  if (bad && tid() == 0) atomicOr(&p.stats->numeric_error, 1);
+                                   side ? p.Vb : p.Ub, side ? nullptr : p.R, lds, ilds, p.split,
+                                   p.explicit_cond, &cond);
+  if (tid() == 0) {
+    // largest condition estimate of the batch (non-negative doubles order
+    // like their bit patterns)
+    atomicMax((unsigned long long *)&p.stats->p_cond_bits,
+              (unsigned long long)__double_as_longlong(cond));
+    if (bad) atomicOr(&p.stats->numeric_error, kNumericSingularP);
+  }
   clk.tick(p.stats, 6);
 }
 
@@ -1154,9 +1263,9 @@ __global__ __launch_bounds__(NT) void chain_scatter_kernel(ChainParams p, int ch
 
 size_t chain_scratch_doubles() { return SCRATCH_DOUBLES; }
 
-hipError_t launch_chain(damf_ctx *c, int n_chunks, const uint64_t *meets) {
-  if (n_chunks <= 0) return hipSuccess;
-  hipStream_t s = c->stream;
+namespace {
+
+ChainParams chain_params(damf_ctx *c, int n_chunks) {
   ChainParams p;
   p.d = c->d;
   p.n = c->n;
@@ -1174,46 +1283,125 @@ hipError_t launch_chain(damf_ctx *c, int n_chunks, const uint64_t *meets) {
   p.scr = c->ws.scratch;
   p.tau = c->cfg.tau;
   p.jtol = c->cfg.jacobi_tol > 0.0 ? c->cfg.jacobi_tol : (c->split ? kJacobiTolSplit : kJacobiTol);
+  const double limit = c->cfg.flush_cond == 0.0 ? kDefaultFlushCond : c->cfg.flush_cond;
+  p.explicit_cond = limit > 0.0 ? std::max(limit, kMinExplicitCond) : kSingularCond;
   p.stats = c->ws.cstats;
   p.split = c->split;
-  DAMF_HIP(hipMemsetAsync(c->ws.cstats, 0, sizeof(ChainStats), s));
-  // The projections alternate between P and Pnext from chunk to chunk.  The
-  // solve-and-scatter of chunk ch runs on stream t after chunk ch's back and
-  // beside chunk ch + 1; stream s waits for it before the front of chunk
-  // ch + 1 when that chunk's S1 or S2 meets chunk ch's (the front reads those
-  // rows of U_b, V_b), and always before the front of chunk ch + 2 (whose
-  // back reuses chunk ch's P buffer and row-correction parity).  The result
-  // is the same as with every step in one stream.
+  return p;
+}
+
+__global__ void zero_stats_kernel(ChainStats *st) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *st = ChainStats{};
+}
+
+__global__ void copy_doubles_kernel(double *dst, const double *src, int count) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+    dst[i] = src[i];
+}
+
+// The launch sequence of chunks [first, last) (see launch_chain).  With
+// `graph` every device-side step is a kernel (no memset or copy nodes), so the
+// sequence can be captured into a HIP graph and replayed.
+hipError_t enqueue_chain(damf_ctx *c, int first, int last, int n_chunks, const uint64_t *meets,
+                         bool graph) {
+  hipStream_t s = c->stream;
+  const ChainParams p = chain_params(c, n_chunks);
+  if (graph)
+    zero_stats_kernel<<<1, 64, 0, s>>>(c->ws.cstats);
+  else
+    DAMF_HIP(hipMemsetAsync(c->ws.cstats, 0, sizeof(ChainStats), s));
   hipStream_t t = c->scatter_stream;
   double *Pbuf[2] = {c->P, c->Pnext};
-  // with kernel timing, a pair of events brackets each core launch
-  const bool timed = c->cfg.kernel_timing != 0;
+  const bool timed = c->cfg.kernel_timing != 0 && !graph;
   c->core_timed = 0;
-  for (int ch = 0; ch < n_chunks; ++ch) {
-    if (ch >= 2) DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(ch - 2) & 3], 0));
-    if (ch >= 1 && ((meets[ch >> 6] >> (ch & 63)) & 1))
+  for (int ch = first; ch < last; ++ch) {
+    const int j = ch - first;
+    if (j >= 2) DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(ch - 2) & 3], 0));
+    if (j >= 1 && ((meets[ch >> 6] >> (ch & 63)) & 1))
       DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(ch - 1) & 3], 0));
-    chain_front_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[ch & 1]);
-    const bool tm = timed && ch < damf_ctx::kCoreTimed;
-    if (tm) DAMF_HIP(hipEventRecord(c->ev_core[2 * ch], s));
+    chain_front_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[j & 1]);
+    const bool tm = timed && j < damf_ctx::kCoreTimed;
+    if (tm) DAMF_HIP(hipEventRecord(c->ev_core[2 * j], s));
     chain_core_kernel<<<1, NT, 0, s>>>(p, ch);
     if (tm) {
-      DAMF_HIP(hipEventRecord(c->ev_core[2 * ch + 1], s));
-      c->core_timed = ch + 1;
+      DAMF_HIP(hipEventRecord(c->ev_core[2 * j + 1], s));
+      c->core_timed = j + 1;
     }
-    chain_back_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[ch & 1], Pbuf[(ch + 1) & 1]);
+    chain_back_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[j & 1], Pbuf[(j + 1) & 1]);
     DAMF_HIP(hipEventRecord(c->ev_back[ch & 3], s));
     DAMF_HIP(hipStreamWaitEvent(t, c->ev_back[ch & 3], 0));
-    chain_scatter_kernel<<<2, NT, 0, t>>>(p, ch, Pbuf[(ch + 1) & 1]);
+    chain_scatter_kernel<<<2, NT, 0, t>>>(p, ch, Pbuf[(j + 1) & 1]);
     DAMF_HIP(hipEventRecord(c->ev_scatter[ch & 3], t));
   }
-  DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(n_chunks - 1) & 3], 0));
+  DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(last - 1) & 3], 0));
   DAMF_HIP(hipGetLastError());
-  double *Pc = Pbuf[n_chunks & 1];
-  if (Pc != c->P)
-    DAMF_HIP(hipMemcpyAsync(c->P, Pc, 2 * (size_t)c->d * c->d * sizeof(double),
-                            hipMemcpyDeviceToDevice, s));
+  double *Pc = Pbuf[(last - first) & 1];
+  if (Pc != c->P) {
+    const int cnt = 2 * c->d * c->d;
+    if (graph)
+      copy_doubles_kernel<<<(cnt + 255) / 256, 256, 0, s>>>(c->P, Pc, cnt);
+    else
+      DAMF_HIP(hipMemcpyAsync(c->P, Pc, cnt * sizeof(double), hipMemcpyDeviceToDevice, s));
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_chain_graph(damf_ctx *c, int n_chunks, const uint64_t *meets, bool *used) {
+  *used = false;
+  if (n_chunks < 1 || n_chunks > c->cfg.graph_chunks || n_chunks > 64 || c->cfg.kernel_timing)
+    return hipSuccess;
+  // the captured sequence depends only on the chunk count and on which
+  // chunks wait for their predecessor's scatter
+  uint64_t bits = 0;
+  for (int ch = 1; ch < n_chunks; ++ch) bits |= ((meets[0] >> ch) & 1ull) << ch;
+  const uint64_t key = (bits << 7) | (uint64_t)n_chunks;
+  auto it = c->graphs.find(key);
+  if (it == c->graphs.end()) {
+    if (c->graphs.size() >= 256) {
+      for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+      c->graphs.clear();
+    }
+    hipStream_t s = c->stream;
+    DAMF_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal));
+    const hipError_t e = enqueue_chain(c, 0, n_chunks, n_chunks, meets, true);
+    hipGraph_t g = nullptr;
+    const hipError_t e2 = hipStreamEndCapture(s, &g);
+    if (e != hipSuccess) {
+      if (g) (void)hipGraphDestroy(g);
+      return e;
+    }
+    DAMF_HIP(e2);
+    hipGraphExec_t x = nullptr;
+    const hipError_t e3 = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    DAMF_HIP(e3);
+    it = c->graphs.emplace(key, x).first;
+  }
+  c->core_timed = 0;
+  DAMF_HIP(hipGraphLaunch(it->second, c->stream));
+  *used = true;
   return hipSuccess;
+}
+
+hipError_t launch_chain(damf_ctx *c, int first, int last, int n_chunks, const uint64_t *meets) {
+  if (first >= last) return hipSuccess;
+  // The projections alternate between P and Pnext from chunk to chunk,
+  // starting from P at chunk `first`.  The solve-and-scatter of chunk ch runs
+  // on the scatter stream after chunk ch's back and beside chunk ch + 1; the
+  // context stream waits for it before the front of chunk ch + 1 when that
+  // chunk's S1 or S2 meets chunk ch's (the front reads those rows of U_b,
+  // V_b), and always before the front of chunk ch + 2 (whose back reuses
+  // chunk ch's P buffer and row-correction parity).  The result is the same
+  // as with every step in one stream.
+  return enqueue_chain(c, first, last, n_chunks, meets, false);
+}
+
+hipError_t launch_chunk_scatter(damf_ctx *c, int ch, int n_chunks, const double *Pn) {
+  const ChainParams p = chain_params(c, n_chunks);
+  chain_scatter_kernel<<<2, NT, 0, c->stream>>>(p, ch, Pn);
+  return hipGetLastError();
 }
 
 }  // namespace damf

@@ -6,6 +6,7 @@
 
 #include <cstdint>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/damf.h"
@@ -20,6 +21,7 @@ constexpr int kMaxSide = 64;        // |S1|, |S2| per chunk
 constexpr int kChainThreads = 512;  // one workgroup (8 waves) runs Steps 1-3
 constexpr int kMaxRequests = 256;   // request segments per batch
 constexpr int64_t kEditStagePool = 1 << 24;  // staging entries for long-row edits
+constexpr double kDefaultFlushCond = 1e3;    // flush P once its condition estimate passes this
 
 // Dynamic CSR with per-row slack.  Row u occupies col[start[u] .. start[u] +
 // len[u]) in ascending order; cap[u] >= len[u] entries are reserved there.
@@ -61,19 +63,29 @@ struct BatchHeader {
   int32_t max_s;          // largest |S1| or |S2|
   int32_t pool_overflow;  // CSR rows that found no pool space (set by edits)
   int32_t s1_total;       // entries of all chunks' S1 lists
+  int32_t s2_total;       // entries of all chunks' S2 lists
+  int32_t pad_;
   // bit j: chunk j's S1 meets chunk j-1's S1, or its S2 meets chunk j-1's S2
   uint64_t meets_prev[kMaxBatch / 64];
 };
+
+// ChainStats::numeric_error bits
+constexpr int32_t kNumericSingularP = 1;  // new P past the chunk limit: scatter refused
+constexpr int32_t kNumericCore = 2;       // non-finite core (corrupt state)
 
 // Per-chunk results written by the chain kernels (for batch info).
 struct ChainStats {
   int32_t max_core;
   int32_t dropped;
   int32_t sweeps;
-  int32_t numeric_error;
+  int32_t numeric_error;  // kNumeric* bits
   double flops;  // FP64 flops executed (counted per phase)
   uint64_t phase_ticks[8];  // wall-clock ticks per phase (see chain.hip)
   double core_flops;        // the core-SVD kernel's share of flops
+  double core_flops_model;  // 9 N^3 per sweep (one-sided Jacobi with V accumulated)
+  uint64_t p_cond_bits;     // max over chunks of the new P's condition estimate (double bits)
+  int32_t small_sv_columns; // right-vector columns re-orthogonalised (small singular value)
+  int32_t pad_;
 };
 
 struct Workspace {
@@ -113,13 +125,19 @@ struct Workspace {
   // chain kernels' scratch (float64, L2 resident)
   double *scratch = nullptr;
   size_t scratch_doubles = 0;
+  // state before the chunks of a batch, for the explicit re-run of a batch in
+  // which a projection turned singular: U_b rows of every chunk's S1 and V_b
+  // rows of every chunk's S2 (as stored, in chunk-list order), P and Sigma
+  float *undo_u = nullptr, *undo_v = nullptr;
+  double *psave = nullptr;  // 2 d^2 + kMaxCore
   // PPR push
   int32_t *stamp = nullptr;      // per node: last round it was queued
   int32_t *cand = nullptr;       // candidate list (n)
   int32_t *cand2 = nullptr;      // next round's candidates (n)
   int32_t *frontier = nullptr;   // frontier list (n)
   int64_t *counters = nullptr;   // device counters: 0-7 Step 4 (cand, frontier, edges, ...),
-                                 // 8-11 CSR pool tops and needs, 12 bad query ids
+                                 // 8-11 CSR pool tops and needs, 12 bad query ids,
+                                 // 13 a joining node's two degrees (node.hip)
   int64_t *counters_host = nullptr;
   double *dscratch_host = nullptr;
 };
@@ -158,6 +176,13 @@ struct damf_ctx {
   double push_ms = 0.0, push_bytes = 0.0;  // accumulated by ppr_push
   double wall_khz = 100000.0;               // device wall-clock rate (kHz)
   int64_t batches_since_reorth = 0;
+  double last_p_cond = 0.0;  // condition estimate of P after the last batch's chunks
+  int last_flushed = 0;      // the last batch flushed P (condition limit)
+  int last_explicit = 0;     // chunks of the last batch applied explicitly
+  // captured chain launch sequences (graph_chunks), keyed by chunk count and
+  // the chunks that wait for their predecessor
+  std::unordered_map<uint64_t, hipGraphExec_t> graphs;
+  int64_t graph_launches = 0;
   bool split = false;  // U_b, V_b as BF16 pairs (precision form)
 };
 
@@ -175,12 +200,23 @@ damf_status step_prepare(damf_ctx *c, int64_t k, const int32_t *src, const int32
 damf_status step_graph(damf_ctx *c, const BatchHeader &h);
 // Steps 1-3 over every chunk (asynchronous).
 damf_status step_chain(damf_ctx *c, const BatchHeader &h);
-// Waits for the stream, checks pool overflow and numeric failure.
+// Waits for the chunks, re-runs a batch whose projection turned singular
+// (explicit chunks), poisons on a non-finite core, and flushes the lazy
+// projections when their condition estimate passes the configured limit.
+damf_status step_check(damf_ctx *c, const BatchHeader &h);
+// Waits for the stream, checks pool overflow and compacts the CSR pools.
 damf_status step_finish(damf_ctx *c, const BatchHeader &h);
 void step_info(damf_ctx *c, const BatchHeader &h, int64_t k, damf_batch_info *info);
 // First-round Step 4 candidates into ws.pend_rows: rows of the net change and,
 // with several requests, every chunk's S1 rows (rows whose R got a signal).
 damf_status step_push_rows(damf_ctx *c, const BatchHeader &h, int nseg, int64_t *count);
+// The steps after batch preparation (graph edits, Steps 1-3, checks,
+// re-orthogonalisation when due, Step 4, statistics) for a prepared header.
+damf_status update_apply(damf_ctx *c, const BatchHeader &h, int64_t k, int nseg,
+                         damf_batch_info *info);
+// ---- node.hip: node change (Theorem 1) prepared as chunks on the host
+damf_status node_prepare(damf_ctx *c, int32_t node, int64_t k_in, const int32_t *in_nbrs,
+                         int64_t k_out, const int32_t *out_nbrs, BatchHeader *h);
 damf_status update_impl(damf_ctx *c, int64_t k, const int32_t *src, const int32_t *dst,
                         const int8_t *op, int32_t flags, int nseg, const int32_t *seg_end,
                         damf_batch_info *info, damf_request_stats *per_request);
@@ -203,7 +239,16 @@ hipError_t launch_csr_edit(damf_ctx *c, Csr &g, const NetEntry *net,
                            int nrows, bool transposed);
 
 // ---- chain.hip
-hipError_t launch_chain(damf_ctx *c, int n_chunks, const uint64_t *meets);
+// Steps 1-3 for chunks [first, last) of the n_chunks prepared ones, starting
+// from c->P and leaving the last projection in c->P.
+hipError_t launch_chain(damf_ctx *c, int first, int last, int n_chunks, const uint64_t *meets);
+// All n_chunks chunks as one captured HIP graph when n_chunks <= graph_chunks
+// and kernel timing is off (*used = true); the graph is built on first use of
+// its shape and replayed after.  Otherwise nothing is launched (*used = false).
+hipError_t launch_chain_graph(damf_ctx *c, int n_chunks, const uint64_t *meets, bool *used);
+// The solve-and-scatter of chunk ch alone with projection Pn (2 d x d), on
+// the context stream: rows += (row corrections of ch) Pn^-1.
+hipError_t launch_chunk_scatter(damf_ctx *c, int ch, int n_chunks, const double *Pn);
 
 // ---- ppr.hip
 hipError_t ppr_init(damf_ctx *c);
@@ -243,6 +288,15 @@ hipError_t reorthogonalize(damf_ctx *c, int *numeric_bad);
 // ---- state.hip
 hipError_t launch_query(damf_ctx *c, int which, int64_t q,
                         const int32_t *d_nodes, float *d_out);
+// Undo log over a stretch of the chunk lists (S1 entries [s1_off, s1_off +
+// n_s1) for U_b, S2 entries for V_b; a row may appear several times): save
+// copies the rows into the log; restore removes the chain's signal additions
+// from R (R -= U_b - log) and copies the rows back, entry by entry in list
+// order, so a repeated row is corrected once.
+hipError_t launch_undo_rows(damf_ctx *c, int s1_off, int n_s1, int s2_off, int n_s2, bool restore);
+// out[i] = <rows of which_a at u[i], rows of which_b at v[i]> (device lists)
+hipError_t launch_score_pairs(damf_ctx *c, int which_a, int which_b, int64_t q, const int32_t *d_u,
+                              const int32_t *d_v, float *d_out, bool both_ways);
 // *d_bad = number of ids of d_nodes[0..q) outside [0, n) (cleared first)
 hipError_t launch_count_bad_ids(const int32_t *d_nodes, int64_t q, int64_t n, int64_t *d_bad,
                                 hipStream_t s);

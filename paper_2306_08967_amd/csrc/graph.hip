@@ -613,7 +613,7 @@ __device__ void bitonic_u32(uint32_t *a, int P) {
 // graph edits use the net change of the whole batch.  With one segment this
 // is the plain batch.
 __device__ void set_header(BatchHeader *h, int bad, int ne, int nchunks, int rows_out,
-                           int rows_in, int maxs, int s1tot) {
+                           int rows_in, int maxs, int s1tot, int s2tot) {
   h->bad_ops = bad;
   h->n_net = ne;
   h->n_chunks = nchunks;
@@ -622,6 +622,7 @@ __device__ void set_header(BatchHeader *h, int bad, int ne, int nchunks, int row
   h->max_s = maxs;
   h->pool_overflow = 0;
   h->s1_total = s1tot;
+  h->s2_total = s2tot;
 }
 
 __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams p) {
@@ -677,7 +678,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
   }
   __syncthreads();
   if (s_bad > 0) {
-    if (threadIdx.x == 0) set_header(p.hdr, s_bad, 0, 0, 0, 0, 0, 0);
+    if (threadIdx.x == 0) set_header(p.hdr, s_bad, 0, 0, 0, 0, 0, 0, 0);
     return;
   }
   // sort (key, idx) pairs; equal keys keep batch order through idx
@@ -817,7 +818,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
   __syncthreads();
   int n_rows_in = emit_sorted_entries(ent, ne, true, p.net_t, p.rows_in, p.rowpos_in, wbuf);
   // ---- phase 4: greedy chunking of the units (one wave, sequential)
-  __shared__ int s_nchunks, s_maxs, s_s1tot;
+  __shared__ int s_nchunks, s_maxs, s_s1tot, s_s2tot;
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     int32_t s1v = -1, s2v = -1;  // lane-held members of S1 and S2
@@ -934,6 +935,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
       s_nchunks = nchunks;
       s_maxs = maxs;
       s_s1tot = s1_total;
+      s_s2tot = s2_total;
     }
   }
   __syncthreads();
@@ -959,7 +961,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
   __syncthreads();
   for (int i = threadIdx.x; i < kMaxBatch / 64; i += kPrepThreads) p.hdr->meets_prev[i] = s_meets[i];
   if (threadIdx.x == 0)
-    set_header(p.hdr, 0, ne, s_nchunks, n_rows_out, n_rows_in, s_maxs, s_s1tot);
+    set_header(p.hdr, 0, ne, s_nchunks, n_rows_out, n_rows_in, s_maxs, s_s1tot, s_s2tot);
 }
 
 hipError_t launch_batch_prepare(damf_ctx *c, int k, int nseg) {

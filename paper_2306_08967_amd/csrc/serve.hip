@@ -1,9 +1,12 @@
 // serve.hip -- continuous-batching update server (include/damf_serve.h).
 //
-// One server thread owns the context.  Clients admit requests under a memory
-// cap; the thread takes every admitted request that fits into the next step
-// (up to max_step_ops / max_step_requests), concatenates them as request
-// segments and runs one update step:
+// One server thread owns the context.  Clients admit requests under two
+// memory caps (host staging and the device memory their graph edits may
+// claim); the thread takes every admitted request that fits into the next
+// step (up to max_step_ops / max_step_requests), concatenates them as request
+// segments and runs one update step.  A request longer than max_step_ops runs
+// alone as consecutive parts of max_step_ops ops (its ops in order, so the
+// graph ends as with one batch).  Step:
 //
 //   prepare (segments) -> chain kernel (stream A, async)
 //       || Step 4 of the previous step (stream B: push rounds)
@@ -18,6 +21,9 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cmath>
+#include <cstdio>
+#include <string>
 #include <condition_variable>
 #include <cstring>
 #include <deque>
@@ -34,9 +40,19 @@ using namespace damf;
 namespace {
 
 constexpr int64_t kReqOverheadBytes = 64;
+// device memory an op may claim: one entry (4 B) in each of the out- and
+// in-CSR pools, times 3 for a moved row's reservation (len + len/2 + 8) and
+// the old copy that compaction later frees
+constexpr int64_t kDeviceBytesPerOp = 24;
+constexpr int kMaxRequestOps = 1 << 20;
+// chunk ranks the tuner tries, and steps per candidate
+constexpr int kTuneRanks[] = {16, 32, 48, 64};
+constexpr int kTuneSteps = 4;
 
 struct Req {
-  int64_t ticket = 0, k = 0, bytes = 0;
+  int64_t ticket = 0, k = 0, bytes = 0, dev_bytes = 0;
+  int64_t sched = 0;  // ops handed to steps so far
+  int32_t parts = 0, chunk_rank = 0;
   std::vector<int32_t> src, dst;
   std::vector<int8_t> op;
   double submit_us = 0, start_us = 0, done_us = 0;
@@ -44,6 +60,14 @@ struct Req {
   int32_t step_requests = 0;
   damf_status status = DAMF_OK;
   bool done = false;
+};
+
+// ops [off, off + len) of a request, carried by one step; `last` marks the
+// part that completes it
+struct Part {
+  Req *r;
+  int64_t off, len;
+  bool last;
 };
 
 }  // namespace
@@ -58,11 +82,17 @@ struct damf_server {
   std::unordered_map<int64_t, Req *> reqs;   // until waited (under mu)
   int64_t next_ticket = 1;
   int64_t admitted_bytes = 0, peak_bytes = 0;
+  int64_t admitted_dev = 0, peak_dev = 0, dev_cap = 0;
+  // chunk-rank tuner (worker thread only; tuned_rank read under mu)
+  int tune_idx = -1, tune_left = 0, tuned_rank = 0;
+  double tune_ms[4] = {}, tune_net[4] = {};
+  int64_t tuner_steps = 0;
+  std::string tune_key, tune_path;  // the cache path is copied at creation
   bool stop = false, paused = false;
   damf_status dead = DAMF_OK;                // set after a device error
   hipStream_t push_stream = nullptr;
   // deferred Step 4 (worker thread only)
-  std::vector<Req *> pending;
+  std::vector<Part> pending;
   int64_t pending_rows = 0;
   bool pending_push = false;
   // pinned staging of one step's ops
@@ -81,15 +111,20 @@ struct damf_server {
 
 namespace {
 
-// Marks requests complete with status st (a request's own earlier failure wins).
-void complete(damf_server *s, std::vector<Req *> &rs, damf_status st) {
+// Ends the step's parts with status st (a request's own earlier failure
+// wins); a request completes with its last part, or with any part when
+// `all` (the server stopped).
+void complete(damf_server *s, std::vector<Part> &ps, damf_status st, bool all = false) {
   const double t = s->now_us();
   std::lock_guard<std::mutex> lk(s->mu);
-  for (Req *r : rs) {
+  for (Part &pt : ps) {
+    Req *r = pt.r;
     if (r->status == DAMF_OK) r->status = st;
+    if ((!pt.last && !all) || r->done) continue;
     r->done_us = t;
     r->done = true;
     s->admitted_bytes -= r->bytes;
+    s->admitted_dev -= r->dev_bytes;
     if (r->status == DAMF_OK) {
       s->lat_ms.push_back((t - r->submit_us) * 1e-3);
       s->ops_done += r->k;
@@ -99,22 +134,22 @@ void complete(damf_server *s, std::vector<Req *> &rs, damf_status st) {
     std::vector<int32_t>().swap(r->dst);
     std::vector<int8_t>().swap(r->op);
   }
-  rs.clear();
+  ps.clear();
   s->cv_done.notify_all();
 }
 
 // After a device error the context is poisoned: fail everything admitted.
 void fail_all(damf_server *s, damf_status st) {
-  complete(s, s->pending, st);
+  complete(s, s->pending, st, true);
   s->pending_push = false;
-  std::vector<Req *> rest;
+  std::vector<Part> rest;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     s->dead = st;
-    rest.assign(s->queue.begin(), s->queue.end());
+    for (Req *r : s->queue) rest.push_back(Part{r, 0, 0, true});
     s->queue.clear();
   }
-  complete(s, rest, st);
+  complete(s, rest, st, true);
 }
 
 damf_status run_pending_push(damf_server *s, hipStream_t st, bool beside_chain) {
@@ -140,7 +175,91 @@ void finish_pending(damf_server *s, hipStream_t st, bool beside_chain) {
   if (rc != DAMF_OK) fail_all(s, rc);
 }
 
-void do_step(damf_server *s, std::vector<Req *> &step) {
+// ---- chunk-rank tuner.  The chain's cost per net entry depends on the chunk
+// rank r (core size d + r against the number of chunks); the tuner runs
+// kTuneSteps steps at each candidate rank, keeps the one with the least chain
+// time per net entry, and records it in the cache file under a key of the
+// device architecture, n, d, precision and the graph size (log2 of m).
+
+std::string tune_key(damf_ctx *c) {
+  hipDeviceProp_t prop{};
+  (void)hipGetDeviceProperties(&prop, c->device);
+  char buf[256];
+  const int64_t m = std::max<int64_t>(1, c->out.nnz_built);
+  std::snprintf(buf, sizeof buf, "%s n=%lld d=%d precision=%d log2m=%d", prop.gcnArchName,
+                (long long)c->n, c->d, c->split ? 1 : 0, (int)std::floor(std::log2((double)m)));
+  return std::string(buf);
+}
+
+int tune_cache_lookup(const char *path, const std::string &key) {
+  if (!path) return 0;
+  FILE *f = std::fopen(path, "r");
+  if (!f) return 0;
+  char line[512];
+  int r = 0;
+  while (std::fgets(line, sizeof line, f)) {
+    const std::string ln(line);
+    const size_t at = ln.rfind(" r=");
+    if (at != std::string::npos && ln.compare(0, at, key) == 0 && at == key.size())
+      r = std::atoi(ln.c_str() + at + 3);  // the last entry for the key wins
+  }
+  std::fclose(f);
+  return r;
+}
+
+void tune_cache_store(const char *path, const std::string &key, int r) {
+  if (!path) return;
+  FILE *f = std::fopen(path, "a");
+  if (!f) return;
+  std::fprintf(f, "%s r=%d\n", key.c_str(), r);
+  std::fclose(f);
+}
+
+int tune_candidates(damf_ctx *c, int *out) {
+  int cnt = 0;
+  for (int r : kTuneRanks)
+    if (r <= c->cfg.max_side && c->d + r <= kMaxCore) out[cnt++] = r;
+  return cnt;
+}
+
+// before a step: the rank to use
+void tune_before(damf_server *s) {
+  if (s->tune_idx < 0) return;
+  int cand[4];
+  tune_candidates(s->c, cand);
+  s->c->cfg.max_core_rank = cand[s->tune_idx];
+}
+
+// after a step: record its chain time per net entry; move on or decide
+void tune_after(damf_server *s, double chain_ms, int64_t net) {
+  if (s->tune_idx < 0 || net <= 0) return;
+  s->tune_ms[s->tune_idx] += chain_ms;
+  s->tune_net[s->tune_idx] += (double)net;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    ++s->tuner_steps;
+  }
+  if (--s->tune_left > 0) return;
+  int cand[4];
+  const int nc = tune_candidates(s->c, cand);
+  if (s->tune_idx + 1 < nc) {
+    ++s->tune_idx;
+    s->tune_left = kTuneSteps;
+    return;
+  }
+  int best = 0;
+  for (int i = 1; i < nc; ++i)
+    if (s->tune_ms[i] / s->tune_net[i] < s->tune_ms[best] / s->tune_net[best]) best = i;
+  s->c->cfg.max_core_rank = cand[best];
+  s->tune_idx = -1;
+  {
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->tuned_rank = cand[best];
+  }
+  tune_cache_store(s->tune_path.empty() ? nullptr : s->tune_path.c_str(), s->tune_key, cand[best]);
+}
+
+void do_step(damf_server *s, std::vector<Part> &step) {
   damf_ctx *c = s->c;
   const double t_start = s->now_us();
   const int nseg = (int)step.size();
@@ -152,16 +271,19 @@ void do_step(damf_server *s, std::vector<Req *> &step) {
     step_index = s->steps++;
     s->step_reqs_sum += nseg;
   }
+  tune_before(s);
   for (int i = 0; i < nseg; ++i) {
-    Req *r = step[i];
-    std::memcpy(s->h_src + k, r->src.data(), r->k * sizeof(int32_t));
-    std::memcpy(s->h_dst + k, r->dst.data(), r->k * sizeof(int32_t));
-    std::memcpy(s->h_op + k, r->op.data(), r->k * sizeof(int8_t));
-    k += r->k;
+    Req *r = step[i].r;
+    const int64_t off = step[i].off, len = step[i].len;
+    std::memcpy(s->h_src + k, r->src.data() + off, len * sizeof(int32_t));
+    std::memcpy(s->h_dst + k, r->dst.data() + off, len * sizeof(int32_t));
+    std::memcpy(s->h_op + k, r->op.data() + off, len * sizeof(int8_t));
+    k += len;
     seg_end[i] = (int32_t)k;
-    r->start_us = t_start;
+    if (r->parts++ == 0) r->start_us = t_start;
     r->step = step_index;
     r->step_requests = nseg;
+    r->chunk_rank = c->cfg.max_core_rank;
   }
   {
     std::lock_guard<std::mutex> lk(s->mu);
@@ -177,8 +299,8 @@ void do_step(damf_server *s, std::vector<Req *> &step) {
     return;
   }
   for (int i = 0; i < nseg; ++i) {
-    step[i]->net = c->ws.seg_stats_host[2 * i];
-    step[i]->chunks = c->ws.seg_stats_host[2 * i + 1];
+    step[i].r->net += c->ws.seg_stats_host[2 * i];
+    step[i].r->chunks += c->ws.seg_stats_host[2 * i + 1];
   }
   st = step_chain(c, h);
   // the previous step's Step 4 runs beside this step's chunks
@@ -186,6 +308,11 @@ void do_step(damf_server *s, std::vector<Req *> &step) {
   if (st == DAMF_OK) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) st = api_dev_fail(c, e, "chain");
+  }
+  if (st == DAMF_OK) st = step_check(c, h);
+  if (st == DAMF_OK && h.n_chunks > 0) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) tune_after(s, ms, h.n_net);
   }
   if (st == DAMF_OK) st = step_graph(c, h);
   if (st == DAMF_OK) st = step_finish(c, h);
@@ -241,13 +368,25 @@ void worker_main(damf_server *s) {
       if (s->stop && (s->queue.empty() || s->paused)) break;
       continue;
     }
-    std::vector<Req *> step;
+    // whole requests while they fit; a request longer than a step runs
+    // alone, one part of max_step_ops ops per step
+    std::vector<Part> step;
     int64_t tot = 0;
-    while (!s->queue.empty() && (int)step.size() < s->cfg.max_step_requests &&
-           tot + s->queue.front()->k <= s->cfg.max_step_ops) {
-      tot += s->queue.front()->k;
-      step.push_back(s->queue.front());
-      s->queue.pop_front();
+    while (!s->queue.empty() && (int)step.size() < s->cfg.max_step_requests) {
+      Req *f = s->queue.front();
+      const int64_t rem = f->k - f->sched;
+      if (rem <= s->cfg.max_step_ops - tot) {
+        step.push_back(Part{f, f->sched, rem, true});
+        f->sched = f->k;
+        tot += rem;
+        s->queue.pop_front();
+        continue;
+      }
+      if (step.empty()) {
+        step.push_back(Part{f, f->sched, (int64_t)s->cfg.max_step_ops, false});
+        f->sched += s->cfg.max_step_ops;
+      }
+      break;
     }
     lk.unlock();
     do_step(s, step);
@@ -278,6 +417,10 @@ void damf_server_config_default(damf_server_config *cfg) {
   cfg->max_step_requests = kMaxRequests;
   cfg->overlap_push = 1;
   cfg->start_paused = 0;
+  cfg->admit_device_bytes = 0;
+  cfg->max_request_ops = 1 << 16;
+  cfg->autotune = 0;
+  cfg->tune_cache = nullptr;
 }
 
 damf_status damf_server_create(damf_ctx *ctx, const damf_server_config *cfg, damf_server **out) {
@@ -289,7 +432,9 @@ damf_status damf_server_create(damf_ctx *ctx, const damf_server_config *cfg, dam
   else
     damf_server_config_default(&cf);
   if (cf.admit_bytes < 1 || cf.max_step_ops < 1 || cf.max_step_ops > kMaxBatch ||
-      cf.max_step_requests < 1 || cf.max_step_requests > kMaxRequests)
+      cf.max_step_requests < 1 || cf.max_step_requests > kMaxRequests ||
+      cf.max_request_ops < 1 || cf.max_request_ops > kMaxRequestOps || cf.admit_device_bytes < 0 ||
+      (cf.autotune != 0 && cf.autotune != 1))
     return DAMF_E_INVALID_ARG;
   if (ctx->poisoned) return DAMF_E_STATE;
   damf_server *s = new (std::nothrow) damf_server();
@@ -310,6 +455,30 @@ damf_status damf_server_create(damf_ctx *ctx, const damf_server_config *cfg, dam
     delete s;
     return DAMF_E_DEVICE;
   }
+  if (cf.admit_device_bytes > 0) {
+    s->dev_cap = cf.admit_device_bytes;
+  } else {
+    size_t free_b = 0, total_b = 0;
+    if (hipMemGetInfo(&free_b, &total_b) != hipSuccess) free_b = 0;
+    s->dev_cap = (int64_t)(free_b / 2);
+  }
+  s->tune_key = tune_key(ctx);
+  if (cf.tune_cache) s->tune_path = cf.tune_cache;
+  s->cfg.tune_cache = nullptr;  // the caller's string need not outlive the call
+  if (cf.autotune) {
+    const int cached = tune_cache_lookup(cf.tune_cache, s->tune_key);
+    int cand[4];
+    const int nc = tune_candidates(ctx, cand);
+    bool ok = false;
+    for (int i = 0; i < nc; ++i) ok = ok || cand[i] == cached;
+    if (ok) {
+      ctx->cfg.max_core_rank = cached;
+      s->tuned_rank = cached;
+    } else if (nc > 1) {
+      s->tune_idx = 0;
+      s->tune_left = kTuneSteps;
+    }
+  }
   s->worker = std::thread(worker_main, s);
   *out = s;
   return DAMF_OK;
@@ -318,27 +487,31 @@ damf_status damf_server_create(damf_ctx *ctx, const damf_server_config *cfg, dam
 damf_status damf_submit(damf_server *s, int64_t k, const int32_t *src, const int32_t *dst,
                         const int8_t *op, int64_t *ticket) {
   if (!s || !ticket) return DAMF_E_INVALID_ARG;
-  if (k < 1 || k > s->cfg.max_step_ops || !src || !dst || !op) return DAMF_E_INVALID_ARG;
+  if (k < 1 || k > s->cfg.max_request_ops || !src || !dst || !op) return DAMF_E_INVALID_ARG;
   const int64_t n = s->c->n;
   for (int64_t i = 0; i < k; ++i)
     if (src[i] < 0 || dst[i] < 0 || src[i] >= n || dst[i] >= n || (op[i] != 1 && op[i] != -1))
       return DAMF_E_OUT_OF_RANGE;
   const int64_t bytes = 9 * k + kReqOverheadBytes;
+  const int64_t dev = kDeviceBytesPerOp * k;
   Req *r = nullptr;
   {
     std::lock_guard<std::mutex> lk(s->mu);
     if (s->dead != DAMF_OK) return DAMF_E_STATE;
-    if (s->admitted_bytes + bytes > s->cfg.admit_bytes) {
+    if (s->admitted_bytes + bytes > s->cfg.admit_bytes || s->admitted_dev + dev > s->dev_cap) {
       ++s->busy;
       return DAMF_E_BUSY;
     }
     s->admitted_bytes += bytes;
+    s->admitted_dev += dev;
     s->peak_bytes = std::max(s->peak_bytes, s->admitted_bytes);
+    s->peak_dev = std::max(s->peak_dev, s->admitted_dev);
   }
   r = new (std::nothrow) Req();
   if (r) {
     r->k = k;
     r->bytes = bytes;
+    r->dev_bytes = dev;
     r->src.assign(src, src + k);
     r->dst.assign(dst, dst + k);
     r->op.assign(op, op + k);
@@ -346,6 +519,7 @@ damf_status damf_submit(damf_server *s, int64_t k, const int32_t *src, const int
   std::lock_guard<std::mutex> lk(s->mu);
   if (!r) {
     s->admitted_bytes -= bytes;
+    s->admitted_dev -= dev;
     return DAMF_E_OOM;
   }
   r->ticket = s->next_ticket++;
@@ -383,6 +557,8 @@ damf_status damf_wait(damf_server *s, int64_t ticket, int64_t timeout_us,
     info->start_us = r->start_us;
     info->done_us = r->done_us;
     info->latency_ms = (r->done_us - r->submit_us) * 1e-3;
+    info->parts = r->parts;
+    info->chunk_rank = r->chunk_rank;
   }
   const damf_status st = r->status;
   s->reqs.erase(it);
@@ -421,6 +597,10 @@ damf_status damf_server_get_stats(damf_server *s, damf_server_stats *out) {
   out->mean_requests_per_step = s->steps ? (double)s->step_reqs_sum / (double)s->steps : 0.0;
   out->mean_ops_per_step = s->steps ? (double)s->step_ops_sum / (double)s->steps : 0.0;
   out->push_overlapped_ms = s->push_overlap_ms;
+  out->admitted_device_bytes_peak = s->peak_dev;
+  out->device_cap_bytes = s->dev_cap;
+  out->tuned_chunk_rank = s->tuned_rank;
+  out->tuner_steps = s->tuner_steps;
   return DAMF_OK;
 }
 

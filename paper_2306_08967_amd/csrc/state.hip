@@ -56,6 +56,120 @@ __global__ __launch_bounds__(256) void query_kernel(const float *Mb, const doubl
   }
 }
 
+// Undo log of one basis over a row list that may repeat rows.  Save (one
+// wave per entry, any order): log[i] = M[rows[i]], the stored words.
+__global__ __launch_bounds__(256) void undo_save_kernel(const int32_t *rows, int nrows,
+                                                        const float *M, float *log, int d) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nrows;
+       i += (int64_t)gridDim.x * 4) {
+    const int64_t row = rows[i];
+    for (int c = lane; c < d; c += 64) log[i * d + c] = M[row * d + c];
+  }
+}
+
+// Restore, by one wave walking the list in order: with R,
+// R[row] -= M[row] - log[i] (what the chain's scatters added to R along with
+// U_b), then M[row] = log[i].  Every entry of a row logged the same pre-chain
+// words, so after its first entry the difference is zero: a repeated row is
+// corrected once.  A lane always handles the same columns, so the entries of
+// one row are ordered by program order.
+__global__ __launch_bounds__(64) void undo_restore_kernel(const int32_t *rows, int nrows, float *M,
+                                                          const float *log, float *R, int d,
+                                                          bool split) {
+  const int lane = threadIdx.x;
+  for (int i = 0; i < nrows; ++i) {
+    const int64_t row = rows[i];
+    for (int c = lane; c < d; c += 64) {
+      const int64_t at = row * d + c, li = (int64_t)i * d + c;
+      if (R) R[at] -= basis_ld(M, at, split) - basis_ld(log, li, split);
+      M[at] = log[li];
+    }
+  }
+}
+
+hipError_t launch_undo_rows(damf_ctx *c, int s1_off, int n_s1, int s2_off, int n_s2, bool restore) {
+  const Workspace &w = c->ws;
+  hipStream_t s = c->stream;
+  const int32_t *l1 = w.chunk_s1 + s1_off, *l2 = w.chunk_s2 + s2_off;
+  if (!restore) {
+    if (n_s1 > 0) {
+      const Grid g = geom_rows(n_s1);
+      undo_save_kernel<<<g.blocks, g.threads, 0, s>>>(l1, n_s1, c->Ub, w.undo_u, c->d);
+    }
+    if (n_s2 > 0) {
+      const Grid g = geom_rows(n_s2);
+      undo_save_kernel<<<g.blocks, g.threads, 0, s>>>(l2, n_s2, c->Vb, w.undo_v, c->d);
+    }
+  } else {
+    if (n_s1 > 0)
+      undo_restore_kernel<<<1, 64, 0, s>>>(l1, n_s1, c->Ub, w.undo_u, c->ppr_on ? c->R : nullptr,
+                                           c->d, c->split);
+    if (n_s2 > 0)
+      undo_restore_kernel<<<1, 64, 0, s>>>(l2, n_s2, c->Vb, w.undo_v, nullptr, c->d, c->split);
+  }
+  return hipGetLastError();
+}
+
+// score[i] = <A[u_i], B[v_i]> with A, B rows of X, Y or Z (Sec. 5.2: the
+// inner product of u's context vector and v's content vector), and with
+// both_ways max(<A[u], B[v]>, <A[v], B[u]>) (undirected graphs).  A row of A
+// is Ma_b[u] Pa Sigma^(1/2) as in the query; one wave per pair, FP64
+// accumulation, pairs in a grid-stride loop.
+__global__ __launch_bounds__(256) void score_pairs_kernel(const float *Ma, const double *Pa, bool split_a,
+                                                          const float *Mb, const double *Pb, bool split_b,
+                                                          const double *sigma, int d, int64_t q,
+                                                          const int32_t *u, const int32_t *v,
+                                                          float *out, bool both_ways) {
+  __shared__ double ra[4][kMaxD], rb[4][kMaxD];
+  const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + w; i < q; i += (int64_t)gridDim.x * 4) {
+    double best = -INFINITY;
+    for (int dir = 0; dir < (both_ways ? 2 : 1); ++dir) {
+      const int64_t a = dir ? v[i] : u[i], b = dir ? u[i] : v[i];
+      for (int k = lane; k < d; k += 64) {
+        ra[w][k] = (double)basis_ld(Ma, a * d + k, split_a);
+        rb[w][k] = (double)basis_ld(Mb, b * d + k, split_b);
+      }
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+      double dot = 0.0;
+      for (int c = lane; c < d; c += 64) {
+        double xa = 0.0, xb = 0.0;
+        for (int k = 0; k < d; ++k) {
+          xa = fma(ra[w][k], Pa[k * d + c], xa);
+          xb = fma(rb[w][k], Pb[k * d + c], xb);
+        }
+        dot = fma(xa * sigma[c], xb, dot);  // sqrt(sigma_c)^2
+      }
+      dot = wave_sum(dot);
+      best = fmax(best, dot);
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    }
+    if (lane == 0) out[i] = (float)best;
+  }
+}
+
+hipError_t launch_score_pairs(damf_ctx *c, int which_a, int which_b, int64_t q, const int32_t *d_u,
+                              const int32_t *d_v, float *d_out, bool both_ways) {
+  if (q <= 0) return hipSuccess;
+  auto mat = [&](int which, const float **M, const double **P, bool *split) {
+    *M = (which == DAMF_X) ? c->Ub : (which == DAMF_Y) ? c->Vb : c->Zb;
+    *P = (which == DAMF_Y) ? c->P + (size_t)c->d * c->d : c->P;
+    *split = c->split && which != DAMF_Z;
+  };
+  const float *Ma, *Mb;
+  const double *Pa, *Pb;
+  bool sa, sb;
+  mat(which_a, &Ma, &Pa, &sa);
+  mat(which_b, &Mb, &Pb, &sb);
+  const Grid g = geom_query(q);
+  score_pairs_kernel<<<g.blocks, g.threads, 0, c->stream>>>(Ma, Pa, sa, Mb, Pb, sb, c->sigma, c->d, q,
+                                                            d_u, d_v, d_out, both_ways);
+  return hipGetLastError();
+}
+
 hipError_t launch_count_bad_ids(const int32_t *d_nodes, int64_t q, int64_t n, int64_t *d_bad,
                                 hipStream_t s) {
   clear_counter_kernel<<<1, 64, 0, s>>>(d_bad);

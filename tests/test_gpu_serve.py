@@ -168,7 +168,9 @@ def test_server_admission_by_memory(damf):
     ctx = damf.Context.init(cfg, s0, t0)
     pool = _pool(rng, n, 100, loops=False)
     r1, r2 = _requests(rng, n, 2, pool, 30, 30)
-    cap = 9 * len(r1[0]) + 64 + 10
+    # room for either request alone (9 B per op + 64 per request), not for both
+    cap = 9 * max(len(r1[0]), len(r2[0])) + 64 + 10
+    assert 9 * (len(r1[0]) + len(r2[0])) + 128 > cap
     with damf.Server(ctx, admit_bytes=cap, start_paused=1) as srv:
         t1 = srv.submit(*r1)
         assert t1 is not None
@@ -184,3 +186,105 @@ def test_server_admission_by_memory(damf):
     with pytest.raises(damf.DamfError):
         ctx.update(np.array([n], np.int32), np.array([0], np.int32), np.array([1], np.int8))
     ctx.close()
+
+
+def test_server_request_above_step_cap(damf):
+    """A 10,000-op request (the serving workload's clip) runs as parts of at
+    most max_step_ops ops; the result equals damf_update on the same parts."""
+    _say("case server_large_request")
+    rng = np.random.default_rng(31)
+    n, d = 3000, 16
+    s0, t0 = chung_lu_directed(n, 24000, 2.1, 12)
+    cfg = damf.default_config(n, d, directed=True, alpha=0.15, eps=1e-5, max_core_rank=16,
+                              max_side=32, tau=1e-6, oversample=6, seed=5)
+    cm = damf.Context.init(cfg, s0, t0)
+    ca = damf.Context.init(cfg, s0, t0)
+    pool = _pool(rng, n, 20000, loops=False)
+    e = rng.integers(0, len(pool[0]), 10000)
+    big = (pool[0][e].copy(), pool[1][e].copy(),
+           np.where(rng.random(10000) < 0.1, -1, 1).astype(np.int8))
+    small = _requests(rng, n, 3, pool, 50, 200)
+    with damf.Server(cm, start_paused=1) as srv:
+        tickets = [srv.submit(*r) for r in [small[0], big, small[1], small[2]]]
+        srv.resume()
+        infos = [srv.wait(t, timeout_us=120_000_000) for t in tickets]
+    assert [i["status"] for i in infos] == [0, 0, 0, 0]
+    assert infos[1]["parts"] == 2 and infos[1]["ops"] == 10000
+    # alone: the small request, the big one in parts of 8192 and 1808, the rest
+    ca.update(*small[0])
+    ca.update(*(a[:8192] for a in big))
+    ca.update(*(a[8192:] for a in big))
+    ca.update(*small[1])
+    ca.update(*small[2])
+    _same_factorization(cm, ca)
+    cm.close()
+    ca.close()
+
+
+def test_server_admission_by_device_memory(damf):
+    _say("case server_device_admission")
+    rng = np.random.default_rng(4)
+    n, d = 200, 8
+    s0, t0 = chung_lu_directed(n, 1500, 2.1, 2)
+    cfg = damf.default_config(n, d, directed=True, alpha=1.0, max_core_rank=8, max_side=16,
+                              oversample=4)
+    ctx = damf.Context.init(cfg, s0, t0)
+    pool = _pool(rng, n, 100, loops=False)
+    r1, r2 = _requests(rng, n, 2, pool, 30, 30)
+    # room for either request alone (24 B per op), not for both
+    cap = 24 * max(len(r1[0]), len(r2[0])) + 10
+    assert 24 * (len(r1[0]) + len(r2[0])) > cap
+    with damf.Server(ctx, admit_device_bytes=cap, start_paused=1) as srv:
+        t1 = srv.submit(*r1)
+        assert t1 is not None
+        assert srv.submit(*r2) is None
+        srv.resume()
+        srv.wait(t1, timeout_us=30_000_000)
+        t2 = srv.submit(*r2)
+        assert t2 is not None
+        srv.wait(t2, timeout_us=30_000_000)
+        st = srv.stats()
+    assert st["busy_rejects"] == 1 and st["admitted_device_bytes_peak"] <= cap
+    assert st["device_cap_bytes"] == cap
+    ctx.close()
+
+
+def test_server_chunk_rank_tuner(damf, tmp_path):
+    """The tuner tries the chunk ranks, keeps one, writes the cache; a second
+    server reads the cache and does not tune; every request reports the rank
+    it ran with, and replaying them alone with those ranks is bit-identical."""
+    _say("case server_tuner")
+    rng = np.random.default_rng(41)
+    n, d = 2000, 32
+    s0, t0 = chung_lu_directed(n, 20000, 2.1, 9)
+    cfg = damf.default_config(n, d, directed=True, alpha=1.0, max_core_rank=64, max_side=64,
+                              tau=1e-6, oversample=8, seed=4)
+    cm = damf.Context.init(cfg, s0, t0)
+    ca = damf.Context.init(cfg, s0, t0)
+    pool = _pool(rng, n, 3000)
+    reqs = _requests(rng, n, 24, pool, 150, 600)
+    cache = str(tmp_path / "tune.txt")
+    infos = []
+    with damf.Server(cm, autotune=1, tune_cache=cache, max_step_requests=1) as srv:
+        tickets = [srv.submit(*r) for r in reqs]
+        infos = [srv.wait(t, timeout_us=120_000_000) for t in tickets]
+        st = srv.stats()
+    ranks = [i["chunk_rank"] for i in infos]
+    _say(f"  tuned rank {st['tuned_chunk_rank']} after {st['tuner_steps']} steps; ranks {ranks}")
+    assert st["tuned_chunk_rank"] in (16, 32, 48, 64) and st["tuner_steps"] >= 16
+    assert set(ranks[:16]) == {16, 32, 48, 64}
+    line = open(cache).read().strip().splitlines()[-1]
+    assert line.endswith(f" r={st['tuned_chunk_rank']}")
+    for r, info in zip(reqs, infos):
+        ca.set_chunk_rank(info["chunk_rank"])
+        ca.update(*r)
+    _same_factorization(cm, ca)
+    # a second server: the cached rank, no tuning
+    with damf.Server(cm, autotune=1, tune_cache=cache) as srv:
+        t = srv.submit(*reqs[0])
+        i = srv.wait(t, timeout_us=60_000_000)
+        st2 = srv.stats()
+    assert st2["tuner_steps"] == 0 and st2["tuned_chunk_rank"] == st["tuned_chunk_rank"]
+    assert i["chunk_rank"] == st["tuned_chunk_rank"]
+    cm.close()
+    ca.close()
