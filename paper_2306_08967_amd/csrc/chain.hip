@@ -116,87 +116,114 @@ constexpr int NG = NT / 128;  // groups of 128 threads (one column each)
 
 // ---------------------------------------------------------------- Step 1
 
-// MP[i][c] = sum_q Mb[rows[i]][q] * Pm[q][c]  (rows of U or V in the current basis)
-// C = A B for one 512-thread workgroup, FP64, M <= 32 MR, N <= 128, any K:
-// K is staged through LDS KC values at a time (A as [k][i], B as [k][c]);
-// thread (rb, cb) accumulates rows MR rb .. + MR and columns 8 cb .. + 8 in
-// registers, reading both operands as 16-byte pairs.  aload(i, k), bload(k,
-// c) fetch the operands; cstore(i, c, v) writes the result.  Uses
-// KC (32 MR + 130) doubles of LDS; starts and ends with the caller's LDS free.
-template <int MR>
-constexpr int wg_gemm_lds() {
-  return 32 * (32 * MR + 2 + 128 + 2);
-}
-template <int MR, class AL, class BL, class CS>
-__device__ __forceinline__ void wg_gemm(int M, int N, int K, AL aload, BL bload, CS cstore,
-                                        double *lds) {
-  constexpr int KC = 32, MT = 32 * MR, AS = MT + 2, BS = 128 + 2;
-  static_assert(MR % 2 == 0 && NT == 512 && KC * (AS + BS) <= LDS_DOUBLES, "wg_gemm shape");
-  double *At = lds, *Bt = lds + KC * AS;
-  const int cb = tid() & 15, rb = tid() >> 4;
-  double acc[MR][8];
+// C = A B for one 512-thread workgroup on FP64 MFMA (v_mfma_f64_16x16x4f64),
+// M, N <= 128, any K.  The 16 x 16 output tiles t = I TN + J (TN = ceil(N /
+// 16)) are dealt to the 8 waves (wave w: t = w, w + 8, ...; at most 8 each,
+// one v4f64 accumulator per tile).  K is staged through LDS KC = 16 values at
+// a time, A as [i][k] (odd row stride, conflict-free fragment reads) and B as
+// [k][j]; the next stage is fetched into registers while the current one is
+// used (A with consecutive threads along k, B along j: both coalesced for
+// row-major operands).  aload(i, k), bload(k, c) fetch the operands; cstore(i,
+// c, v) writes the result.  Uses wg_mma_lds() doubles of LDS; starts and ends
+// with the caller's LDS free.
+typedef double v4f64 __attribute__((ext_vector_type(4)));
+constexpr int kMmaKC = 16, kMmaAS = kMmaKC + 1, kMmaBS = 128 + 2;
+constexpr int wg_mma_lds() { return 128 * kMmaAS + kMmaKC * kMmaBS; }
+// NQ tiles per wave: tile slot q of wave w is t = w + 8 q, clamped to the last
+// tile (a clamped slot repeats that tile's MFMAs and is not stored), so the
+// inner loop has no branches.
+template <int NQ, class AL, class BL, class CS>
+__device__ __forceinline__ void wg_mma_n(int M, int N, int K, int TN, int T, AL aload, BL bload,
+                                         CS cstore, double *lds) {
+  constexpr int KC = kMmaKC, AS = kMmaAS, BS = kMmaBS;
+  constexpr int PF = KC * 128 / NT;  // operand values per thread per stage
+  static_assert(NT == 512 && PF * NT == KC * 128 && wg_mma_lds() <= LDS_DOUBLES, "wg_mma shape");
+  double *As = lds, *Bs = lds + 128 * AS;
+  const int lane = tid() & 63;
+  const int w = __builtin_amdgcn_readfirstlane(tid() >> 6);
+  v4f64 acc[NQ];
+  int ia[NQ], ib[NQ];  // fragment offsets of the wave's tiles
 #pragma unroll
-  for (int q = 0; q < MR; ++q) {
-#pragma unroll
-    for (int u = 0; u < 8; ++u) acc[q][u] = 0.0;
+  for (int q = 0; q < NQ; ++q) {
+    acc[q] = v4f64{0.0, 0.0, 0.0, 0.0};
+    const int t = min(w + 8 * q, T - 1), I = t / TN, J = t - I * TN;
+    ia[q] = (16 * I + (lane & 15)) * AS + (lane >> 4);
+    ib[q] = (lane >> 4) * BS + 16 * J + (lane & 15);
   }
+  double pa[PF], pb[PF];
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid() + q * NT;
+      const int i = e / KC, kk = e % KC, kb = e >> 7, c = e & 127;
+      pa[q] = (i < M && k0 + kk < K) ? aload(i, k0 + kk) : 0.0;
+      pb[q] = (c < N && k0 + kb < K) ? bload(k0 + kb, c) : 0.0;
+    }
+  };
+  fetch(0);
   for (int k0 = 0; k0 < K; k0 += KC) {
-    const int kn = min(KC, K - k0);
-    __syncthreads();
-    for (int e = tid(); e < KC * MT; e += NT) {
-      const int kk = e % KC, i = e / KC;
-      At[kk * AS + i] = (kk < kn && i < M) ? aload(i, k0 + kk) : 0.0;
-    }
-    for (int e = tid(); e < KC * 128; e += NT) {
-      const int c = e & 127, kk = e >> 7;
-      Bt[kk * BS + c] = (kk < kn && c < N) ? bload(k0 + kk, c) : 0.0;
+    __syncthreads();  // the previous stage's fragments are read
+#pragma unroll
+    for (int q = 0; q < PF; ++q) {
+      const int e = tid() + q * NT;
+      As[(e / KC) * AS + e % KC] = pa[q];
+      Bs[(e >> 7) * BS + (e & 127)] = pb[q];
     }
     __syncthreads();
-    for (int kk = 0; kk < kn; ++kk) {
-      double av[MR], bv[8];
-      const double2 *ap = reinterpret_cast<const double2 *>(At + kk * AS + MR * rb);
-      const double2 *bp = reinterpret_cast<const double2 *>(Bt + kk * BS + 8 * cb);
+    if (k0 + KC < K) fetch(k0 + KC);
 #pragma unroll
-      for (int q = 0; q < MR / 2; ++q) {
-        const double2 x = ap[q];
-        av[2 * q] = x.x;
-        av[2 * q + 1] = x.y;
+    for (int ks = 0; ks < KC; ks += 4) {
+      double a[NQ], b[NQ];  // all of the step's fragments first, then the MFMAs
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        a[q] = As[ia[q] + ks];
+        b[q] = Bs[ib[q] + ks * BS];
       }
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        const double2 x = bp[u];
-        bv[2 * u] = x.x;
-        bv[2 * u + 1] = x.y;
-      }
-#pragma unroll
-      for (int q = 0; q < MR; ++q) {
-#pragma unroll
-        for (int u = 0; u < 8; ++u) acc[q][u] = fma(av[q], bv[u], acc[q][u]);
-      }
+      for (int q = 0; q < NQ; ++q) acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[q], b[q], acc[q], 0, 0, 0);
     }
   }
+  // output layout: register v of lane group g (lanes 16 g .. 16 g + 15) holds
+  // row 4 v + g of the tile, column lane % 16
 #pragma unroll
-  for (int q = 0; q < MR; ++q) {
-    const int i = MR * rb + q;
+  for (int q = 0; q < NQ; ++q) {
+    const int t = w + 8 * q;
+    if (t < T) {
+      const int I = t / TN, J = t - I * TN;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int c = 8 * cb + u;
-      if (i < M && c < N) cstore(i, c, acc[q][u]);
+      for (int v = 0; v < 4; ++v) {
+        const int i = 16 * I + 4 * v + (lane >> 4), c = 16 * J + (lane & 15);
+        if (i < M && c < N) cstore(i, c, acc[q][v]);
+      }
     }
   }
   __syncthreads();
 }
+template <class AL, class BL, class CS>
+__device__ __forceinline__ void wg_mma(int M, int N, int K, AL aload, BL bload, CS cstore, double *lds) {
+  const int TN = __builtin_amdgcn_readfirstlane((N + 15) >> 4);
+  const int T = __builtin_amdgcn_readfirstlane(((M + 15) >> 4) * TN);
+  if (T > 32)
+    wg_mma_n<8>(M, N, K, TN, T, aload, bload, cstore, lds);
+  else if (T > 16)
+    wg_mma_n<4>(M, N, K, TN, T, aload, bload, cstore, lds);
+  else if (T > 8)
+    wg_mma_n<2>(M, N, K, TN, T, aload, bload, cstore, lds);
+  else if (T > 0)
+    wg_mma_n<1>(M, N, K, TN, T, aload, bload, cstore, lds);
+}
 
-__device__ __noinline__ void gather_project(const float *Mb, const int32_t *rows, int s, const double *Pm,
+// MP[i][c] = sum_q Mb[rows[i]][q] * Pm[q][c]  (rows of U or V in the current basis)
+__device__ __forceinline__ void gather_project(const float *Mb, const int32_t *rows, int s, const double *Pm,
                                int d, double *lds, double *MP, bool split) {
-  wg_gemm<2>(
+  wg_mma(
       s, d, d, [&](int i, int q) { return (double)basis_ld(Mb, (int64_t)rows[i] * d + q, split); },
       [&](int q, int c) { return Pm[q * d + c]; }, [&](int i, int c, double v) { MP[i * d + c] = v; },
       lds);
 }
 
 // Dense D (s1 x s2) into LDS from the chunk entries.
-__device__ __noinline__ void build_D(const ChunkState &cs, double *D) {
+__device__ __forceinline__ void build_D(const ChunkState &cs, double *D) {
   for (int e = tid(); e < cs.s1 * cs.s2; e += NT) D[e] = 0.0;
   __syncthreads();
   for (int e = tid(); e < cs.ne; e += NT) {
@@ -210,8 +237,8 @@ __device__ __noinline__ void build_D(const ChunkState &cs, double *D) {
 
 // W^T (k x d) for one side into Wg (global): side 0 (B): mode 1: W_B^T = UP;
 // mode 0: W_B^T = D^T UP.  side 1 (C): mode 1: W_C^T = D VP; mode 0: W_C^T =
-// VP.  D (LDS, s1 x s2) stays readable; stage is wg_gemm's LDS.
-__device__ __noinline__ void build_Wt(const ChunkState &cs, int side, int d, const double *D,
+// VP.  D (LDS, s1 x s2) stays readable; stage is wg_mma's LDS.
+__device__ __forceinline__ void build_Wt(const ChunkState &cs, int side, int d, const double *D,
                                       const double *MP, double *Wg, double *stage) {
   const int k = cs.k, s2 = cs.s2;
   const bool copy = side ? (cs.mode == 0) : (cs.mode != 0);
@@ -219,12 +246,12 @@ __device__ __noinline__ void build_Wt(const ChunkState &cs, int side, int d, con
     for (int e = tid(); e < k * d; e += NT) Wg[e] = MP[e];
     __syncthreads();
   } else if (side == 0) {
-    wg_gemm<2>(
+    wg_mma(
         k, d, cs.s1, [&](int t, int i) { return D[i * s2 + t]; },
         [&](int i, int c) { return MP[i * d + c]; }, [&](int t, int c, double v) { Wg[t * d + c] = v; },
         stage);
   } else {
-    wg_gemm<2>(
+    wg_mma(
         k, d, s2, [&](int t, int j) { return D[t * s2 + j]; },
         [&](int j, int c) { return MP[j * d + c]; }, [&](int t, int c, double v) { Wg[t * d + c] = v; },
         stage);
@@ -234,7 +261,7 @@ __device__ __noinline__ void build_Wt(const ChunkState &cs, int side, int d, con
 // G = B^T B - W^T W (side B) or C^T C - W^T W (side C), k x k in LDS (row
 // stride KMAX), as one product [B^T | W] [B | -W]^T (B^T B = D^T D, C^T C =
 // D D^T, or I); also returns max(1, max diag of B^T B) through *bmax.
-__device__ __noinline__ void build_gram(const ChunkState &cs, int side, int d, const double *D,
+__device__ __forceinline__ void build_gram(const ChunkState &cs, int side, int d, const double *D,
                                         const double *Wg, double *G, double *bmax_out, double *stage) {
   const int k = cs.k, s2 = cs.s2;
   __shared__ double s_bmax;
@@ -249,7 +276,7 @@ __device__ __noinline__ void build_gram(const ChunkState &cs, int side, int d, c
     for (int x = 0; x < sB; ++x) v = fma(bel(a, x), bel(a, x), v);
     if (v > 1.0) atomicMax((unsigned long long *)&s_bmax, __double_as_longlong(v));
   }
-  wg_gemm<2>(
+  wg_mma(
       k, k, sB + d, [&](int a, int x) { return (x < sB) ? bel(a, x) : Wg[a * d + x - sB]; },
       [&](int x, int b) { return (x < sB) ? bel(b, x) : -Wg[b * d + x - sB]; },
       [&](int a, int b, double v) { G[a * KMAX + b] = (ident && a == b) ? 1.0 + v : v; }, stage);
@@ -260,13 +287,14 @@ __device__ __noinline__ void build_gram(const ChunkState &cs, int side, int d, c
 // (value, index) of the larger value, ties to the lower index: a total
 // order, so a butterfly leaves every lane with the same winner.
 __device__ __forceinline__ void argmax_take(double &v, int &i, double ov, int oi) {
-  const bool take = (ov > v) || (ov == v && oi < i);
+  // non-short-circuit operators: a select, not a branch, per stage
+  const bool take = (ov > v) | ((ov == v) & (oi < i));
   v = take ? ov : v;
   i = take ? oi : i;
 }
 template <int CTRL>
 __device__ __forceinline__ void argmax_dpp(double &v, int &i) {
-  argmax_take(v, i, dpp_d<CTRL>(v), __builtin_amdgcn_update_dpp(0, i, CTRL, 0xF, 0xF, false));
+  argmax_take(v, i, dpp_d<CTRL>(v), __builtin_amdgcn_mov_dpp(i, CTRL, 0xF, 0xF, false));
 }
 __device__ __forceinline__ void argmax_wave(double &v, int &i) {
   argmax_dpp<0xB1>(v, i);   // quad_perm [1,0,3,2]
@@ -294,70 +322,83 @@ __device__ __forceinline__ void argmax_wave(double &v, int &i) {
     i = ia;
   }
 }
-// Pivoted Cholesky of the k x k PSD matrix G (LDS, row stride KMAX), by wave
-// 0 with row i of G in the VGPRs of lane i: each step picks the largest
-// remaining diagonal (wave argmax), stops when it is <= thr, else passes the
-// pivot row through LDS (rb, KMAX doubles) and applies the rank-1 update lane
-// by lane.  Rows are never moved: on return G[i][j] (j < rho) holds L in the
-// original row order (row i's entry for the j-th pivot; 0 for steps after row
-// i was itself the pivot), perm[j] the j-th pivot for j < rho and the other
-// rows in increasing order after it.  Returns rho.
-__device__ __noinline__ int pivoted_cholesky(double *G, int k, double thr, int *perm, double *rb) {
-  __shared__ int s_rho;
-  if (tid() < 64) {
-    const int i = tid();
-    const bool row = i < k;
-    double g[KMAX];
+// Pivoted Cholesky of the k x k PSD matrix G (LDS, row stride KMAX, k <= 64)
+// by the whole workgroup: thread (row i = tid % 64, column group cg = tid /
+// 64) keeps the Schur complement's entries (i, 8 cg .. 8 cg + 7) in VGPRs,
+// and every wave keeps its diagonal (lane i: row i).  Each step every wave
+// picks the largest remaining diagonal v (the same wave argmax on the same
+// values, so the same pivot everywhere) and stops when it is <= thr; the wave
+// holding the pivot's column writes that column u of the Schur complement to
+// LDS; after one barrier every thread applies the rank-1 update u u^T / v to
+// its eight entries and its diagonal copy, and the owner stores column j of L
+// (u / sqrt(v)) into G.  The column buffer alternates between two halves of
+// lc by step parity, so a wave that runs ahead never overwrites a column
+// another wave still reads; lc holds 2 KMAX doubles of LDS.  Rows are never
+// moved: on return G[i][j] (j < rho) holds L in the original row order (row
+// i's entry for the j-th pivot; 0 for steps after row i was itself the
+// pivot), perm[j] the j-th pivot for j < rho and the other rows in increasing
+// order after it.  Returns rho.
+__device__ __forceinline__ double sel8(double g0, double g1, double g2, double g3, double g4, double g5,
+                                       double g6, double g7, int u) {
+  // a select tree on the bits of a wave-uniform u (no runtime-indexed array,
+  // which would live in scratch memory)
+  const double a0 = (u & 1) ? g1 : g0, a1 = (u & 1) ? g3 : g2;
+  const double a2 = (u & 1) ? g5 : g4, a3 = (u & 1) ? g7 : g6;
+  const double b0 = (u & 2) ? a1 : a0, b1 = (u & 2) ? a3 : a2;
+  return (u & 4) ? b1 : b0;
+}
+__device__ __forceinline__ int pivoted_cholesky(double *G, int k, double thr, int *perm, double *lc) {
+  static_assert(KMAX == 64 && NT == 512, "one row per lane, eight column groups");
+  const int i = tid() & 63;
+  const int cg = __builtin_amdgcn_readfirstlane(tid() >> 6);
+  const bool row = i < k;
+  double g[8];
 #pragma unroll
-    for (int l = 0; l < KMAX; ++l) g[l] = (row && l < k) ? G[i * KMAX + l] : 0.0;
-    double dg = row ? G[i * KMAX + i] : 0.0;
-    uint64_t done = 0;  // rows already used as pivots (wave-uniform)
-    bool mine_done = false;
-    int rho = k;
-    for (int j = 0; j < k; ++j) {
-      double v = (row && !mine_done) ? dg : -1.0;
-      int p = i;
-      argmax_wave(v, p);
-      p = __builtin_amdgcn_readfirstlane(p);
-      if (!(v > thr)) {
-        rho = j;
-        break;
-      }
-      const double ljj = sqrt(v), inv = 1.0 / ljj;
-      if (i == p) {
-        double2 *w = reinterpret_cast<double2 *>(rb);
-#pragma unroll
-        for (int l = 0; l < KMAX / 2; ++l) w[l] = make_double2(g[2 * l], g[2 * l + 1]);
-      }
-      __builtin_amdgcn_wave_barrier();
-      // column j of L for every row: 0 for earlier pivots, ljj for p
-      const double li = (!row || mine_done) ? 0.0 : ((i == p) ? ljj : rb[i] * inv);
-      G[i * KMAX + j] = li;  // lane i only touches row i, already in VGPRs
-      if (i == 0) perm[j] = p;
-      done |= 1ull << p;
-      mine_done = mine_done || (i == p);
-      // g[l] -= L[i][j] L[l][j]; entries of pivoted columns l become
-      // meaningless but are never read for a row still in play
-      const double2 *r2 = reinterpret_cast<const double2 *>(rb);
-      const double lis = li * inv;
-#pragma unroll
-      for (int l2 = 0; l2 < KMAX / 2; ++l2) {
-        const double2 x = r2[l2];
-        g[2 * l2] = fma(-lis, x.x, g[2 * l2]);
-        g[2 * l2 + 1] = fma(-lis, x.y, g[2 * l2 + 1]);
-      }
-      dg = fma(-li, li, dg);
-      __builtin_amdgcn_wave_barrier();
-    }
-    // the remaining rows after the pivots, in increasing order
-    if (row && !((done >> i) & 1)) {
-      const uint64_t below = (i == 0) ? 0ull : (~done & ((1ull << i) - 1));
-      perm[rho + __builtin_popcountll(below)] = i;
-    }
-    if (i == 0) s_rho = rho;
+  for (int u = 0; u < 8; ++u) {
+    const int c = 8 * cg + u;
+    g[u] = (row && c < k) ? G[i * KMAX + c] : 0.0;
   }
-  __syncthreads();
-  const int rho = s_rho;
+  double dg = row ? G[i * KMAX + i] : 0.0;
+  __syncthreads();  // every thread has read G before column 0 of L overwrites it
+  uint64_t done = 0;  // rows already used as pivots (uniform)
+  int rho = k;
+  for (int j = 0; j < k; ++j) {
+    double v = (row && !((done >> i) & 1)) ? dg : -1.0;
+    int p = i;
+    argmax_wave(v, p);
+    p = __builtin_amdgcn_readfirstlane(p);
+    if (!(v > thr)) {  // the same decision in every wave
+      rho = j;
+      break;
+    }
+    double *col = lc + (j & 1) * KMAX;
+    const bool owner = cg == (p >> 3);
+    const bool live = row && !((done >> i) & 1);
+    if (owner) {
+      const double gp = sel8(g[0], g[1], g[2], g[3], g[4], g[5], g[6], g[7], p & 7);
+      col[i] = live ? gp : 0.0;  // the pivot's own entry is v
+      if (i == 0) perm[j] = p;
+    }
+    const double inv = rcp_nr(v);
+    __syncthreads();
+    done |= 1ull << p;
+    const double ui = col[i];
+    const double si = ui * inv;
+    const double2 *u2 = reinterpret_cast<const double2 *>(col + 8 * cg);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const double2 x = u2[q];
+      g[2 * q] = fma(-si, x.x, g[2 * q]);
+      g[2 * q + 1] = fma(-si, x.y, g[2 * q + 1]);
+    }
+    dg = fma(-si, ui, dg);
+    if (owner && row) G[i * KMAX + j] = ui * rsqrt_nr(v);  // column j of L
+  }
+  // the remaining rows after the pivots, in increasing order
+  if (cg == 0 && row && !((done >> i) & 1)) {
+    const uint64_t below = (i == 0) ? 0ull : (~done & ((1ull << i) - 1));
+    perm[rho + __builtin_popcountll(below)] = i;
+  }
   __syncthreads();
   return rho;
 }
@@ -365,7 +406,7 @@ __device__ __noinline__ int pivoted_cholesky(double *G, int k, double thr, int *
 // L (k x k, pivoted order) and R (rho x k): with Lo = G in original row
 // order, L[a][b] = Lo[perm[a]][b] (b < rho) and R[i][perm[j]] = L[j][i] (j >= i),
 // i.e. R = L^T Pi^T.
-__device__ __noinline__ void store_factor(const double *G, int k, int rho, const int *perm, double *Lg,
+__device__ __forceinline__ void store_factor(const double *G, int k, int rho, const int *perm, double *Lg,
                              double *Rg) {
   for (int e = tid(); e < KMAX * KMAX; e += NT) {
     const int i = e >> 6, j = e & 63;
@@ -698,39 +739,58 @@ __device__ __noinline__ void complete_basis(int d, int NB, int NC, double *scr, 
 // ---------------------------------------------------------------- Step 3
 
 // Y = T E_bot (k x d): solve L1^T X = E_bot (rho x d) and scatter rows by perm.
-// side 0 uses E (rows d.. of EG), side 1 uses H (rows d.. of HG).
-__device__ __noinline__ void solve_Y(int side, int d, int k, int rho, const int *perm, const double *Lg,
+// side 0 uses E (rows d.. of EG), side 1 uses H (rows d.. of HG).  Back
+// substitution by four adjacent lanes per column (d <= 128 columns, 512
+// threads): lane q sums the terms j = i + 1 + q, i + 5 + q, ... into two
+// accumulators, a quad reduction (DPP) gives every lane the total, and lane 0
+// of the quad writes X[i][c] (LDS operations of one wave complete in order, so
+// the quad reads it back in the next row).  The diagonal's reciprocals are
+// formed once.
+__device__ __forceinline__ void solve_Y(int side, int d, int k, int rho, const int *perm, const double *Lg,
                         double *scr, double *lds) {
+  static_assert(NT == 4 * DMAX, "four lanes per column");
   double *Y = scr + (side ? OFF_YC : OFF_YB);
   const double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
-  double *L = lds;              // k x k
-  double *X = lds + KMAX * KMAX;  // rho x d
+  double *L = lds;                               // k x k
+  double *X = lds + KMAX * KMAX;                 // rho x d
+  double *rinv = lds + KMAX * KMAX + KMAX * DMAX;  // rho
   for (int e = tid(); e < k * k; e += NT) L[e] = Lg[e];
   for (int e = tid(); e < rho * d; e += NT) {
     int i = e / d, c = e - i * d;
     X[e] = side ? HG[(d + i) * DMAX + c] : EG[c * NPMAX + d + i];
   }
+  for (int i = tid(); i < rho; i += NT) rinv[i] = 1.0 / Lg[i * k + i];
   __syncthreads();
-  const int c = tid();
-  if (c < d) {
-    for (int i = rho - 1; i >= 0; --i) {
-      double v = X[i * d + c];
-      for (int j = i + 1; j < rho; ++j) v -= L[j * k + i] * X[j * d + c];
-      X[i * d + c] = v / L[i * k + i];
+  const int c = tid() >> 2, q = tid() & 3;
+  const bool col = c < d;
+  for (int i = rho - 1; i >= 0; --i) {
+    double v0 = 0.0, v1 = 0.0;
+    if (col) {
+      int j = i + 1 + q;
+      for (; j + 4 < rho; j += 8) {
+        v0 = fma(L[j * k + i], X[j * d + c], v0);
+        v1 = fma(L[(j + 4) * k + i], X[(j + 4) * d + c], v1);
+      }
+      if (j < rho) v0 = fma(L[j * k + i], X[j * d + c], v0);
     }
+    double v = v0 + v1;
+    v += dpp_d<0xB1>(v);  // quad_perm [1,0,3,2]
+    v += dpp_d<0x4E>(v);  // quad_perm [2,3,0,1]
+    if (col && q == 0) X[i * d + c] = (X[i * d + c] - v) * rinv[i];
+    __builtin_amdgcn_wave_barrier();
   }
   __syncthreads();
-  for (int e = tid(); e < k * d; e += NT) Y[e] = 0.0;
-  __syncthreads();
-  for (int e = tid(); e < rho * d; e += NT) {
+  // rows of Y: the solved X rows at their pivots' positions, zeros for the
+  // dropped directions (perm is a permutation of 0 .. k - 1)
+  for (int e = tid(); e < k * d; e += NT) {
     int i = e / d, c2 = e - i * d;
-    Y[perm[i] * d + c2] = X[e];
+    Y[perm[i] * d + c2] = (i < rho) ? X[e] : 0.0;
   }
   __syncthreads();
 }
 
 // F = E_top - W Y (d x d) and the row corrections, as workgroup GEMMs.
-__device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, int d, double *scr,
+__device__ __forceinline__ void build_F_and_delta(const ChunkState &cs, int side, int d, double *scr,
                                   double *lds, int ch) {
   const int k = cs.k, s2 = cs.s2;
   const double *Y = scr + (side ? OFF_YC : OFF_YB);
@@ -738,7 +798,7 @@ __device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, i
   const double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
   double *F = scr + (side ? OFF_FV : OFF_FU);
   double *Dl = scr + off_dl(side, ch);
-  wg_gemm<4>(
+  wg_mma(
       d, d, k, [&](int i, int t) { return Wt[t * d + i]; }, [&](int t, int c) { return Y[t * d + c]; },
       [&](int i, int c, double v) {
         F[i * d + c] = (side ? HG[i * DMAX + c] : EG[c * NPMAX + i]) - v;
@@ -754,7 +814,7 @@ __device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, i
   }
   double *D = lds;  // s1 x s2
   double *stage = lds + KMAX * KMAX;
-  static_assert(KMAX * KMAX + wg_gemm_lds<2>() <= LDS_DOUBLES, "Step 3 staging does not fit");
+  static_assert(KMAX * KMAX + wg_mma_lds() <= LDS_DOUBLES, "Step 3 staging does not fit");
   for (int e = tid(); e < cs.s1 * s2; e += NT) D[e] = 0.0;
   __syncthreads();
   for (int e = tid(); e < cs.ne; e += NT) {
@@ -765,18 +825,18 @@ __device__ __noinline__ void build_F_and_delta(const ChunkState &cs, int side, i
   }
   __syncthreads();
   if (side == 0)
-    wg_gemm<2>(
+    wg_mma(
         cs.s1, d, k, [&](int i, int t) { return D[i * s2 + t]; }, [&](int t, int c) { return Y[t * d + c]; },
         [&](int i, int c, double v) { Dl[i * d + c] = v; }, stage);
   else
-    wg_gemm<2>(
+    wg_mma(
         s2, d, k, [&](int i, int t) { return D[t * s2 + i]; }, [&](int t, int c) { return Y[t * d + c]; },
         [&](int i, int c, double v) { Dl[i * d + c] = v; }, stage);
 }
 
 // Pn = Po F (d x d).
-__device__ __noinline__ void mul_PF(int d, const double *Po, const double *F, double *Pn, double *lds) {
-  wg_gemm<4>(
+__device__ __forceinline__ void mul_PF(int d, const double *Po, const double *F, double *Pn, double *lds) {
+  wg_mma(
       d, d, d, [&](int i, int q) { return Po[i * d + q]; }, [&](int q, int c) { return F[q * d + c]; },
       [&](int i, int c, double v) { Pn[i * d + c] = v; }, lds);
 }
@@ -1134,7 +1194,7 @@ __global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, 
   double bmax = 1.0;
   double *D = lds;                              // s1 x s2 (<= 4096)
   double *stage = lds + KMAX * KMAX;            // GEMM staging (< 8192)
-  static_assert(wg_gemm_lds<2>() <= KMAX * DMAX, "Step 1 GEMM staging must end before G");
+  static_assert(wg_mma_lds() <= KMAX * DMAX, "Step 1 GEMM staging must end before G");
   double *G = lds + KMAX * KMAX + KMAX * DMAX;  // k x k, row stride KMAX
   double *Wg = scr + (side ? OFF_WC : OFF_WB);  // W^T, k x d
   build_D(cs, D);

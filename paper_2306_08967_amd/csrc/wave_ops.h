@@ -9,11 +9,15 @@
 
 namespace damf {
 
+// DPP move of a double.  Every CTRL used here (quad_perm, row_mirror,
+// row_half_mirror) reads a lane of the same 16-lane row with all rows and
+// banks enabled, so every lane is written and the old value is never used:
+// mov_dpp, which leaves it undefined, saves zeroing the destination.
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double x) {
   int lo = __double2loint(x), hi = __double2hiint(x);
-  lo = __builtin_amdgcn_update_dpp(0, lo, CTRL, 0xF, 0xF, false);
-  hi = __builtin_amdgcn_update_dpp(0, hi, CTRL, 0xF, 0xF, false);
+  lo = __builtin_amdgcn_mov_dpp(lo, CTRL, 0xF, 0xF, false);
+  hi = __builtin_amdgcn_mov_dpp(hi, CTRL, 0xF, 0xF, false);
   return __hiloint2double(hi, lo);
 }
 
