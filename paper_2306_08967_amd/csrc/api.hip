@@ -131,6 +131,7 @@ damf_status alloc_state(damf_ctx *c) {
   API_HIP(c, hipEventCreate(&c->ev_k[1]), "event");
   API_HIP(c, hipStreamCreateWithFlags(&c->scatter_stream, hipStreamNonBlocking), "stream");
   for (auto &e : c->ev_back) API_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
+  for (auto &e : c->ev_front) API_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
   for (auto &e : c->ev_scatter) API_HIP(c, hipEventCreateWithFlags(&e, hipEventDisableTiming), "event");
   if (c->cfg.kernel_timing)
     for (auto &e : c->ev_core) API_HIP(c, hipEventCreate(&e), "event");
@@ -167,6 +168,8 @@ void free_ctx(damf_ctx *c) {
   for (auto &e : c->ev_core)
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->ev_back)
+    if (e) (void)hipEventDestroy(e);
+  for (auto &e : c->ev_front)
     if (e) (void)hipEventDestroy(e);
   for (auto &e : c->ev_scatter)
     if (e) (void)hipEventDestroy(e);
@@ -326,9 +329,17 @@ damf_status step_graph(damf_ctx *c, const BatchHeader &h) {
   return DAMF_OK;
 }
 
-damf_status step_chain(damf_ctx *c, const BatchHeader &h) {
+damf_status step_chain(damf_ctx *c, const BatchHeader &h, int nseg) {
   if (h.n_chunks <= 0) return DAMF_OK;
   hipStream_t s = c->stream;
+  // a request's first chunk that meets the previous request's last chunk
+  // waits for that chunk's scatter (see chain_hold)
+  std::memset(c->chain_hold, 0, sizeof(c->chain_hold));
+  for (int i = 0, ch0 = 0; i < nseg; ++i) {
+    if (ch0 > 0 && ch0 < h.n_chunks && ((h.meets_prev[ch0 >> 6] >> (ch0 & 63)) & 1))
+      c->chain_hold[ch0 >> 6] |= 1ull << (ch0 & 63);
+    ch0 += c->ws.seg_stats_host[2 * i + 1];
+  }
   // undo log: the touched rows of U_b, V_b, and P, Sigma before the chunks
   const size_t dd = 2 * (size_t)c->d * c->d;
   API_HIP(c, launch_undo_rows(c, 0, h.s1_total, 0, h.s2_total, false), "undo log");
@@ -546,7 +557,7 @@ damf_status update_apply(damf_ctx *c, const BatchHeader &h, int64_t k, int nseg,
   hipStream_t s = c->stream;
   damf_status st;
   if ((st = step_graph(c, h)) != DAMF_OK) return st;
-  if ((st = step_chain(c, h)) != DAMF_OK) return st;
+  if ((st = step_chain(c, h, nseg)) != DAMF_OK) return st;
   if ((st = step_check(c, h)) != DAMF_OK) return st;
   // re-orthogonalisation due: before Step 4, so the push restores max |R| <= eps
   bool reorth_refused = false;

@@ -555,68 +555,36 @@ __device__ __noinline__ int core_svd(const ChunkState &cs, int d, const double *
     }
   }
   __syncthreads();
-  // ---- H = K^T E Theta^-1 for the top d: rows of K and E staged through LDS
-  // 32 at a time; thread (jb, cb) accumulates rows j = JR jb .. + JR of H and
-  // columns c = 8 cb .. + 8 (register block, operands read as 16-byte pairs).
+  // ---- H = K^T E Theta^-1 for the top d, from K = D + L_m R_m^T (D =
+  // diag(Sigma, 0)): K^T E = D E + R_m (L_m^T E), two products on FP64 MFMA
+  // (2 k NB d + 2 NC k d flops instead of 2 NC NB d for K^T E itself).
   {
-    constexpr int JR = NP / 32;
-    constexpr int ET = DMAX + 2, KT = NP + 2;  // padded row strides (even: 16-byte rows)
-    static_assert(32 * (ET + KT) <= LDS_DOUBLES && NT == 512, "H staging does not fit");
-    const int cb = tid() & 15, jb = tid() >> 4;
-    double acc[JR][8];
-#pragma unroll
-    for (int q = 0; q < JR; ++q) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[q][u] = 0.0;
+    double *T1 = lds + 6000;            // L_m^T E, k x d (row stride DMAX)
+    double *rth = lds + 6000 + KMAX * DMAX;  // 1 / theta_c, 0 below the cut
+    static_assert(wg_mma_lds() <= 6000 && 6000 + KMAX * DMAX + DMAX <= LDS_DOUBLES, "H staging");
+    for (int c = tid(); c < d; c += NT) rth[c] = (TH[c] > cut) ? 1.0 / TH[c] : 0.0;
+    wg_mma(
+        k, d, NB, [&](int t, int i) { return (i < d) ? WBt[t * d + i] : RB[(i - d) * k + t]; },
+        [&](int i, int c) { return EG[c * NPMAX + i]; }, [&](int t, int c, double v) { T1[t * DMAX + c] = v; },
+        lds);
+    for (int j0 = 0; j0 < NC; j0 += 128) {
+      wg_mma(
+          min(128, NC - j0), d, k,
+          [&](int jj, int t) {
+            const int j = j0 + jj;
+            return (j < d) ? WCt[t * d + j] : RC[(j - d) * k + t];
+          },
+          [&](int t, int c) { return T1[t * DMAX + c]; },
+          [&](int jj, int c, double v) {
+            const int j = j0 + jj;
+            const double de = (j < d) ? sigma[j] * EG[c * NPMAX + j] : 0.0;
+            HG[j * DMAX + c] = (v + de) * rth[c];
+          },
+          lds);
     }
-    double *Et = lds;            // [32][ET]
-    double *Kt = lds + 32 * ET;  // [32][KT]
-    for (int i0 = 0; i0 < NB; i0 += 32) {
-      for (int e = tid(); e < 32 * DMAX; e += NT) {
-        const int ii = e & 31, cc = e >> 5;
-        Et[ii * ET + cc] = (cc < d && i0 + ii < NB) ? EG[cc * NPMAX + i0 + ii] : 0.0;
-      }
-      for (int e = tid(); e < 32 * NP; e += NT) {
-        const int ii = e & 31, jj = e >> 5;
-        Kt[ii * KT + jj] = (i0 + ii < NB) ? KG[jj * NPMAX + i0 + ii] : 0.0;
-      }
-      __syncthreads();
-      for (int ii = 0; ii < 32; ++ii) {
-        double ev[8], kv[JR];
-        const double2 *ep = reinterpret_cast<const double2 *>(Et + ii * ET + 8 * cb);
-        const double2 *kp = reinterpret_cast<const double2 *>(Kt + ii * KT + JR * jb);
-#pragma unroll
-        for (int u = 0; u < 4; ++u) {
-          const double2 x = ep[u];
-          ev[2 * u] = x.x;
-          ev[2 * u + 1] = x.y;
-        }
-#pragma unroll
-        for (int q = 0; q < JR / 2; ++q) {
-          const double2 x = kp[q];
-          kv[2 * q] = x.x;
-          kv[2 * q + 1] = x.y;
-        }
-#pragma unroll
-        for (int q = 0; q < JR; ++q) {
-#pragma unroll
-          for (int u = 0; u < 8; ++u) acc[q][u] = fma(kv[q], ev[u], acc[q][u]);
-        }
-      }
-      __syncthreads();
-    }
-#pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int c = 8 * cb + u;
-      if (c < d) {
-        const double sc = TH[c];
-        const double inv = (sc > cut) ? 1.0 / sc : 0.0;
-#pragma unroll
-        for (int q = 0; q < JR; ++q) {
-          const int j = JR * jb + q;
-          HG[j * DMAX + c] = (j < NC) ? acc[q][u] * inv : 0.0;
-        }
-      }
+    for (int e = tid(); e < (NP - NC) * d; e += NT) {
+      const int j = NC + e / d, c = e - (e / d) * d;
+      HG[j * DMAX + c] = 0.0;
     }
   }
   __syncthreads();
@@ -1178,7 +1146,13 @@ struct PhaseClock {
   }
 };
 
-__global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, const double *Pc) {
+// Step 1 of chunk ch.  With pend, the solve-and-scatter of chunk ch - 1 has
+// not run yet (it waits for this kernel): the rows this chunk shares with
+// chunk ch - 1 are read as they were before that chunk, and its row
+// corrections are added here, since (M_b + dM P^-1) P = M_b P + dM with P
+// the projection after chunk ch - 1.
+__global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, const double *Pc,
+                                                         int pend) {
   __shared__ __align__(16) double lds[LDS_DOUBLES];
   __shared__ __align__(16) int ilds[1024];
   const int side = blockIdx.x;
@@ -1188,8 +1162,27 @@ __global__ __launch_bounds__(NT) void chain_front_kernel(ChainParams p, int ch, 
   ChunkState cs = chunk_state(p, ch, nullptr);
   const int k = cs.k;
   PhaseClock clk;
-  gather_project(side ? p.Vb : p.Ub, side ? cs.S2 : cs.S1, side ? cs.s2 : cs.s1,
-                 Pc + side * d * d, d, lds, scr + (side ? OFF_VP : OFF_UP), p.split);
+  const int32_t *rows = side ? cs.S2 : cs.S1;
+  const int ns = side ? cs.s2 : cs.s1;
+  double *MP = scr + (side ? OFF_VP : OFF_UP);
+  gather_project(side ? p.Vb : p.Ub, rows, ns, Pc + side * d * d, d, lds, MP, p.split);
+  if (pend) {
+    const ChunkDesc pd = p.chunks[ch - 1];
+    const int32_t *prow = side ? p.S2 + pd.s2_off : p.S1 + pd.s1_off;
+    const int pn = side ? pd.s2 : pd.s1;
+    const double *Dl = scr + off_dl(side, ch - 1);
+    int *at = ilds;  // row i's position in chunk ch - 1's list, or -1
+    for (int i = tid(); i < ns; i += NT) {
+      const int a = (int)lower_bound(prow, (int64_t)pn, rows[i]);
+      at[i] = (a < pn && prow[a] == rows[i]) ? a : -1;
+    }
+    __syncthreads();
+    for (int e = tid(); e < ns * d; e += NT) {
+      const int i = e / d, c = e - i * d, a = at[i];
+      if (a >= 0) MP[e] += Dl[a * d + c];
+    }
+    __syncthreads();
+  }
   clk.tick(p.stats, 0);
   double bmax = 1.0;
   double *D = lds;                              // s1 x s2 (<= 4096)
@@ -1376,10 +1369,26 @@ hipError_t enqueue_chain(damf_ctx *c, int first, int last, int n_chunks, const u
   c->core_timed = 0;
   for (int ch = first; ch < last; ++ch) {
     const int j = ch - first;
-    if (j >= 2) DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(ch - 2) & 3], 0));
-    if (j >= 1 && ((meets[ch >> 6] >> (ch & 63)) & 1))
+    const bool meet = j >= 1 && ((meets[ch >> 6] >> (ch & 63)) & 1);
+    const bool hold = meet && ((c->chain_hold[ch >> 6] >> (ch & 63)) & 1);
+    if (hold) {
+      // chunk ch - 1's solve-and-scatter first, and the front reads its rows
+      chain_scatter_kernel<<<2, NT, 0, t>>>(p, ch - 1, Pbuf[j & 1]);
+      DAMF_HIP(hipEventRecord(c->ev_scatter[(ch - 1) & 3], t));
       DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(ch - 1) & 3], 0));
-    chain_front_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[j & 1]);
+    }
+    // the front reads rows that chunk ch - 2's solve-and-scatter wrote; the
+    // corrections of chunk ch - 1 to the rows they share it adds itself
+    if (j >= 2) DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(ch - 2) & 3], 0));
+    const bool pend = meet && !hold;
+    chain_front_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[j & 1], pend ? 1 : 0);
+    if (j >= 1 && !hold) {
+      // chunk ch - 1's solve-and-scatter, once this front has read its rows
+      DAMF_HIP(hipEventRecord(c->ev_front[ch & 3], s));
+      DAMF_HIP(hipStreamWaitEvent(t, c->ev_front[ch & 3], 0));
+      chain_scatter_kernel<<<2, NT, 0, t>>>(p, ch - 1, Pbuf[j & 1]);
+      DAMF_HIP(hipEventRecord(c->ev_scatter[(ch - 1) & 3], t));
+    }
     const bool tm = timed && j < damf_ctx::kCoreTimed;
     if (tm) DAMF_HIP(hipEventRecord(c->ev_core[2 * j], s));
     chain_core_kernel<<<1, NT, 0, s>>>(p, ch);
@@ -1390,9 +1399,9 @@ hipError_t enqueue_chain(damf_ctx *c, int first, int last, int n_chunks, const u
     chain_back_kernel<<<2, NT, 0, s>>>(p, ch, Pbuf[j & 1], Pbuf[(j + 1) & 1]);
     DAMF_HIP(hipEventRecord(c->ev_back[ch & 3], s));
     DAMF_HIP(hipStreamWaitEvent(t, c->ev_back[ch & 3], 0));
-    chain_scatter_kernel<<<2, NT, 0, t>>>(p, ch, Pbuf[(j + 1) & 1]);
-    DAMF_HIP(hipEventRecord(c->ev_scatter[ch & 3], t));
   }
+  chain_scatter_kernel<<<2, NT, 0, t>>>(p, last - 1, Pbuf[(last - first) & 1]);
+  DAMF_HIP(hipEventRecord(c->ev_scatter[(last - 1) & 3], t));
   DAMF_HIP(hipStreamWaitEvent(s, c->ev_scatter[(last - 1) & 3], 0));
   DAMF_HIP(hipGetLastError());
   double *Pc = Pbuf[(last - first) & 1];
@@ -1413,10 +1422,13 @@ hipError_t launch_chain_graph(damf_ctx *c, int n_chunks, const uint64_t *meets, 
   if (n_chunks < 1 || n_chunks > c->cfg.graph_chunks || n_chunks > 64 || c->cfg.kernel_timing)
     return hipSuccess;
   // the captured sequence depends only on the chunk count and on which
-  // chunks wait for their predecessor's scatter
-  uint64_t bits = 0;
-  for (int ch = 1; ch < n_chunks; ++ch) bits |= ((meets[0] >> ch) & 1ull) << ch;
-  const uint64_t key = (bits << 7) | (uint64_t)n_chunks;
+  // chunks meet their predecessor and which of those wait for its scatter
+  uint64_t bits = 0, hold = 0;
+  for (int ch = 1; ch < n_chunks; ++ch) {
+    bits |= ((meets[0] >> ch) & 1ull) << ch;
+    hold |= ((c->chain_hold[0] >> ch) & 1ull) << ch;
+  }
+  const auto key = std::make_tuple(bits, hold & bits, n_chunks);
   auto it = c->graphs.find(key);
   if (it == c->graphs.end()) {
     if (c->graphs.size() >= 256) {
@@ -1449,12 +1461,13 @@ hipError_t launch_chain(damf_ctx *c, int first, int last, int n_chunks, const ui
   if (first >= last) return hipSuccess;
   // The projections alternate between P and Pnext from chunk to chunk,
   // starting from P at chunk `first`.  The solve-and-scatter of chunk ch runs
-  // on the scatter stream after chunk ch's back and beside chunk ch + 1; the
-  // context stream waits for it before the front of chunk ch + 1 when that
-  // chunk's S1 or S2 meets chunk ch's (the front reads those rows of U_b,
-  // V_b), and always before the front of chunk ch + 2 (whose back reuses
-  // chunk ch's P buffer and row-correction parity).  The result is the same
-  // as with every step in one stream.
+  // on the scatter stream after chunk ch's back and chunk ch + 1's front, and
+  // beside chunk ch + 1's core: that front reads the rows it shares with
+  // chunk ch as they were before chunk ch and adds chunk ch's row
+  // corrections itself.  The context stream waits for it before the front of
+  // chunk ch + 2 (which reads rows it wrote, and whose back reuses chunk ch's
+  // P buffer and row-correction parity).  The result is the same as with
+  // every step in one stream, up to the rounding of the stored rows.
   return enqueue_chain(c, first, last, n_chunks, meets, false);
 }
 

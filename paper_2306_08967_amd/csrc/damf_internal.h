@@ -6,6 +6,8 @@
 
 #include <cstdint>
 #include <string>
+#include <map>
+#include <tuple>
 #include <unordered_map>
 #include <vector>
 
@@ -169,9 +171,10 @@ struct damf_ctx {
   hipEvent_t ev_core[2 * kCoreTimed] = {};  // created only with cfg.kernel_timing
   int core_timed = 0;                       // launches timed by the last chain
   // Step 3's solve-and-scatter runs on scatter_stream, beside the next
-  // chunk's core; ev_front / ev_scatter order the two streams (rings of 4)
+  // chunk's core; ev_back / ev_front / ev_scatter order the two streams
+  // (rings of 4)
   hipStream_t scatter_stream = nullptr;
-  hipEvent_t ev_back[4] = {}, ev_scatter[4] = {};
+  hipEvent_t ev_back[4] = {}, ev_front[4] = {}, ev_scatter[4] = {};
   damf_init_info init_info{};
   double push_ms = 0.0, push_bytes = 0.0;  // accumulated by ppr_push
   double wall_khz = 100000.0;               // device wall-clock rate (kHz)
@@ -181,7 +184,14 @@ struct damf_ctx {
   int last_explicit = 0;     // chunks of the last batch applied explicitly
   // captured chain launch sequences (graph_chunks), keyed by chunk count and
   // the chunks that wait for their predecessor
-  std::unordered_map<uint64_t, hipGraphExec_t> graphs;
+  // captured chains by (bits of chunks that meet their predecessor, bits of
+  // chunks that wait for its scatter, chunk count)
+  std::map<std::tuple<uint64_t, uint64_t, int>, hipGraphExec_t> graphs;
+  // chunks of this batch whose front waits for the previous chunk's
+  // solve-and-scatter instead of adding its corrections: the first chunk of a
+  // request (after the first) that meets the previous request's last chunk,
+  // so that a request's result does not depend on being served with others
+  uint64_t chain_hold[damf::kMaxBatch / 64] = {};
   int64_t graph_launches = 0;
   bool split = false;  // U_b, V_b as BF16 pairs (precision form)
 };
@@ -199,7 +209,7 @@ damf_status step_prepare(damf_ctx *c, int64_t k, const int32_t *src, const int32
 // Structural PPR fix-up and CSR edits of A and A^T (asynchronous).
 damf_status step_graph(damf_ctx *c, const BatchHeader &h);
 // Steps 1-3 over every chunk (asynchronous).
-damf_status step_chain(damf_ctx *c, const BatchHeader &h);
+damf_status step_chain(damf_ctx *c, const BatchHeader &h, int nseg);
 // Waits for the chunks, re-runs a batch whose projection turned singular
 // (explicit chunks), poisons on a non-finite core, and flushes the lazy
 // projections when their condition estimate passes the configured limit.

@@ -302,7 +302,7 @@ void do_step(damf_server *s, std::vector<Part> &step) {
     step[i].r->net += c->ws.seg_stats_host[2 * i];
     step[i].r->chunks += c->ws.seg_stats_host[2 * i + 1];
   }
-  st = step_chain(c, h);
+  st = step_chain(c, h, nseg);
   // the previous step's Step 4 runs beside this step's chunks
   if (st == DAMF_OK) finish_pending(s, s->push_stream, h.n_chunks > 0);
   if (st == DAMF_OK) {
