@@ -106,40 +106,62 @@ __device__ __forceinline__ double wave_max_d(double x) {
   return x;
 }
 
-// Index of the pair whose wave total 16-lane row `row` holds in reduced slot
-// q, and whether lane sl of that row computes it (slot sl).
+// Index of the pair whose wave total lands in slot q of 16-lane row `row`;
+// slot q is held by the four lanes 4 q .. 4 q + 3 of the row, and the first
+// of them ("plane" lane) computes the pair's rotation.
 template <class S>
 __device__ __forceinline__ int jw_pair(int row, int q) {
-  return (q < S::QF) ? q + (row & 1) * S::QF + (row >> 1) * S::H : (S::H - 1) + (row >> 1) * S::H;
+  return q + (row & 1) * S::QF + (row >> 1) * S::H;
 }
+__device__ __forceinline__ int jw_slot(int lane) { return (lane >> 2) & 3; }
 template <class S>
-__device__ __forceinline__ bool jw_plane(int row, int sl) {
-  return sl < S::QF || (S::QL && sl == S::QF && (row & 1) == 0);
+__device__ __forceinline__ bool jw_plane(int lane) {
+  return (lane & 3) == 0 && jw_slot(lane) < S::QF;
 }
 
-// v[p] (p < B): per-lane partial sums.  On return out[q] (q < QS), in every
-// lane of 16-lane row R, is the wave total of v[jw_pair(R, q)].
+// v[p] (p < B): per-lane partial sums.  Returns, in the four lanes of slot q
+// of 16-lane row R, the wave total of v[jw_pair(R, q)] (q < QF; lanes of
+// slots QF .. 3 return zero or partial sums).  Lane swaps across the halves
+// and quarters of the wave (permlane32 / permlane16 swaps), then a reduce-
+// scatter inside each row: lanes l and l ^ 8 keep two slots each (DPP
+// row_ror:8), lanes l and 7 - l of each half-row one each (row_half_mirror),
+// and a quad sum.
 template <class S>
-__device__ __forceinline__ void jw_reduce(const double (&v)[S::B], double (&out)[S::QS]) {
-  constexpr int B = S::B, H = S::H, QF = S::QF;
+__device__ __forceinline__ double jw_reduce(const double (&v)[S::B]) {
+  constexpr int H = S::H, QF = S::QF;
+  static_assert(S::QL == 0 && QF >= 1 && QF <= 4, "even half count, at most four slots a row");
   double h[H];
 #pragma unroll
   for (int p = 0; p < H; ++p) h[p] = xsum32(v[p], v[p + H]);
+  double q[4];
 #pragma unroll
-  for (int q = 0; q < QF; ++q) out[q] = row_sum16(xsum16(h[q], h[q + QF]));
-  if (S::QL) out[S::QS - 1] = row_sum16(xsum16(h[H - 1], h[H - 1]));
-  (void)B;
+  for (int i = 0; i < 4; ++i) q[i] = (i < QF) ? xsum16(h[i], h[i + QF]) : 0.0;
+  const int lane = threadIdx.x & 63;
+  const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
+  // slots 0, 1 stay in the lanes without bit 3, slots 2, 3 in the others
+  const double s0 = b3 ? q[0] : q[2], s1 = b3 ? q[1] : q[3];
+  double k0 = b3 ? q[2] : q[0], k1 = b3 ? q[3] : q[1];
+  k0 += dpp_d<0x128>(s0);  // row_ror:8, lane l ^ 8
+  k1 += dpp_d<0x128>(s1);
+  // the even slot stays in the lanes without bit 2 (row_half_mirror pairs
+  // lane l with 7 - l, which has bit 2 flipped)
+  const double sb = b2 ? k0 : k1;
+  double kb = b2 ? k1 : k0;
+  kb += dpp_d<0x141>(sb);
+  kb += dpp_d<0xB1>(kb);  // quad_perm [1,0,3,2]
+  kb += dpp_d<0x4E>(kb);  // quad_perm [2,3,0,1]
+  return kb;
 }
 
 // Exact squared norms of the wave's 2B columns into ns[].x by column id (the
 // wave holds its sweep-boundary half-blocks w and NW + w).
 template <class S>
 __device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double2 *ns, int w) {
-  constexpr int B = S::B, Q = S::QS, RPL = S::RPL;
-  const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
+  constexpr int B = S::B, RPL = S::RPL;
+  const int lane = threadIdx.x & 63, row = lane >> 4;
 #pragma unroll
   for (int half = 0; half < 2; ++half) {
-    double v[B], out[Q];
+    double v[B];
 #pragma unroll
     for (int p = 0; p < B; ++p) {
       double s = 0.0;
@@ -147,11 +169,8 @@ __device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double2 *ns, int w)
       for (int r = 0; r < RPL; ++r) s = fma(J.a[half * B + p][r], J.a[half * B + p][r], s);
       v[p] = s;
     }
-    jw_reduce<S>(v, out);
-    double mine = out[0];
-#pragma unroll
-    for (int q = 1; q < Q; ++q) mine = (sl == q) ? out[q] : mine;
-    if (jw_plane<S>(row, sl)) ns[jw_col<S>(w, half * B + jw_pair<S>(row, sl))].x = mine;
+    const double mine = jw_reduce<S>(v);
+    if (jw_plane<S>(lane)) ns[jw_col<S>(w, half * B + jw_pair<S>(row, jw_slot(lane)))].x = mine;
   }
 }
 
@@ -179,9 +198,9 @@ template <class S, class PM, class IdF>
 __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
                                         double floor2, double tol2, double conv2, IdF ids, int &rot,
                                         int &big, int &skip) {
-  constexpr int B = S::B, Q = S::QS, RPL = S::RPL;
-  const int lane = threadIdx.x & 63, row = lane >> 4, sl = lane & 15;
-  double v[B], g[Q];
+  constexpr int B = S::B, RPL = S::RPL;
+  const int lane = threadIdx.x & 63, row = lane >> 4;
+  double v[B];
 #pragma unroll
   for (int p = 0; p < B; ++p) {
     double s = 0.0;
@@ -189,13 +208,10 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
     for (int r = 0; r < RPL; ++r) s = fma(J.a[PM::a(p)][r], J.a[PM::b(p)][r], s);
     v[p] = s;
   }
-  jw_reduce<S>(v, g);
-  // lane (row, q < Q) computes the rotation of pair jw_pair(row, q)
-  double myg = g[0];
-#pragma unroll
-  for (int q = 1; q < Q; ++q) myg = (sl == q) ? g[q] : myg;
-  const bool plane = jw_plane<S>(row, sl);
-  const int pair = plane ? jw_pair<S>(row, sl) : 0;
+  // the plane lane of slot q of row R computes the rotation of pair jw_pair(R, q)
+  const double myg = jw_reduce<S>(v);
+  const bool plane = jw_plane<S>(lane);
+  const int pair = plane ? jw_pair<S>(row, jw_slot(lane)) : 0;
   int it, ib;
   ids(pair, it, ib);
   const double2 nsi = ns[it], nsj = ns[ib];
@@ -209,9 +225,13 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
   // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 g),
   // as sign(be - al) 2g / (|be - al| + sqrt((be - al)^2 + 4 g^2))
   const double dd = be - al, gg = doit ? 2.0 * gt : 0.0;
+  // t itself needs no more than about 1e-14 (any angle near the optimal one
+  // shrinks the pair's inner product quadratically, and the rotation stays
+  // orthogonal because c is formed from this t to full precision): one Newton
+  // step on each hardware estimate
   const double q2 = fma(dd, dd, gg * gg);
-  const double den = fabs(dd) + q2 * rsqrt_nr(q2);
-  const double t = doit ? (dd >= 0.0 ? gg : -gg) * rcp_nr(den) : 0.0;
+  const double den = fabs(dd) + q2 * rsqrt_nr1(q2);
+  const double t = doit ? (dd >= 0.0 ? gg : -gg) * rcp_nr1(den) : 0.0;
   const double q1 = fma(t, t, 1.0);
   const double cs = rsqrt_nr(q1);
   const double inv = rcp_nr(di * dj);

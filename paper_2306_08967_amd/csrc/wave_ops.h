@@ -48,6 +48,16 @@ __device__ __forceinline__ double rsqrt_nr(double x) {
   y = y * fma(-hx * y, y, 1.5);
   return y;
 }
+// One Newton step each: about 2^-46 relative from the hardware estimates,
+// for quantities that need no more.
+__device__ __forceinline__ double rsqrt_nr1(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  return y * fma(-0.5 * x * y, y, 1.5);
+}
+__device__ __forceinline__ double rcp_nr1(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  return y * fma(-x, y, 2.0);
+}
 __device__ __forceinline__ double rcp_nr(double x) {
   double y = __builtin_amdgcn_rcp(x);
   y = y * fma(-x, y, 2.0);
