@@ -593,7 +593,7 @@ def billion_main(args):
         "stage_ms_mean": {k: mean(k) for k in ("ms_prepare", "ms_chain", "ms_enhance",
                                                "ms_core_kernel", "ms_push_kernel")},
         "per_batch_mean": {k: mean(k) for k in ("chunks", "sweeps", "push_rounds", "pushes",
-                                                "push_edges")},
+                                                "push_edges", "small_sv_columns")},
         "residual_max": ctx.residual_max(),
         "roofline": core_roofline(infos),
         "cpu_baseline": None,
@@ -694,7 +694,7 @@ def c3_main(args):
         "stage_ms_mean": {k: mean(k) for k in ("ms_prepare", "ms_chain", "ms_enhance", "ms_reorth",
                                                "ms_core_kernel", "ms_push_kernel")},
         "per_batch_mean": {k: mean(k) for k in ("net_entries", "chunks", "sweeps", "push_rounds",
-                                                "pushes")},
+                                                "pushes", "small_sv_columns")},
         "accuracy": accuracy,
         "residual_max": ctx.residual_max(),
         "roofline": core_roofline(infos),

@@ -159,7 +159,7 @@ typedef struct {
                              as a captured graph (graph_chunks)                */
   int32_t small_sv_columns;/* right singular vectors of the cores that were
                              re-orthogonalised because their singular value
-                             was below 1e7 jacobi_tol sigma_1 (H = K^T E
+                             was below 1e5 jacobi_tol sigma_1 (H = K^T E
                              Theta^-1 amplifies E's residual non-orthogonality
                              by sigma_1 / theta there)                        */
   int32_t pad1_;

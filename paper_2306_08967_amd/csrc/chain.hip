@@ -1226,9 +1226,10 @@ __global__ __launch_bounds__(NT) void chain_core_kernel(ChainParams p, int ch) {
     nonfinite = core_svd<3>(cs, d, p.sigma, scr, lds, ilds, &sw, jt, p.jtol);
   if (nonfinite && tid() == 0) atomicOr(&p.stats->numeric_error, kNumericCore);
   clk.tick(p.stats, 2);
-  // small singular values: H's columns re-orthogonalised (the threshold puts
-  // the amplified Jacobi tolerance at 1e-7), zero ones completed
-  const double hrel = fmin(0.5, p.jtol * 1e7);
+  // small singular values: H's columns re-orthogonalised (the threshold bounds
+  // the amplified Jacobi tolerance by 1e-5 in the worst case; the sweeps'
+  // quadratic convergence leaves far less), zero ones completed
+  const double hrel = fmin(0.5, p.jtol * 1e5);
   int *redo = ilds + 600;
   int small_h = 0;
   if (scr[OFF_TH + d - 1] <= hrel * scr[OFF_TH]) {

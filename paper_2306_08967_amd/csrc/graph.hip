@@ -819,6 +819,15 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
   int n_rows_in = emit_sorted_entries(ent, ne, true, p.net_t, p.rows_in, p.rowpos_in, wbuf);
   // ---- phase 4: greedy chunking of the units (one wave, sequential)
   __shared__ int s_nchunks, s_maxs, s_s1tot, s_s2tot;
+  // the wave's window of 64 units and the per-request counts live in LDS: a
+  // window in VGPRs, or a read-modify-write of the counts in global memory,
+  // makes every step wait for the vector-memory counter, which the entry
+  // stores keep busy
+  __shared__ uint64_t s_wuk[64];
+  __shared__ int s_wsg[64];
+  __shared__ int s_segc[2 * kMaxRequests];
+  for (int i = threadIdx.x; i < 2 * nseg; i += kPrepThreads) s_segc[i] = 0;
+  __syncthreads();
   if (threadIdx.x < 64) {
     const int lane = threadIdx.x;
     int32_t s1v = -1, s2v = -1;  // lane-held members of S1 and S2
@@ -843,7 +852,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
         c.e_off = e_start;
         c.ne = e_cnt;
         p.chunks[nchunks] = c;
-        p.seg_stats[2 * cur_seg + 1] += 1;
+        s_segc[2 * cur_seg + 1] += 1;
       }
       maxs = max(maxs, max(s1, s2));
       s1_total += s1;
@@ -855,22 +864,22 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
       s1v = s2v = -1;
       cur_units = 0;
     };
-    // the units arrive 64 at a time, one per lane, and are read lane by lane
-    // (a global load per unit would put its latency on every step)
-    uint64_t win_uk = 0ull;
-    int win_sg = 0;
+    // the units arrive 64 at a time (one per lane, through LDS) and are read
+    // one by one (a global load per unit would put its latency on every step)
     int acc_seg = -1, acc_cnt = 0;  // lane 0: the current segment's entry count
     for (int t = 0; t < n_units; ++t) {
       if ((t & 63) == 0) {
         const int q = t + lane;
-        win_uk = (q < n_units) ? p.units[q] : 0ull;
-        win_sg = (q < n_units) ? p.unit_seg[q] : 0;
+        s_wuk[lane] = (q < n_units) ? p.units[q] : 0ull;
+        s_wsg[lane] = (q < n_units) ? p.unit_seg[q] : 0;
+        __builtin_amdgcn_wave_barrier();  // LDS operations of one wave complete in order
       }
       const int at = t & 63;
-      const uint32_t ulo = __builtin_amdgcn_readlane((uint32_t)win_uk, at);
-      const uint32_t uhi = __builtin_amdgcn_readlane((uint32_t)(win_uk >> 32), at);
+      const uint64_t ukv = s_wuk[at];
+      const uint32_t ulo = __builtin_amdgcn_readfirstlane((uint32_t)ukv);
+      const uint32_t uhi = __builtin_amdgcn_readfirstlane((uint32_t)(ukv >> 32));
       const uint64_t uk = ((uint64_t)uhi << 32) | ulo;
-      const int sg = __builtin_amdgcn_readlane(win_sg, at);
+      const int sg = __builtin_amdgcn_readfirstlane(s_wsg[at]);
       int32_t u = (int32_t)(uk >> 33), v = (int32_t)((uk >> 1) & 0x7fffffffu);
       int ins = (int)(uk & 1u);
       bool pair = !p.directed && u != v;
@@ -920,7 +929,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
         // entries per segment, flushed when the segment changes (units come
         // in segment order)
         if (sg != acc_seg) {
-          if (acc_seg >= 0) p.seg_stats[2 * acc_seg] += acc_cnt;
+          if (acc_seg >= 0) s_segc[2 * acc_seg] += acc_cnt;
           acc_seg = sg;
           acc_cnt = 0;
         }
@@ -930,7 +939,7 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
       ++cur_units;
     }
     if (cur_units > 0) close();
-    if (lane == 0 && acc_seg >= 0) p.seg_stats[2 * acc_seg] += acc_cnt;
+    if (lane == 0 && acc_seg >= 0) s_segc[2 * acc_seg] += acc_cnt;
     if (lane == 0) {
       s_nchunks = nchunks;
       s_maxs = maxs;
@@ -945,18 +954,21 @@ __global__ __launch_bounds__(kPrepThreads) void batch_prepare_kernel(PrepParams 
   __shared__ unsigned long long s_meets[kMaxBatch / 64];
   for (int i = threadIdx.x; i < kMaxBatch / 64; i += kPrepThreads) s_meets[i] = 0ull;
   __syncthreads();
-  auto meet = [](const int32_t *a, int na, const int32_t *b, int nb) {
-    for (int i = 0; i < nb; ++i) {
-      const int64_t q = lower_bound(a, (int64_t)na, b[i]);
-      if (q < na && a[q] == b[i]) return true;
+  // one wave per chunk j; lane l looks up entry l of chunk j's lists (at most
+  // 64 each) in chunk j - 1's sorted lists
+  for (int i = threadIdx.x; i < 2 * nseg; i += kPrepThreads) p.seg_stats[i] = s_segc[i];
+  {
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    auto has = [](const int32_t *a, int na, int32_t x) {
+      const int64_t q = lower_bound(a, (int64_t)na, x);
+      return q < na && a[q] == x;
+    };
+    for (int j = 1 + wv; j < s_nchunks; j += kPrepThreads / 64) {
+      const ChunkDesc a = p.chunks[j - 1], b = p.chunks[j];
+      const bool m1 = lane < b.s1 && has(p.chunk_s1 + a.s1_off, a.s1, p.chunk_s1[b.s1_off + lane]);
+      const bool m2 = lane < b.s2 && has(p.chunk_s2 + a.s2_off, a.s2, p.chunk_s2[b.s2_off + lane]);
+      if (__ballot(m1 || m2) != 0ull && lane == 0) atomicOr(&s_meets[j >> 6], 1ull << (j & 63));
     }
-    return false;
-  };
-  for (int j = 1 + threadIdx.x; j < s_nchunks; j += kPrepThreads) {
-    const ChunkDesc a = p.chunks[j - 1], b = p.chunks[j];
-    if (meet(p.chunk_s1 + a.s1_off, a.s1, p.chunk_s1 + b.s1_off, b.s1) ||
-        meet(p.chunk_s2 + a.s2_off, a.s2, p.chunk_s2 + b.s2_off, b.s2))
-      atomicOr(&s_meets[j >> 6], 1ull << (j & 63));
   }
   __syncthreads();
   for (int i = threadIdx.x; i < kMaxBatch / 64; i += kPrepThreads) p.hdr->meets_prev[i] = s_meets[i];
