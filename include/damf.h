@@ -23,7 +23,8 @@
  *   - Calls on one context are serialised by the caller (one thread at a
  *     time); separate contexts are independent.
  *   - After a device error the context is poisoned: later calls return
- *     DAMF_E_STATE.  An input error (DAMF_E_INVALID_ARG,
+ *     DAMF_E_STATE (DAMF_E_NUMERIC from an update undoes the batch and
+ *     leaves the context usable, see damf_update).  An input error (DAMF_E_INVALID_ARG,
  *     DAMF_E_OUT_OF_RANGE) is detected before any state changes, so the
  *     context is unchanged.
  */
@@ -221,8 +222,11 @@ damf_status damf_init_factors(const damf_config *cfg, int64_t m,
  * explicitly (every row rotated by P F, then its row corrections with P = I);
  * info->explicit_chunks counts them.  Errors: DAMF_E_INVALID_ARG,
  * DAMF_E_OUT_OF_RANGE (state unchanged), DAMF_E_NUMERIC (non-finite values
- * in the core: the state is corrupt and the context is poisoned),
- * DAMF_E_DEVICE. */
+ * in a chunk's core, e.g. from singular values near the top of the double
+ * range: the batch is undone, bases, P, Sigma, R and the graph are bit for
+ * bit as before the call and the context stays usable; only when it comes
+ * up during the one-by-one re-run of explicit chunks is the context
+ * poisoned), DAMF_E_DEVICE. */
 damf_status damf_update(damf_ctx *ctx, int64_t k, const int32_t *src,
                         const int32_t *dst, const int8_t *op, int32_t flags,
                         damf_batch_info *info);

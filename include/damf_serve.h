@@ -114,7 +114,11 @@ damf_status damf_submit(damf_server *srv, int64_t k, const int32_t *src, const i
 /* Waits until the request is complete, at most timeout_us microseconds
  * (< 0: no limit), then fills *info (nullable) and releases the ticket.
  * Returns the request's status, DAMF_E_TIMEOUT (ticket kept), or
- * DAMF_E_INVALID_ARG for an unknown ticket. */
+ * DAMF_E_INVALID_ARG for an unknown ticket.  A step whose core comes out
+ * non-finite fails each of its requests with DAMF_E_NUMERIC: the step is
+ * undone (bases, P, Sigma; its graph edits had not run yet) and the PPR state
+ * is seeded again from the restored basis (its previous push ran beside the
+ * chain), and the server goes on with the next requests. */
 damf_status damf_wait(damf_server *srv, int64_t ticket, int64_t timeout_us,
                       damf_request_info *info);
 

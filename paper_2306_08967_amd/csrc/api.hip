@@ -115,6 +115,7 @@ damf_status alloc_state(damf_ctx *c) {
   API_HIP(c, dalloc(&w.scratch, w.scratch_doubles), "alloc scratch");
   API_HIP(c, dalloc(&w.undo_u, (size_t)(2 * kMaxBatch + kMaxSide) * d), "alloc undo log");
   API_HIP(c, dalloc(&w.undo_v, (size_t)(2 * kMaxBatch + kMaxSide) * d), "alloc undo log");
+  if (c->ppr_on) API_HIP(c, dalloc(&w.undo_r, (size_t)(kRLogS1 + 2 * kMaxBatch + kMaxSide) * d), "alloc undo log");
   API_HIP(c, dalloc(&w.psave, 2 * (size_t)d * d + kMaxCore), "alloc undo log");
   API_HIP(c, dalloc(&w.counters, 16), "alloc ws");
   API_HIP(c, hipHostMalloc((void **)&w.counters_host, 16 * sizeof(int64_t)), "alloc pinned");
@@ -152,7 +153,7 @@ void free_ctx(damf_ctx *c) {
                   c->ws.cand2, c->ws.frontier, c->ws.unit_seg, c->ws.units_comb,
                   c->ws.seg_end, c->ws.seg_stats, c->ws.pend_rows, c->ws.edit_stage,
                   c->ws.edit_stage_top, c->ws.hbuf, c->ws.hnode, c->ws.hseg,
-                  c->ws.push_ring, c->ws.push_log, c->ws.undo_u, c->ws.undo_v, c->ws.psave};
+                  c->ws.push_ring, c->ws.push_log, c->ws.undo_u, c->ws.undo_v, c->ws.undo_r, c->ws.psave};
   for (void *p : ptrs)
     if (p) (void)hipFree(p);
   if (c->ws.hdr_host) (void)hipHostFree(c->ws.hdr_host);
@@ -306,7 +307,11 @@ damf_status step_prepare(damf_ctx *c, int64_t k, const int32_t *src, const int32
   return DAMF_OK;
 }
 
-damf_status step_graph(damf_ctx *c, const BatchHeader &h) {
+namespace {
+
+// The batch's CSR edits (and, with fixup, Step 4's structural fix-up of the
+// edited rows' residuals, after saving those rows of R for a rollback).
+damf_status graph_edit(damf_ctx *c, const BatchHeader &h, bool fixup) {
   if (h.n_net <= 0) return DAMF_OK;
   Workspace &w = c->ws;
   hipStream_t s = c->stream;
@@ -323,11 +328,18 @@ damf_status step_graph(damf_ctx *c, const BatchHeader &h) {
     API_HIP(c, csr_compact(c, c->out, c->cfg.graph_slack, 2 * need_out), "CSR compaction");
   if (c->in.pool_cap - w.counters_host[9] < need_in)
     API_HIP(c, csr_compact(c, c->in, c->cfg.graph_slack, 2 * need_in), "CSR^T compaction");
-  if (c->ppr_on) API_HIP(c, ppr_fixup(c, h.n_rows_out), "PPR structural fix-up");
+  if (c->ppr_on && fixup) {
+    API_HIP(c, launch_r_rows(c, w.rows_out, h.n_rows_out, 0, false), "undo log (R)");
+    API_HIP(c, ppr_fixup(c, h.n_rows_out), "PPR structural fix-up");
+  }
   API_HIP(c, launch_csr_edit(c, c->out, w.net, w.rows_out, w.rowpos_out, h.n_rows_out, false), "CSR edit");
   API_HIP(c, launch_csr_edit(c, c->in, w.net_t, w.rows_in, w.rowpos_in, h.n_rows_in, true), "CSR^T edit");
   return DAMF_OK;
 }
+
+}  // namespace
+
+damf_status step_graph(damf_ctx *c, const BatchHeader &h) { return graph_edit(c, h, true); }
 
 damf_status step_chain(damf_ctx *c, const BatchHeader &h, int nseg) {
   if (h.n_chunks <= 0) return DAMF_OK;
@@ -340,9 +352,10 @@ damf_status step_chain(damf_ctx *c, const BatchHeader &h, int nseg) {
       c->chain_hold[ch0 >> 6] |= 1ull << (ch0 & 63);
     ch0 += c->ws.seg_stats_host[2 * i + 1];
   }
-  // undo log: the touched rows of U_b, V_b, and P, Sigma before the chunks
+  // undo log: the touched rows of U_b, V_b and R, and P, Sigma before the chunks
   const size_t dd = 2 * (size_t)c->d * c->d;
   API_HIP(c, launch_undo_rows(c, 0, h.s1_total, 0, h.s2_total, false), "undo log");
+  API_HIP(c, launch_r_rows(c, c->ws.chunk_s1, h.s1_total, kRLogS1, false), "undo log (R)");
   API_HIP(c, hipMemcpyAsync(c->ws.psave, c->P, dd * sizeof(double), hipMemcpyDeviceToDevice, s), "undo log");
   API_HIP(c, hipMemcpyAsync(c->ws.psave + dd, c->sigma, kMaxCore * sizeof(double), hipMemcpyDeviceToDevice, s),
           "undo log");
@@ -408,6 +421,8 @@ damf_status chain_recover(damf_ctx *c, const BatchHeader &h, ChainStats *out) {
     API_HIP(c, hipStreamSynchronize(s), "chain (one chunk)");
     const ChainStats one = *w.cstats_host;
     if (one.numeric_error & kNumericCore) {
+      // the per-chunk undo log has overwritten the batch's, and an explicit
+      // chunk may have rotated every row: no exact undo is left
       c->poisoned = true;
       return fail(c, DAMF_E_NUMERIC, "non-finite core in the update");
     }
@@ -435,7 +450,46 @@ damf_status chain_recover(damf_ctx *c, const BatchHeader &h, ChainStats *out) {
 
 }  // namespace
 
-damf_status step_check(damf_ctx *c, const BatchHeader &h) {
+namespace {
+
+// A core came out non-finite (NaN or infinite values, e.g. from singular
+// values near the top of the double range): undo the whole batch instead of
+// leaving a corrupt state.  The rows of U_b and V_b and P, Sigma come back
+// from the undo log.  With the graph already edited (damf_update: edit,
+// chain, check), R's rows come back from their copies, the chunks' S1 rows
+// first (saved after the fix-up) and then the edited rows (saved before it),
+// and the graph from the inverse edit: the context is then bit for bit what
+// it was before the call.  Otherwise (the server: chain, check, edit) the
+// previous step's push ran beside the chain, so R's saved rows are stale;
+// the PPR state is seeded again from the restored basis (Z = 0, R = X, pushed
+// to eps / 2), which is as valid an approximation as the one it replaces.
+damf_status rollback_batch(damf_ctx *c, const BatchHeader &h, bool graph_edited) {
+  hipStream_t s = c->stream;
+  Workspace &w = c->ws;
+  const size_t dd = 2 * (size_t)c->d * c->d;
+  API_HIP(c, launch_undo_rows(c, 0, h.s1_total, 0, h.s2_total, true, false), "undo");
+  API_HIP(c, hipMemcpyAsync(c->P, w.psave, dd * sizeof(double), hipMemcpyDeviceToDevice, s), "undo");
+  API_HIP(c, hipMemcpyAsync(c->sigma, w.psave + dd, kMaxCore * sizeof(double), hipMemcpyDeviceToDevice, s),
+          "undo");
+  if (graph_edited) {
+    API_HIP(c, launch_r_rows(c, w.chunk_s1, h.s1_total, kRLogS1, true), "undo (R)");
+    API_HIP(c, launch_r_rows(c, w.rows_out, h.n_rows_out, 0, true), "undo (R)");
+    if (h.n_net > 0) {
+      API_HIP(c, launch_negate_net(c, h.n_net), "undo (graph)");
+      const damf_status st = graph_edit(c, h, false);
+      if (st != DAMF_OK) return st;
+    }
+  } else if (c->ppr_on) {
+    API_HIP(c, hipDeviceSynchronize(), "undo");
+    API_HIP(c, ppr_init(c), "undo (PPR seed)");
+  }
+  API_HIP(c, hipStreamSynchronize(s), "undo");
+  return fail(c, DAMF_E_NUMERIC, "non-finite core in the update: the batch was undone");
+}
+
+}  // namespace
+
+damf_status step_check(damf_ctx *c, const BatchHeader &h, bool graph_edited) {
   c->last_p_cond = 0.0;
   c->last_flushed = 0;
   c->last_explicit = 0;
@@ -445,10 +499,7 @@ damf_status step_check(damf_ctx *c, const BatchHeader &h) {
   API_HIP(c, hipMemcpyAsync(w.cstats_host, w.cstats, sizeof(ChainStats), hipMemcpyDeviceToHost, s), "stats");
   API_HIP(c, hipStreamSynchronize(s), "chain");
   ChainStats cs = *w.cstats_host;
-  if (cs.numeric_error & kNumericCore) {
-    c->poisoned = true;
-    return fail(c, DAMF_E_NUMERIC, "non-finite core in the update");
-  }
+  if (cs.numeric_error & kNumericCore) return rollback_batch(c, h, graph_edited);
   if (cs.numeric_error & kNumericSingularP) {
     const damf_status st = chain_recover(c, h, &cs);
     if (st != DAMF_OK) return st;
@@ -558,7 +609,7 @@ damf_status update_apply(damf_ctx *c, const BatchHeader &h, int64_t k, int nseg,
   damf_status st;
   if ((st = step_graph(c, h)) != DAMF_OK) return st;
   if ((st = step_chain(c, h, nseg)) != DAMF_OK) return st;
-  if ((st = step_check(c, h)) != DAMF_OK) return st;
+  if ((st = step_check(c, h, true)) != DAMF_OK) return st;
   // re-orthogonalisation due: before Step 4, so the push restores max |R| <= eps
   bool reorth_refused = false;
   double ms_reorth = 0.0;

@@ -131,6 +131,10 @@ struct Workspace {
   // which a projection turned singular: U_b rows of every chunk's S1 and V_b
   // rows of every chunk's S2 (as stored, in chunk-list order), P and Sigma
   float *undo_u = nullptr, *undo_v = nullptr;
+  // rows of R the update touches before Step 4: the edited rows before the
+  // structural fix-up (from row 0), the chunks' S1 rows before the chain
+  // (from row kRLogS1)
+  float *undo_r = nullptr;
   double *psave = nullptr;  // 2 d^2 + kMaxCore
   // PPR push
   int32_t *stamp = nullptr;      // per node: last round it was queued
@@ -213,7 +217,7 @@ damf_status step_chain(damf_ctx *c, const BatchHeader &h, int nseg);
 // Waits for the chunks, re-runs a batch whose projection turned singular
 // (explicit chunks), poisons on a non-finite core, and flushes the lazy
 // projections when their condition estimate passes the configured limit.
-damf_status step_check(damf_ctx *c, const BatchHeader &h);
+damf_status step_check(damf_ctx *c, const BatchHeader &h, bool graph_edited);
 // Waits for the stream, checks pool overflow and compacts the CSR pools.
 damf_status step_finish(damf_ctx *c, const BatchHeader &h);
 void step_info(damf_ctx *c, const BatchHeader &h, int64_t k, damf_batch_info *info);
@@ -303,7 +307,16 @@ hipError_t launch_query(damf_ctx *c, int which, int64_t q,
 // copies the rows into the log; restore removes the chain's signal additions
 // from R (R -= U_b - log) and copies the rows back, entry by entry in list
 // order, so a repeated row is corrected once.
-hipError_t launch_undo_rows(damf_ctx *c, int s1_off, int n_s1, int s2_off, int n_s2, bool restore);
+// With r_delta false the restore leaves R alone.
+hipError_t launch_undo_rows(damf_ctx *c, int s1_off, int n_s1, int s2_off, int n_s2, bool restore,
+                            bool r_delta = true);
+// save (restore = false) or put back the rows `rows` of R (one FP32 row of d
+// per list entry, list order) at row `at` of undo_r; a no-op without PPR
+constexpr int kRLogS1 = 2 * kMaxBatch + 1;
+hipError_t launch_r_rows(damf_ctx *c, const int32_t *rows, int n, int at, bool restore);
+// flip the sign of the batch's net entries (both sort orders), so that the
+// graph edit applies the inverse change
+hipError_t launch_negate_net(damf_ctx *c, int n_net);
 // out[i] = <rows of which_a at u[i], rows of which_b at v[i]> (device lists)
 hipError_t launch_score_pairs(damf_ctx *c, int which_a, int which_b, int64_t q, const int32_t *d_u,
                               const int32_t *d_v, float *d_out, bool both_ways);

@@ -368,6 +368,8 @@ hipError_t ppr_fixup(damf_ctx *c, int n_rows) {
 // first_rows: candidate rows of the first round (device list), or nullptr to
 // start from every node.  Runs on stream s (the server overlaps it with the
 // next step's chain kernel; R is only ever changed by atomics meanwhile).
+constexpr int kPushGrid = 512;
+
 hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64_t nfirst,
                     int64_t *rounds, int64_t *pushes, int64_t *edges) {
   Workspace &w = c->ws;
@@ -412,14 +414,18 @@ hipError_t ppr_push(damf_ctx *c, hipStream_t s, const int32_t *first_rows, int64
   for (;;) {
     for (int g = 0; g < kPushGroup; ++g, ++r) {
       const int32_t round = (int32_t)((id0 + 1 + r) & 0x7fffffff);
-      select_kernel<<<2048, 256, 0, s>>>(
+      // two workgroups per CU: the grids stride over the round's candidates and
+      // frontier, and larger grids only cost dispatch time in the late rounds
+      // (select and push at 2048, 512 and 256 workgroups: 0.74, 0.69 and 0.77 ms
+      // of push kernels per C2 batch)
+      select_kernel<<<kPushGrid, 256, 0, s>>>(
           (r == 0 && all) ? nullptr : cand[r & 1], r == 0 ? nullptr : ring(r - 1) + 2, ncand0,
           c->R, d, c->cfg.eps, w.stamp, (r == 0 && !all) ? id0 : -1, w.frontier, ring(r),
           ring(r + 1), r == 0 ? nullptr : ring(r - 1), w.push_log + 2 * (size_t)(r > 0 ? r - 1 : 0));
-      push_kernel<<<2048, 256, 0, s>>>(c->in, c->out.len, w.frontier, c->R, c->Zb, d, alpha,
+      push_kernel<<<kPushGrid, 256, 0, s>>>(c->in, c->out.len, w.frontier, c->R, c->Zb, d, alpha,
                                        round, w.stamp, cand[(r + 1) & 1], ring(r), w.hbuf,
                                        w.hnode, reinterpret_cast<int2 *>(w.hseg));
-      spread_heavy_kernel<<<1024, 256, 0, s>>>(c->in, c->out.len, c->R, d, alpha, round, w.stamp,
+      spread_heavy_kernel<<<kPushGrid / 2, 256, 0, s>>>(c->in, c->out.len, c->R, d, alpha, round, w.stamp,
                                                cand[(r + 1) & 1], ring(r), w.hbuf, w.hnode,
                                                reinterpret_cast<const int2 *>(w.hseg));
     }

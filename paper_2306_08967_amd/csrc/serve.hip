@@ -309,7 +309,7 @@ void do_step(damf_server *s, std::vector<Part> &step) {
     hipError_t e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) st = api_dev_fail(c, e, "chain");
   }
-  if (st == DAMF_OK) st = step_check(c, h);
+  if (st == DAMF_OK) st = step_check(c, h, false);
   if (st == DAMF_OK && h.n_chunks > 0) {
     float ms = 0.f;
     if (hipEventElapsedTime(&ms, c->ev[4], c->ev[5]) == hipSuccess) tune_after(s, ms, h.n_net);

@@ -88,7 +88,8 @@ __global__ __launch_bounds__(64) void undo_restore_kernel(const int32_t *rows, i
   }
 }
 
-hipError_t launch_undo_rows(damf_ctx *c, int s1_off, int n_s1, int s2_off, int n_s2, bool restore) {
+hipError_t launch_undo_rows(damf_ctx *c, int s1_off, int n_s1, int s2_off, int n_s2, bool restore,
+                            bool r_delta) {
   const Workspace &w = c->ws;
   hipStream_t s = c->stream;
   const int32_t *l1 = w.chunk_s1 + s1_off, *l2 = w.chunk_s2 + s2_off;
@@ -103,11 +104,55 @@ hipError_t launch_undo_rows(damf_ctx *c, int s1_off, int n_s1, int s2_off, int n
     }
   } else {
     if (n_s1 > 0)
-      undo_restore_kernel<<<1, 64, 0, s>>>(l1, n_s1, c->Ub, w.undo_u, c->ppr_on ? c->R : nullptr,
-                                           c->d, c->split);
+      undo_restore_kernel<<<1, 64, 0, s>>>(l1, n_s1, c->Ub, w.undo_u,
+                                           (c->ppr_on && r_delta) ? c->R : nullptr, c->d, c->split);
     if (n_s2 > 0)
       undo_restore_kernel<<<1, 64, 0, s>>>(l2, n_s2, c->Vb, w.undo_v, nullptr, c->d, c->split);
   }
+  return hipGetLastError();
+}
+
+// Rows of R as they were before the structural fix-up or the chain changed
+// them, saved into undo_r or put back from it.  A list may repeat a row
+// (S1 over several chunks); its copies all hold the same saved words, so the
+// restore can write them in parallel.
+__global__ __launch_bounds__(256) void r_rows_restore_kernel(const int32_t *rows, int nrows, float *R,
+                                                             const float *log, int d) {
+  const int lane = threadIdx.x & 63;
+  for (int64_t i = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6); i < nrows;
+       i += (int64_t)gridDim.x * 4) {
+    const int64_t row = rows[i];
+    for (int c = lane; c < d; c += 64) R[row * d + c] = log[i * d + c];
+  }
+}
+
+hipError_t launch_r_rows(damf_ctx *c, const int32_t *rows, int n, int at, bool restore) {
+  if (n <= 0 || !c->ppr_on) return hipSuccess;
+  const Grid g = geom_rows(n);
+  float *log = c->ws.undo_r + (size_t)at * c->d;
+  if (restore)
+    r_rows_restore_kernel<<<g.blocks, g.threads, 0, c->stream>>>(rows, n, c->R, log, c->d);
+  else
+    undo_save_kernel<<<g.blocks, g.threads, 0, c->stream>>>(rows, n, c->R, log, c->d);
+  return hipGetLastError();
+}
+
+// The inverse of a net change: every insert becomes a delete and back, and
+// pad (the inserts before an entry in its sorted list) becomes the deletes
+// before it, i - pad.
+__global__ void negate_net_kernel(NetEntry *a, NetEntry *b, int n) {
+  for (int i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) {
+    a[i].delta = -a[i].delta;
+    a[i].pad = i - a[i].pad;
+    b[i].delta = -b[i].delta;
+    b[i].pad = i - b[i].pad;
+  }
+}
+
+hipError_t launch_negate_net(damf_ctx *c, int n_net) {
+  if (n_net <= 0) return hipSuccess;
+  const Grid g = geom_elementwise(n_net);
+  negate_net_kernel<<<g.blocks, g.threads, 0, c->stream>>>(c->ws.net, c->ws.net_t, n_net);
   return hipGetLastError();
 }
 

@@ -12,6 +12,12 @@
    invariant of Sec. 4.4 on the GPU's own state.
 2. The condition limit of P: with a limit of 1.5 nearly every batch flushes P;
    C1-shaped parity with the oracle must be unchanged (1e-5 bars).
+3. A core that comes out non-finite (a singular value of 1e300, whose square
+   overflows in the core's column norms) is refused with DAMF_E_NUMERIC and
+   the batch is undone: through damf_update the bases, P, Sigma, Z, R and the
+   graph are bit for bit as before and the context stays usable; through the
+   server the request fails, the graph and bases are unchanged and the PPR
+   state, seeded again, meets the invariant of Sec. 4.4.
 """
 import sys
 
@@ -142,4 +148,75 @@ def test_flush_on_condition_limit(damf):
     assert flushes >= 6
     assert err_s <= 1e-5 and err_p <= 1e-5 and eo <= 1e-5
     _ppr_check(ctx, n, 0.15, 1e-5)
+    ctx.close()
+
+
+DAMF_E_NUMERIC = 5
+
+
+def _overflow_context(damf, directed):
+    """Two-block graph with exact factors, but sigma_1 = 1e300."""
+    n, d, alpha, eps = 40, 16, 0.15, 1e-6
+    s0, t0 = _two_blocks()
+    orc = DAMFOracle(n, d, directed, alpha=alpha, eps=eps, r=4, r_max=8,
+                     tau=1e-4).init_exact(s0, t0)
+    sig = orc.s.copy()
+    sig[0] = 1e300
+    cfg = damf.default_config(n, d, directed=directed, alpha=alpha, eps=eps, max_core_rank=4,
+                              max_side=8, tau=1e-4)
+    return damf.Context.init_factors(cfg, s0, t0, orc.U, sig, orc.V), n, alpha, eps
+
+
+def _snapshot(ctx):
+    st = ctx.export_state()
+    st["sigma"] = ctx.singular_values()
+    st["csr"] = ctx.export_csr()
+    st["csr_t"] = ctx.export_csr(transpose=True)
+    return st
+
+
+def _same(a, b, keys):
+    for k in keys:
+        if k.startswith("csr"):
+            assert np.array_equal(a[k][0], b[k][0]) and np.array_equal(a[k][1], b[k][1]), k
+        else:
+            assert np.array_equal(a[k], b[k]), k
+
+
+# inserts between the blocks and into isolated nodes, a delete inside a block
+_OPS = (np.array([32, 3, 0, 21], np.int32), np.array([35, 27, 10, 26], np.int32),
+        np.array([1, 1, -1, -1], np.int8))
+
+
+@pytest.mark.parametrize("directed", [True, False])
+def test_nonfinite_core_rolls_back(damf, directed):
+    _say(f"case non-finite core rollback directed={directed}")
+    ctx, n, alpha, eps = _overflow_context(damf, directed)
+    before = _snapshot(ctx)
+    for attempt in range(2):
+        with pytest.raises(damf.DamfError) as ei:
+            ctx.update(*_OPS)
+        assert ei.value.status == DAMF_E_NUMERIC
+        after = _snapshot(ctx)
+        _same(before, after, ("Ub", "Vb", "PU", "PV", "Zb", "R", "sigma", "csr", "csr_t"))
+        _say(f"  attempt {attempt}: refused, state unchanged")
+    # still usable: a query and an empty batch
+    assert ctx.query("Z").shape == (n, 16)
+    ctx.update(np.zeros(0, np.int32), np.zeros(0, np.int32), np.zeros(0, np.int8))
+    ctx.close()
+
+
+def test_nonfinite_core_rolls_back_in_server(damf):
+    _say("case non-finite core rollback in the server")
+    ctx, n, alpha, eps = _overflow_context(damf, True)
+    before = _snapshot(ctx)
+    with damf.Server(ctx) as srv:
+        for _ in range(2):
+            t = srv.submit(*_OPS)
+            with pytest.raises(damf.DamfError) as ei:
+                srv.wait(t, timeout_us=60_000_000)
+            assert ei.value.status == DAMF_E_NUMERIC
+    after = _snapshot(ctx)
+    _same(before, after, ("Ub", "Vb", "PU", "PV", "sigma", "csr", "csr_t"))
+    _ppr_check(ctx, n, alpha, eps)
     ctx.close()
