@@ -55,8 +55,7 @@ constexpr double kMinExplicitCond = 1e3;
 constexpr double kJacobiTolSplit = 1e-8;
 
 // global scratch layout (doubles)
-constexpr size_t OFF_KG = 0;                              // K, col-major, stride NPMAX
-constexpr size_t OFF_EG = OFF_KG + NPMAX * NPMAX;         // E, col-major, stride NPMAX
+constexpr size_t OFF_EG = 0;                              // E, col-major, stride NPMAX
 constexpr size_t OFF_HG = OFF_EG + NPMAX * DMAX;          // H, row-major [j][c], stride DMAX
 constexpr size_t OFF_UP = OFF_HG + NPMAX * DMAX;          // U rows of S1, [i][c]
 constexpr size_t OFF_VP = OFF_UP + KMAX * DMAX;
@@ -429,7 +428,7 @@ __device__ __noinline__ int core_svd(const ChunkState &cs, int d, const double *
   const int NB = d + cs.rhoB, NC = d + cs.rhoC;
   const double *WBt = scr + OFF_WB, *WCt = scr + OFF_WC;
   const double *RB = scr + OFF_RB, *RC = scr + OFF_RC;
-  double *KG = scr + OFF_KG, *EG = scr + OFF_EG, *HG = scr + OFF_HG, *TH = scr + OFF_TH;
+  double *EG = scr + OFF_EG, *HG = scr + OFF_HG, *TH = scr + OFF_TH;
   // K = diag(Sigma, 0) + L_m R_m^T with L_m = [W_B; R_B], R_m = [W_C; R_C]
   // (NP x k each); wave w holds columns jw_col(w, c), lane l rows l + 64 r.
   // Both factors are staged in LDS as [t][i] in chunks of KC values of t;
@@ -480,7 +479,6 @@ __device__ __noinline__ int core_svd(const ChunkState &cs, int d, const double *
       const int i = r * 64 + lane;
       if (i >= NB || j >= NC) J.a[c][r] = 0.0;
       if (i == j && i < d) J.a[c][r] += sigma[i];
-      KG[j * NPMAX + i] = J.a[c][r];
     }
   }
   __syncthreads();

@@ -53,7 +53,7 @@ struct JW {
   // leftover slot (rows 0 and 2)
   static constexpr int H = B / 2;
   static constexpr int QF = H / 2, QL = H % 2, QS = QF + QL;
-  static constexpr int XU = (B % 4 == 0) ? 4 : 2;  // cross steps per loop iteration
+  static constexpr int XU = B;  // cross steps per loop iteration: all of a round
   static constexpr int SLOT = B * NP;      // doubles per half-block in the exchange buffer
   static constexpr int NS_OFF = NW * SLOT;      // per column id: (norm^2, scale) pairs
   static constexpr int BC_OFF = NS_OFF + 2 * NP;  // per wave: B rotation factor pairs
@@ -211,7 +211,10 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
   // the plane lane of slot q of row R computes the rotation of pair jw_pair(R, q)
   const double myg = jw_reduce<S>(v);
   const bool plane = jw_plane<S>(lane);
-  const int pair = plane ? jw_pair<S>(row, jw_slot(lane)) : 0;
+  int pair = plane ? jw_pair<S>(row, jw_slot(lane)) : 0;
+  // an opaque copy per step: the pair's column ids are then formed here
+  // (a few integer ops) instead of being kept live across the unrolled round
+  asm volatile("" : "+v"(pair));
   int it, ib;
   ids(pair, it, ib);
   const double2 nsi = ns[it], nsj = ns[ib];
@@ -391,7 +394,7 @@ __device__ __forceinline__ void jw_cross_steps(JWRegs<S> &J, double2 *ns, double
 // are back in their sweep-boundary slots (jw_col) and the squared norms are
 // in lds[S::NS_OFF + 2 id] (jw_norm2).
 template <class S>
-__device__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweeps, double tol) {
+__device__ __forceinline__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweeps, double tol) {
   int skip = 0;  // this wave's steps without a rotation
   constexpr int B = S::B, RPL = S::RPL, XU = S::XU;
   const int lane = threadIdx.x & 63;
