@@ -34,7 +34,7 @@ namespace {
 constexpr int NPMAX = 192;   // max padded core size
 constexpr int DMAX = 128;
 constexpr int KMAX = 64;
-constexpr int LDS_DOUBLES = 19200;  // 150 KB
+constexpr int LDS_DOUBLES = 19456;  // 152 KB (with 4 KB of ints, under the CU's 160 KB)
 // Core-SVD Jacobi tolerance: a pair is rotated while |a_i . a_j| exceeds it
 // relative to ||a_i|| ||a_j||, and sweeps stop once every rotation of a sweep
 // was below its square root, leaving the columns orthogonal to about 1e-9 --

@@ -20,8 +20,9 @@
 // DPP, the pair's rotation is computed by the lane that ends up with its dot
 // product, and read back by every lane from LDS.  Half-blocks move between
 // waves through LDS only between rounds (4 workgroup barriers per round).
-// Squared column norms (with the column scales below, as pairs) live in LDS by
-// column id; a wave touches only those of the columns it holds.
+// Squared column norms (with the column scales below, as pairs, and the
+// scales' reciprocals) live in LDS by column id; a wave touches only those of
+// the columns it holds.
 //
 // Rotations are applied in scaled form: column i is held as x_i with a scale
 // d_i (a_i = d_i x_i, scales in LDS by id).  The rotation (c, s = c t) of the
@@ -55,17 +56,22 @@ struct JW {
   static constexpr int QF = H / 2, QL = H % 2, QS = QF + QL;
   static constexpr int XU = B;  // cross steps per loop iteration: all of a round
   static constexpr int SLOT = B * NP;      // doubles per half-block in the exchange buffer
-  static constexpr int NS_OFF = NW * SLOT;      // per column id: (norm^2, scale) pairs
-  static constexpr int BC_OFF = NS_OFF + 2 * NP;  // per wave: B rotation factor pairs
+  static constexpr int NS_OFF = NW * SLOT;      // per column id: JNs
+  static constexpr int BC_OFF = NS_OFF + 4 * NP;  // per wave: B rotation factor pairs
   static constexpr int LDS = BC_OFF + NW * 2 * B;  // exchange, norms, scales, factors
   static_assert(NP % 64 == 0 && NP <= 192 && B % 2 == 0 && B * 2 * NW == NP,
                 "NP must be 64, 128 or 192 and split into 2 NW half-blocks of even width");
 };
 
+// Per column id: the squared norm of a_i = d_i x_i, the scale d_i and 1 / d_i.
+struct __align__(16) JNs {
+  double n2, d, rd, pad;
+};
+
 // squared norm of column id after jw_sweeps
 template <class S>
 __device__ __forceinline__ double jw_norm2(const double *lds, int id) {
-  return lds[S::NS_OFF + 2 * id];
+  return lds[S::NS_OFF + 4 * id];
 }
 
 template <class S>
@@ -138,15 +144,17 @@ __device__ __forceinline__ double jw_reduce(const double (&v)[S::B]) {
   for (int i = 0; i < 4; ++i) q[i] = (i < QF) ? xsum16(h[i], h[i + QF]) : 0.0;
   const int lane = threadIdx.x & 63;
   const bool b3 = (lane & 8) != 0, b2 = (lane & 4) != 0;
-  // slots 0, 1 stay in the lanes without bit 3, slots 2, 3 in the others
-  const double s0 = b3 ? q[0] : q[2], s1 = b3 ? q[1] : q[3];
-  double k0 = b3 ? q[2] : q[0], k1 = b3 ? q[3] : q[1];
+  // slots 0, 1 stay in the lanes without bit 3, slots 2, 3 in the others; a
+  // slot at or past QF holds nothing, so what its lanes keep or send is free
+  // (no select)
+  const double s0 = (QF > 2 && !b3) ? q[2] : q[0], s1 = (QF > 3 && !b3) ? q[3] : q[1];
+  double k0 = (QF > 2 && b3) ? q[2] : q[0], k1 = (QF > 3 && b3) ? q[3] : q[1];
   k0 += dpp_d<0x128>(s0);  // row_ror:8, lane l ^ 8
   k1 += dpp_d<0x128>(s1);
   // the even slot stays in the lanes without bit 2 (row_half_mirror pairs
   // lane l with 7 - l, which has bit 2 flipped)
-  const double sb = b2 ? k0 : k1;
-  double kb = b2 ? k1 : k0;
+  const double sb = (QF > 1 && !b2) ? k1 : k0;
+  double kb = (QF > 1 && b2) ? k1 : k0;
   kb += dpp_d<0x141>(sb);
   kb += dpp_d<0xB1>(kb);  // quad_perm [1,0,3,2]
   kb += dpp_d<0x4E>(kb);  // quad_perm [2,3,0,1]
@@ -156,7 +164,7 @@ __device__ __forceinline__ double jw_reduce(const double (&v)[S::B]) {
 // Exact squared norms of the wave's 2B columns into ns[].x by column id (the
 // wave holds its sweep-boundary half-blocks w and NW + w).
 template <class S>
-__device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double2 *ns, int w) {
+__device__ __forceinline__ void jw_norms(const JWRegs<S> &J, JNs *ns, int w) {
   constexpr int B = S::B, RPL = S::RPL;
   const int lane = threadIdx.x & 63, row = lane >> 4;
 #pragma unroll
@@ -170,7 +178,7 @@ __device__ __forceinline__ void jw_norms(const JWRegs<S> &J, double2 *ns, int w)
       v[p] = s;
     }
     const double mine = jw_reduce<S>(v);
-    if (jw_plane<S>(lane)) ns[jw_col<S>(w, half * B + jw_pair<S>(row, jw_slot(lane)))].x = mine;
+    if (jw_plane<S>(lane)) ns[jw_col<S>(w, half * B + jw_pair<S>(row, jw_slot(lane)))].n2 = mine;
   }
 }
 
@@ -195,7 +203,7 @@ struct JWIntra {
 // writes it there and every lane reads all B back (broadcast reads; LDS
 // operations of one wave complete in order).
 template <class S, class PM, class IdF>
-__device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
+__device__ __forceinline__ void jw_step(JWRegs<S> &J, JNs *ns, double2 *bc,
                                         double floor2, double tol2, double conv2, IdF ids, int &rot,
                                         int &big, int &skip) {
   constexpr int B = S::B, RPL = S::RPL;
@@ -217,9 +225,9 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
   asm volatile("" : "+v"(pair));
   int it, ib;
   ids(pair, it, ib);
-  const double2 nsi = ns[it], nsj = ns[ib];
-  const double al = nsi.x, be = nsj.x;
-  const double di = nsi.y, dj = nsj.y;
+  const double al = ns[it].n2, be = ns[ib].n2;
+  const double di = ns[it].d, dj = ns[ib].d;
+  const double rdi = ns[it].rd, rdj = ns[ib].rd;
   const double gt = myg * (di * dj);  // a_i . a_j
   const bool live = plane && al > floor2 && be > floor2;
   const double g2 = gt * gt, ab = al * be;
@@ -237,13 +245,18 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, double2 *ns, double2 *bc,
   const double t = doit ? (dd >= 0.0 ? gg : -gg) * rcp_nr1(den) : 0.0;
   const double q1 = fma(t, t, 1.0);
   const double cs = rsqrt_nr(q1);
-  const double inv = rcp_nr(di * dj);
   // two in-place shears: x_j += t (d_i / d_j) x_i, then x_i -= c^2 t (d_j / d_i) x_j
-  // (the new x_j), with d_j <- c d_j and d_i <- d_i / c
-  const double t2 = t * (di * di) * inv, t1 = (cs * cs) * t * (dj * dj) * inv;
+  // (the new x_j), with d_j <- c d_j and d_i <- d_i / c (1 / c = (1 + t^2) c);
+  // the scales' reciprocals are carried along, so no division is needed
+  const double t2 = t * (di * rdj), t1 = ((cs * cs) * t) * (dj * rdi);
   if (doit) {
-    ns[it] = make_double2(fma(-t, gt, al), di * (q1 * cs));  // d_i / c = d_i (1 + t^2) c
-    ns[ib] = make_double2(fma(t, gt, be), cs * dj);
+    const double ic = q1 * cs;
+    ns[it].n2 = fma(-t, gt, al);
+    ns[it].d = di * ic;
+    ns[it].rd = rdi * cs;
+    ns[ib].n2 = fma(t, gt, be);
+    ns[ib].d = cs * dj;
+    ns[ib].rd = rdj * ic;
   }
   rot += doit ? 1 : 0;
   // a step in which no pair rotates would only add zeros (t = 0): skip its
@@ -369,7 +382,7 @@ __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int
 
 // Steps sh .. sh + U - 1 of a cross round, the bottom offset by 0 .. U - 1 slots.
 template <class S, int U, int... SH>
-__device__ __forceinline__ void jw_cross_steps(JWRegs<S> &J, double2 *ns, double2 *bc, double floor2,
+__device__ __forceinline__ void jw_cross_steps(JWRegs<S> &J, JNs *ns, double2 *bc, double floor2,
                                                double tol2, double conv2, int ht, int hb, int sh,
                                                int &rot, int &big, int &skip,
                                                std::integer_sequence<int, SH...>) {
@@ -392,7 +405,7 @@ __device__ __forceinline__ void jw_cross_steps(JWRegs<S> &J, double2 *ns, double
 // neither column is numerically zero (norm^2 below 1e-30 of the largest).
 // Every thread of the 64 NW-thread workgroup calls it; on return the columns
 // are back in their sweep-boundary slots (jw_col) and the squared norms are
-// in lds[S::NS_OFF + 2 id] (jw_norm2).
+// in lds[S::NS_OFF + 4 id] (jw_norm2).
 template <class S>
 __device__ __forceinline__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_flag, int max_sweeps, double tol) {
   int skip = 0;  // this wave's steps without a rotation
@@ -400,9 +413,9 @@ __device__ __forceinline__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_fla
   const int lane = threadIdx.x & 63;
   const int w = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   double *xb = lds;
-  double2 *ns = reinterpret_cast<double2 *>(lds + S::NS_OFF);
+  JNs *ns = reinterpret_cast<JNs *>(lds + S::NS_OFF);
   double2 *bc = reinterpret_cast<double2 *>(lds + S::BC_OFF) + w * B;
-  for (int j = threadIdx.x; j < S::NP; j += blockDim.x) ns[j].y = 1.0;
+  for (int j = threadIdx.x; j < S::NP; j += blockDim.x) ns[j].d = ns[j].rd = 1.0;
   jw_norms<S>(J, ns, w);
   __syncthreads();
   const double tol2 = tol * tol, conv2 = tol;  // (sqrt(tol))^2
@@ -411,7 +424,7 @@ __device__ __forceinline__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_fla
     int rot = 0, big = 0;
     double mx = 0.0;
 #pragma unroll
-    for (int r = 0; r < RPL; ++r) mx = fmax(mx, ns[r * 64 + lane].x);
+    for (int r = 0; r < RPL; ++r) mx = fmax(mx, ns[r * 64 + lane].n2);
     const double floor2 = 1e-30 * wave_max_d(mx);
     for (int round = 0; round < 2 * S::NW - 1; ++round) {
       const int ht = j16_top_id<2 * S::NW>(w, round), hb = j16_bot_id<2 * S::NW>(w, round);
@@ -445,12 +458,12 @@ __device__ __forceinline__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_fla
     // and another sweep would find nothing.
 #pragma unroll
     for (int c = 0; c < S::C; ++c) {
-      const double dc = ns[jw_col<S>(w, c)].y;
+      const double dc = ns[jw_col<S>(w, c)].d;
 #pragma unroll
       for (int r = 0; r < RPL; ++r) J.a[c][r] *= dc;
     }
     __syncthreads();
-    for (int j = threadIdx.x; j < S::NP; j += blockDim.x) ns[j].y = 1.0;
+    for (int j = threadIdx.x; j < S::NP; j += blockDim.x) ns[j].d = ns[j].rd = 1.0;
     jw_norms<S>(J, ns, w);
     if (threadIdx.x == 0) {
       lds_flag[0] = 0;
