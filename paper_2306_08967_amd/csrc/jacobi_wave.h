@@ -266,10 +266,22 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, JNs *ns, double2 *bc,
   if (none) return;
   if (plane) bc[pair] = make_double2(t1, t2);
   __builtin_amdgcn_wave_barrier();
+  // the factor pairs are requested in two halves, each in one LDS round trip
+  // (the compiler otherwise reuses a few registers and waits once per pair of
+  // pairs; all B at once would spill), then consumed in order
+  constexpr int BH = B / 2;
+  double2 u[B];
+#pragma unroll
+  for (int p = 0; p < BH; ++p) u[p] = bc[p];
+  __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
   for (int p = 0; p < B; ++p) {
-    const double2 u = bc[p];
-    const double u1 = u.x, u2 = u.y;
+    if (p == BH) {
+#pragma unroll
+      for (int q = BH; q < B; ++q) u[q] = bc[q];
+      __builtin_amdgcn_sched_barrier(0);
+    }
+    const double u1 = u[p].x, u2 = u[p].y;
 #pragma unroll
     for (int r = 0; r < RPL; ++r) {
       J.a[PM::b(p)][r] = fma(u2, J.a[PM::a(p)][r], J.a[PM::b(p)][r]);
