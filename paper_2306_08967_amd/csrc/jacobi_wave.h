@@ -367,6 +367,11 @@ __device__ __forceinline__ void jw_get(JWRegs<S> &J, const double *xb, int slot,
 // Move the half-blocks to the next round of the circle over waves:
 // new top[w] = old top[w-1] (w >= 2), new top[1] = old bottom[0], top[0] stays;
 // new bottom[w] = old bottom[w+1] (w < NW-1), new bottom[NW-1] = old top[NW-1].
+// Bottoms go through slot w - 1 (wave 0's through slot L), tops of waves
+// 1 .. L-1 through slot w.  Two barriers suffice: a slot is next written by
+// the wave that last read it, except slot 0 (read by wave 0, written by wave
+// 1) and slot L (read by wave 1, written by wave 0), whose reads both come
+// before the second barrier.
 template <class S>
 __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int lane) {
   constexpr int B = S::B, RPL = S::RPL;
@@ -382,14 +387,10 @@ __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int
       for (int r = 0; r < RPL; ++r) J.a[B + j][r] = J.a[j][r];
     }
   }
-  __syncthreads();
   if (w >= 1 && w < L) jw_put<S>(J, xb, w, 0, lane);  // tops of waves 1..NW-2, by source wave
+  if (w == 1) jw_get<S>(J, xb, L, 0, lane);
   __syncthreads();
-  if (w == 1)
-    jw_get<S>(J, xb, L, 0, lane);
-  else if (w >= 2)
-    jw_get<S>(J, xb, w - 1, 0, lane);
-  __syncthreads();
+  if (w >= 2) jw_get<S>(J, xb, w - 1, 0, lane);
 }
 
 // Issue priority through a round: the two waves that share a SIMD run the
