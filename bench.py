@@ -113,7 +113,7 @@ def parse():
                     help="insertions per batch of the billion-edge form (1: single-edge updates)")
     ap.add_argument("--serve-n", type=int, default=10_000_000)
     ap.add_argument("--serve-m", type=int, default=200_000_000)
-    ap.add_argument("--serve-requests", type=int, default=6000)
+    ap.add_argument("--serve-requests", type=int, default=12000)
     ap.add_argument("--serve-sat", type=int, default=400)
     ap.add_argument("--serve-seconds", type=float, default=12.0)
     ap.add_argument("--graph-chunks", type=int, default=8,
@@ -432,9 +432,17 @@ def serve_main(args):
     sat = serve_phase(P, ctx, take(args.serve_sat), 0.0, 2)
     log(f"saturation: {sat['ops_per_s']:.0f} ops/s, {sat['mean_requests_per_step']:.1f} req/step")
     phases = []
-    for i, frac in enumerate((0.5, 0.8, 0.95)):
+    # each phase offers its rate for serve_seconds; should the request pool not
+    # hold that many, every phase is shortened by the same factor (the offered
+    # rates are unchanged)
+    fracs = (0.5, 0.8, 0.95, 0.5)
+    need = sum(int(f * sat["ops_per_s"] / mean_k * args.serve_seconds) for f in fracs)
+    shrink = min(1.0, (len(reqs) - at) / max(need, 1))
+    if shrink < 1.0:
+        log(f"request pool: phases shortened to {shrink * args.serve_seconds:.1f} s each")
+    for i, frac in enumerate(fracs[:3]):
         rate = frac * sat["ops_per_s"] / mean_k
-        cnt = int(rate * args.serve_seconds)
+        cnt = int(rate * args.serve_seconds * shrink)
         r = serve_phase(P, ctx, take(cnt), rate, 10 + i)
         r.update(load=frac, offered_req_s=rate, offered_ops_s=rate * mean_k, coalescing=True)
         phases.append(r)
@@ -442,7 +450,7 @@ def serve_main(args):
             f"{r['ops_per_s']:.0f} ops/s, {r['mean_requests_per_step']:.2f} req/step")
     # the same offered load without coalescing: one request per step (a queue alone)
     rate = 0.5 * sat["ops_per_s"] / mean_k
-    cnt = int(rate * args.serve_seconds)
+    cnt = int(rate * args.serve_seconds * shrink)
     q = serve_phase(P, ctx, take(cnt), rate, 20, max_step_requests=1)
     q.update(load=0.5, offered_req_s=rate, offered_ops_s=rate * mean_k, coalescing=False)
     phases.append(q)
