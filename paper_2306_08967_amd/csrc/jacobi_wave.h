@@ -233,6 +233,12 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, JNs *ns, double2 *bc,
   const double g2 = gt * gt, ab = al * be;
   const bool doit = live && g2 > tol2 * ab;
   big |= (live && g2 >= conv2 * ab) ? 1 : 0;
+  rot += doit ? 1 : 0;
+  // a step in which no pair rotates would only add zeros (t = 0): skip its
+  // rotation parameters and shears; finite results are unchanged bit for bit
+  const bool none = __builtin_amdgcn_ballot_w64(doit) == 0;  // uniform over the wave
+  skip += none ? 1 : 0;
+  if (none) return;
   // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 g),
   // as sign(be - al) 2g / (|be - al| + sqrt((be - al)^2 + 4 g^2))
   const double dd = be - al, gg = doit ? 2.0 * gt : 0.0;
@@ -258,12 +264,6 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, JNs *ns, double2 *bc,
     ns[ib].d = cs * dj;
     ns[ib].rd = rdj * ic;
   }
-  rot += doit ? 1 : 0;
-  // a step in which no pair rotates would only add zeros (t = 0): skip its
-  // shears; finite results are unchanged bit for bit
-  const bool none = __builtin_amdgcn_ballot_w64(doit) == 0;  // uniform over the wave
-  skip += none ? 1 : 0;
-  if (none) return;
   if (plane) bc[pair] = make_double2(t1, t2);
   __builtin_amdgcn_wave_barrier();
   // the factor pairs are requested in two halves, each in one LDS round trip
