@@ -398,35 +398,22 @@ __device__ __forceinline__ void jw_exchange(JWRegs<S> &J, double *xb, int w, int
 // slot, finishes its round first and idles at the exchange while the other
 // runs alone.  Priority falls with the step (3 for the first quarter of a
 // round's cross steps, down to 0 for the last), so the wave that is behind
-// wins instead; the older wave (the first half of the waves, which share
-// their SIMDs with the second half) lowers it kPrioLead steps early, since it
-// still wins ties.  Per C2 chunk: steps 513 / 805 us on the older / younger
-// waves with no priorities, 670 / 750 with the falling priority, 690 / 735
-// with the lead of 2 steps (the Jacobi 5.6% faster).
-constexpr int kPrioLead = 2;
+// wins instead.  Per C2 chunk: steps 513 / 805 us on the older / younger
+// waves with no priorities, 670 / 750 with the falling priority.
 template <int SH, int B>
-__device__ __forceinline__ void jw_prio(bool older) {
+__device__ __forceinline__ void jw_prio() {
   constexpr int Q = (B >= 4) ? B / 4 : 1;
-  constexpr int qa = SH / Q < 3 ? SH / Q : 3;
-  constexpr int qb = (SH + kPrioLead) / Q < 3 ? (SH + kPrioLead) / Q : 3;
-  if constexpr (qa == qb) {
-    if constexpr (SH % Q == 0) __builtin_amdgcn_s_setprio(3 - qa);
-  } else {
-    if (older)
-      __builtin_amdgcn_s_setprio(3 - qb);
-    else
-      __builtin_amdgcn_s_setprio(3 - qa);
-  }
+  if constexpr (SH % Q == 0) __builtin_amdgcn_s_setprio(3 - (SH / Q < 3 ? SH / Q : 3));
 }
 
 // Steps sh .. sh + U - 1 of a cross round, the bottom offset by 0 .. U - 1 slots.
 template <class S, int U, int... SH>
 __device__ __forceinline__ void jw_cross_steps(JWRegs<S> &J, JNs *ns, double2 *bc, double floor2,
                                                double tol2, double conv2, int ht, int hb, int sh,
-                                               int &rot, int &big, int &skip, bool older,
+                                               int &rot, int &big, int &skip,
                                                std::integer_sequence<int, SH...>) {
   constexpr int B = S::B;
-  ((jw_prio<SH, B>(older),
+  ((jw_prio<SH, B>(),
     jw_step<S, JWCross<S, SH>>(J, ns, bc, floor2, tol2, conv2,
                                [&](int p, int &it, int &ib) {
                                  int q = p + sh + SH;
@@ -487,7 +474,7 @@ __device__ __forceinline__ int jw_sweeps(JWRegs<S> &J, double *lds, int *lds_fla
       // with the bottom offset by u slots), then the bottom turned by XU
       for (int sh = 0; sh < B; sh += XU) {
         jw_cross_steps<S, XU>(J, ns, bc, floor2, tol2, conv2, ht, hb, sh, rot, big, skip,
-                              w < S::NW / 2, std::make_integer_sequence<int, XU>{});
+                              std::make_integer_sequence<int, XU>{});
         jw_cross_move<S, XU>(J);
       }
       jw_exchange<S>(J, xb, w, lane);
