@@ -232,23 +232,26 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, JNs *ns, double2 *bc,
   const bool live = plane && al > floor2 && be > floor2;
   const double g2 = gt * gt, ab = al * be;
   const bool doit = live && g2 > tol2 * ab;
-  big |= (live && g2 >= conv2 * ab) ? 1 : 0;
   rot += doit ? 1 : 0;
   // a step in which no pair rotates would only add zeros (t = 0): skip its
   // rotation parameters and shears; finite results are unchanged bit for bit
   const bool none = __builtin_amdgcn_ballot_w64(doit) == 0;  // uniform over the wave
   skip += none ? 1 : 0;
   if (none) return;
+  // a pair above sqrt(tol) is above tol too (tol < 1), so only steps that
+  // rotate can set big
+  big |= (live && g2 >= conv2 * ab) ? 1 : 0;
   // t = sign(zeta) / (|zeta| + sqrt(1 + zeta^2)), zeta = (be - al) / (2 g),
-  // as sign(be - al) 2g / (|be - al| + sqrt((be - al)^2 + 4 g^2))
-  const double dd = be - al, gg = doit ? 2.0 * gt : 0.0;
+  // as sign(be - al) 2g / (|be - al| + sqrt((be - al)^2 + 4 g^2)); a pair
+  // that does not rotate gets t = 0 (its den may be 0)
+  const double dd = be - al, gg = 2.0 * gt;
   // t itself needs no more than about 1e-14 (any angle near the optimal one
   // shrinks the pair's inner product quadratically, and the rotation stays
   // orthogonal because c is formed from this t to full precision): one Newton
   // step on each hardware estimate
   const double q2 = fma(dd, dd, gg * gg);
   const double den = fabs(dd) + q2 * rsqrt_nr1(q2);
-  const double t = doit ? (dd >= 0.0 ? gg : -gg) * rcp_nr1(den) : 0.0;
+  const double t = doit ? gg * __builtin_copysign(rcp_nr1(den), dd) : 0.0;
   const double q1 = fma(t, t, 1.0);
   const double cs = rsqrt_nr(q1);
   // two in-place shears: x_j += t (d_i / d_j) x_i, then x_i -= c^2 t (d_j / d_i) x_j
