@@ -246,14 +246,16 @@ __device__ __forceinline__ void jw_step(JWRegs<S> &J, JNs *ns, double2 *bc,
   // that does not rotate gets t = 0 (its den may be 0)
   const double dd = be - al, gg = 2.0 * gt;
   // t itself needs no more than about 1e-14 (any angle near the optimal one
-  // shrinks the pair's inner product quadratically, and the rotation stays
-  // orthogonal because c is formed from this t to full precision): one Newton
-  // step on each hardware estimate
+  // shrinks the pair's inner product quadratically); c = (1 + t^2)^-1/2 is
+  // formed from this t with one Newton step as well, which keeps each
+  // rotation orthogonal to about 1e-14 (the columns' exact norms are taken
+  // again after every sweep; a second step changed none of the C2 accuracy
+  // figures)
   const double q2 = fma(dd, dd, gg * gg);
   const double den = fabs(dd) + q2 * rsqrt_nr1(q2);
   const double t = doit ? gg * __builtin_copysign(rcp_nr1(den), dd) : 0.0;
   const double q1 = fma(t, t, 1.0);
-  const double cs = rsqrt_nr(q1);
+  const double cs = rsqrt_nr1(q1);
   // two in-place shears: x_j += t (d_i / d_j) x_i, then x_i -= c^2 t (d_j / d_i) x_j
   // (the new x_j), with d_j <- c d_j and d_i <- d_i / c (1 / c = (1 + t^2) c);
   // the scales' reciprocals are carried along, so no division is needed
