@@ -22,6 +22,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cfloat>
+#include <utility>
 
 #include "common.h"
 #include "damf_internal.h"
@@ -704,53 +705,66 @@ __device__ __noinline__ void complete_basis(int d, int NB, int NC, double *scr, 
 
 // ---------------------------------------------------------------- Step 3
 
-// Y = T E_bot (k x d): solve L1^T X = E_bot (rho x d) and scatter rows by perm.
-// side 0 uses E (rows d.. of EG), side 1 uses H (rows d.. of HG).  Back
-// substitution by four adjacent lanes per column (d <= 128 columns, 512
-// threads): lane q sums the terms j = i + 1 + q, i + 5 + q, ... into two
-// accumulators, a quad reduction (DPP) gives every lane the total, and lane 0
-// of the quad writes X[i][c] (LDS operations of one wave complete in order, so
-// the quad reads it back in the next row).  The diagonal's reciprocals are
-// formed once.
+template <int I>
+__device__ __forceinline__ void solve_Y_step(double (&x)[KMAX / 4], int q, int rho, const double *L, int k,
+                                             const double *rinv) {
+  if (I >= rho) return;  // uniform
+  constexpr int r = I & 3, mi = I >> 2;
+  // row I is final: scale it in its owner lane, then hand it to the quad
+  const bool own = q == r;
+  x[mi] = own ? x[mi] * rinv[I] : x[mi];
+  const double xi = dpp_d<r | (r << 2) | (r << 4) | (r << 6)>(x[mi]);  // quad_perm [r,r,r,r]
+  const double keep = x[mi];
+  // rows j < I of the quad's column: x_j -= L[I][j] x_I (L[I][j] = 0 for
+  // j > I, so those rows are unchanged; the owner's row I is put back)
+#pragma unroll
+  for (int m = 0; m < KMAX / 4; ++m) {
+    if (4 * m <= I) x[m] = fma(-L[I * k + 4 * m + q], xi, x[m]);
+  }
+  x[mi] = own ? keep : x[mi];
+}
+
+template <int... I>
+__device__ __forceinline__ void solve_Y_steps(double (&x)[KMAX / 4], int q, int rho, const double *L, int k,
+                                              const double *rinv, std::integer_sequence<int, I...>) {
+  (solve_Y_step<KMAX - 1 - I>(x, q, rho, L, k, rinv), ...);
+}
+
+// Y = T E_bot (k x d): solve L1^T X = E_bot (rho x d) by back substitution
+// with the pivoted Cholesky factor (k x k, lower triangular in pivot order)
+// and scatter the rows by perm; side 0 uses E (rows d.. of EG), side 1 H
+// (rows d.. of HG).  Four lanes per column hold its rows j = 4 m + q
+// in registers; after row I is final (the right-looking form) its owner lane
+// hands it to the quad by DPP and every lane subtracts L[I][j] x_I from its
+// rows, so the only LDS traffic is the factor's rows (broadcast reads that
+// do not depend on the solve) and a step's latency is a DPP move and an FMA.
 __device__ __forceinline__ void solve_Y(int side, int d, int k, int rho, const int *perm, const double *Lg,
                         double *scr, double *lds) {
-  static_assert(NT == 4 * DMAX, "four lanes per column");
+  static_assert(NT == 4 * DMAX && KMAX == 64, "four lanes per column, 16 rows each");
   double *Y = scr + (side ? OFF_YC : OFF_YB);
   const double *EG = scr + OFF_EG, *HG = scr + OFF_HG;
-  double *L = lds;                               // k x k
-  double *X = lds + KMAX * KMAX;                 // rho x d
-  double *rinv = lds + KMAX * KMAX + KMAX * DMAX;  // rho
+  double *L = lds;                    // k x k
+  double *rinv = lds + KMAX * KMAX;   // rho
   for (int e = tid(); e < k * k; e += NT) L[e] = Lg[e];
-  for (int e = tid(); e < rho * d; e += NT) {
-    int i = e / d, c = e - i * d;
-    X[e] = side ? HG[(d + i) * DMAX + c] : EG[c * NPMAX + d + i];
-  }
   for (int i = tid(); i < rho; i += NT) rinv[i] = 1.0 / Lg[i * k + i];
-  __syncthreads();
   const int c = tid() >> 2, q = tid() & 3;
   const bool col = c < d;
-  for (int i = rho - 1; i >= 0; --i) {
-    double v0 = 0.0, v1 = 0.0;
-    if (col) {
-      int j = i + 1 + q;
-      for (; j + 4 < rho; j += 8) {
-        v0 = fma(L[j * k + i], X[j * d + c], v0);
-        v1 = fma(L[(j + 4) * k + i], X[(j + 4) * d + c], v1);
-      }
-      if (j < rho) v0 = fma(L[j * k + i], X[j * d + c], v0);
-    }
-    double v = v0 + v1;
-    v += dpp_d<0xB1>(v);  // quad_perm [1,0,3,2]
-    v += dpp_d<0x4E>(v);  // quad_perm [2,3,0,1]
-    if (col && q == 0) X[i * d + c] = (X[i * d + c] - v) * rinv[i];
-    __builtin_amdgcn_wave_barrier();
+  double x[KMAX / 4];
+#pragma unroll
+  for (int m = 0; m < KMAX / 4; ++m) {
+    const int i = 4 * m + q;
+    x[m] = (col && i < rho) ? (side ? HG[(d + i) * DMAX + c] : EG[c * NPMAX + d + i]) : 0.0;
   }
   __syncthreads();
-  // rows of Y: the solved X rows at their pivots' positions, zeros for the
+  solve_Y_steps(x, q, rho, L, k, rinv, std::make_integer_sequence<int, KMAX>{});
+  // rows of Y: the solved rows at their pivots' positions, zeros for the
   // dropped directions (perm is a permutation of 0 .. k - 1)
-  for (int e = tid(); e < k * d; e += NT) {
-    int i = e / d, c2 = e - i * d;
-    Y[perm[i] * d + c2] = (i < rho) ? X[e] : 0.0;
+  if (col) {
+#pragma unroll
+    for (int m = 0; m < KMAX / 4; ++m) {
+      const int i = 4 * m + q;
+      if (i < k) Y[perm[i] * d + c] = (i < rho) ? x[m] : 0.0;
+    }
   }
   __syncthreads();
 }
